@@ -1,0 +1,61 @@
+"""Choice of scheme and scaling power (oracle, test infrastructure).
+
+Tables 1 and 2 give, for each scheme k in {3, 4, 6, 7} products, the largest
+norms theta^c and theta^s for which the cosine and sine truncation errors stay
+below the unit roundoff, and Section 4 combines the schemes with scaling by
+2^-s and s double-angle steps (2 products each, Section 1).
+
+Readings taken (the paper only shows the resulting staircase in its Figure 1):
+
+* Both outputs share one scaling, so a scheme is usable for theta <= the
+  smaller of its two bounds.
+* (level, s) minimises the total number of products Pi_level + 2 s, where s
+  is the smallest integer >= 0 with theta 2^-s <= theta_level; ties go to the
+  smaller s. s is found by exact halving, never through a floating log2.
+* The 7-product sine bound in double precision is 1.8548 (re-derived from the
+  printed coefficients) instead of the printed 1.97.
+
+Pins (tests/test_oracle_plan.py): a brute-force enumeration over all
+(level, s) candidates written independently, and the table constants against
+the theta re-derivation of ``theta``.
+"""
+from __future__ import annotations
+
+import math
+
+__all__ = ["THETA", "PRODUCTS", "plan", "scaling_for"]
+
+PRODUCTS = {3: 3, 4: 4, 6: 6, 7: 7}
+
+# min(theta^c, theta^s) per scheme; Table 1 (u = 2^-53) and Table 2 (u = 2^-24).
+THETA = {
+    "double": {3: 6.5633e-3, 4: 8.0438e-2, 6: 9.8108e-1, 7: 1.8548},
+    "single": {3: 1.8709e-1, 4: 7.492e-1, 6: 2.9935, 7: 4.3819},
+}
+
+
+def scaling_for(theta: float, limit: float) -> int:
+    """Smallest s >= 0 with theta * 2^-s <= limit (exact halving)."""
+    s = 0
+    t = float(theta)
+    while t > limit:
+        t *= 0.5
+        s += 1
+    return s
+
+
+def plan(theta: float, accuracy: str = "double"):
+    """Return (level, s, products) for a matrix of 1-norm ``theta``.
+
+    Raises ValueError for a non-finite or negative norm.
+    """
+    if not math.isfinite(theta) or theta < 0:
+        raise ValueError("norm must be finite and >= 0")
+    best = None
+    for level in (3, 4, 6, 7):
+        s = scaling_for(theta, THETA[accuracy][level])
+        cand = (PRODUCTS[level] + 2 * s, s, level)
+        if best is None or cand[:2] < best[:2]:
+            best = cand
+    cost, s, level = best
+    return level, s, cost

@@ -1,0 +1,56 @@
+"""Pins for oracle/paper_algorithm.py: the paper's method (plan + scheme + double
+angle) against the independent reference oracle, mpmath, and closed forms."""
+import mpmath
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import paper_algorithm as PA
+from oracle import plan as P
+from oracle import reference as R
+from tests.conftest import rel_fro
+
+
+@pytest.mark.parametrize("family", ["gaussian", "symmetric", "laplacian1d"])
+@pytest.mark.parametrize("e", [-7, -4, -1, 0, 1, 2, 4, 7, 10])
+def test_against_reference(family, e):
+    A = W.family(family, 64, 2.0 ** e, key=(21, e + 10))
+    C, S, plan = PA.sincosm(A, return_plan=True)
+    Cr, Sr = R.sincosm(A)
+    assert plan == P.plan(np.linalg.norm(A, 1))
+    assert rel_fro(C, Cr) <= 1e-12
+    assert rel_fro(S, Sr) <= 1e-12
+
+
+@pytest.mark.parametrize("level_norm", [(3, 5e-3), (4, 6e-2), (6, 0.9), (7, 1.8)])
+def test_each_level_mpmath(level_norm):
+    level, t = level_norm
+    A = W.gaussian(6, t, key=(22, level))
+    C, S, plan = PA.sincosm(A, return_plan=True)
+    assert plan[0] == level and plan[1] == 0
+    with mpmath.workdps(40):
+        M = mpmath.matrix(A.tolist())
+        Cm = np.array(mpmath.cosm(M).tolist(), dtype=float)
+        Sm = np.array(mpmath.sinm(M).tolist(), dtype=float)
+    assert rel_fro(C, Cm) <= 4e-16 * 6
+    assert rel_fro(S, Sm) <= 4e-16 * 6
+
+
+@pytest.mark.parametrize("acc", ["double", "single"])
+def test_single_table_accuracy(acc):
+    """With the single table, the float64 evaluation still reaches about 2^-24."""
+    A = W.gaussian(32, 64.0, key=(23,))
+    C, S = PA.sincosm(A, accuracy=acc)
+    Cl, Sl = R.sincosm_ld(A)
+    tol = 1e-12 if acc == "double" else 5e-6
+    assert rel_fro(C, Cl.astype(float)) <= tol
+    assert rel_fro(S, Sl.astype(float)) <= tol
+
+
+def test_float32_single_accuracy():
+    A64 = W.gaussian(48, 16.0, key=(24,))
+    A32 = A64.astype(np.float32)
+    C, S = PA.sincosm(A32.astype(np.float32), accuracy="single", dtype=np.float32)
+    Cr, Sr = R.sincosm(A32.astype(np.float64))
+    assert rel_fro(C, Cr) <= 5e-5
+    assert rel_fro(S, Sr) <= 5e-5

@@ -1,0 +1,181 @@
+/*
+ * sincosm.h - C ABI of the MI355X (gfx950) library for the simultaneous
+ * matrix cosine and sine of a real dense matrix.
+ *
+ * Method: Seydaoglu, Bader, Blanes, Casas, "Computing the matrix sine and
+ * cosine simultaneously with a reduced number of products" (arXiv
+ * 2010.00465). For a real n x n matrix A the library returns C = cos(A) and
+ * S = sin(A) (Section 2.1, definitions of T^c_{2m} and T^s_{2m+1}) by
+ *   1. theta = ||A||_1 (maximum absolute column sum), in float64 on device;
+ *   2. choosing a scheme with 3, 4, 6 or 7 products and a scaling power s
+ *      from the bounds of Tables 1 (double) / 2 (single): the plan minimises
+ *      the product count Pi + 2 s, with s the smallest integer >= 0 such that
+ *      theta 2^-s does not exceed the scheme's bound, ties to the smaller s;
+ *   3. evaluating the factorized Taylor scheme of Section 2.1 on X = 2^-s A;
+ *   4. s double-angle steps cos 2X = I - 2 sin^2 X, sin 2X = 2 sin X cos X
+ *      (Section 1), two products each.
+ *
+ * Conventions for every call below:
+ *  - Matrices are row-major with a leading dimension (elements between the
+ *    starts of consecutive rows) >= n. The 1-norm is the maximum absolute
+ *    COLUMN sum of the logical matrix.
+ *  - Pointers named A, C, S, Gc, Gs, gA, ws and *_dev are DEVICE pointers on
+ *    the current HIP device; pointers named *_host are host pointers.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the default
+ *    stream. Work is enqueued on it. sincosm_eval and sincosm_backward read
+ *    the 24-byte plan back to the host (one stream synchronisation) before
+ *    they enqueue the products, so they return after the plan is known.
+ *  - The caller owns every buffer. The library allocates no device memory:
+ *    each call takes a workspace whose size the matching *_workspace_size
+ *    query returns. Results are deterministic (bitwise) for identical inputs,
+ *    settings and device.
+ *  - Errors in arguments are returned synchronously and leave outputs
+ *    untouched. n = 0 is a no-op returning SINCOSM_OK.
+ */
+#ifndef SINCOSM_H
+#define SINCOSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SINCOSM_OK = 0,
+  SINCOSM_E_ARG = -1,         /* bad size, leading dimension, null or aliased pointer, bad enum */
+  SINCOSM_E_UNSUPPORTED = -2, /* combination not provided (see each call) */
+  SINCOSM_E_WORKSPACE = -3,   /* workspace missing or smaller than the query's size */
+  SINCOSM_E_NONFINITE = -4,   /* A holds Inf/NaN (or its 1-norm overflows): outputs set to NaN */
+  SINCOSM_E_HIP = -5          /* a HIP runtime call failed */
+} sincosm_status;
+
+/* Storage type of A, C, S and of the gradients. */
+typedef enum { SINCOSM_F64 = 0, SINCOSM_F32 = 1 } sincosm_dtype;
+
+/* Accuracy target of the plan: Table 1 bounds (u = 2^-53) or Table 2 (u = 2^-24). */
+typedef enum { SINCOSM_ACC_DOUBLE = 0, SINCOSM_ACC_SINGLE = 1 } sincosm_accuracy;
+
+/* Arithmetic of the polynomial-phase products (the scheme of step 3):
+ *  NATIVE - the storage type (float64 MFMA for F64, float32 MFMA for F32);
+ *  F32    - float32 MFMA products and float32 intermediates;
+ *  BF16X3 - each float32 operand split as hi + lo (hi = bf16(x), lo = bf16(x - hi)),
+ *           products hi*hi + hi*lo + lo*hi on bf16 MFMA with float32 accumulation.
+ * The 1-norm, the plan and the double-angle steps always run in the storage
+ * type (float64 for F64). */
+typedef enum { SINCOSM_PROD_NATIVE = 0, SINCOSM_PROD_F32 = 1, SINCOSM_PROD_BF16X3 = 2 } sincosm_prod;
+
+/* The plan chosen for one matrix. level in {3,4,6,7} (= products of the
+ * scheme), s = number of double-angle steps, products = level + 2 s, status =
+ * SINCOSM_OK or SINCOSM_E_NONFINITE, norm1 = ||A||_1 as computed on device. */
+typedef struct {
+  int32_t level;
+  int32_t s;
+  int32_t products;
+  int32_t status;
+  double norm1;
+} sincosm_plan;
+
+/* Plan for a given 1-norm, computed on the host with the same rule and
+ * constants as the device (Tables 1-2; the 7-product sine bound in double is
+ * 1.8548, re-derived from the printed coefficients). Pure function.
+ * Returns SINCOSM_E_ARG for a bad `acc` or a null `out`; a NaN/Inf/negative
+ * norm gives status SINCOSM_E_NONFINITE in *out and return SINCOSM_OK. */
+sincosm_status sincosm_plan_host(double norm1, int acc, sincosm_plan* out);
+
+/* Human-readable text for a status code (static storage). */
+const char* sincosm_strerror(int status);
+
+/* The plan sincosm_eval would use for A (1-norm and rule on the device),
+ * read back to *plan_host. ws: sincosm_plan_workspace_size(n) bytes, 256-byte
+ * aligned. Returns SINCOSM_OK also for non-finite input (status in the plan). */
+size_t sincosm_plan_workspace_size(int64_t n);
+sincosm_status sincosm_plan_device(int64_t n, int dtype, const void* A, int64_t lda, int acc,
+                                   void* ws, size_t ws_bytes, sincosm_plan* plan_host, void* stream);
+
+/* Bytes of workspace sincosm_eval needs for this n and settings (0 for n <= 0). */
+size_t sincosm_workspace_size(int64_t n, int dtype, int acc, int prod);
+
+/* cos(A) and sin(A) of one n x n matrix (Sections 1 and 2.1, Tables 1-2).
+ *  A (lda), C (ldc), S (lds): device matrices of type `dtype`; A is read only;
+ *  C and S must not overlap each other or A.
+ *  ws / ws_bytes: device workspace of at least sincosm_workspace_size(...) bytes,
+ *  256-byte aligned.
+ *  plan_host: optional host pointer receiving the plan used.
+ *  Supported: dtype F64 with prod NATIVE, F32 or BF16X3; dtype F32 with prod
+ *  NATIVE (= F32) or BF16X3. acc may be DOUBLE or SINGLE in every case.
+ *  Returns SINCOSM_E_NONFINITE (after filling C and S with NaN) when A holds
+ *  Inf or NaN. */
+sincosm_status sincosm_eval(int64_t n, int dtype, const void* A, int64_t lda,
+                            void* C, int64_t ldc, void* S, int64_t lds,
+                            int acc, int prod, void* ws, size_t ws_bytes,
+                            sincosm_plan* plan_host, void* stream);
+
+/* Bytes of workspace sincosm_eval_batched needs for `batch` matrices whose
+ * orders are n_host[0..batch-1] (host array). */
+size_t sincosm_batched_workspace_size(int64_t batch, const int32_t* n_host, int dtype,
+                                      int acc, int prod);
+
+/* cos and sin of `batch` independent matrices of uneven orders in one call.
+ *  n_host / offset_host: host arrays of the orders (1 <= n <= 256) and the
+ *  element offsets of each matrix inside A, C and S (row-major, leading
+ *  dimension n, the same offsets for A, C and S).
+ *  A, C, S: device base pointers of type dtype (F64 or F32; prod NATIVE only).
+ *  plans_dev: optional device array of `batch` sincosm_plan, one per matrix.
+ *  Each matrix gets its own plan (as sincosm_eval would choose). The call
+ *  enqueues a fixed sequence of launches whose shape depends only on the
+ *  orders, so it can be captured in a HIP graph and replayed with new values
+ *  in A. A matrix with Inf/NaN gets NaN outputs and status SINCOSM_E_NONFINITE
+ *  in its plan; the call itself still returns SINCOSM_OK. */
+sincosm_status sincosm_eval_batched(int64_t batch, int dtype, const int32_t* n_host,
+                                    const int64_t* offset_host, const void* A, void* C, void* S,
+                                    int acc, int prod, void* ws, size_t ws_bytes,
+                                    sincosm_plan* plans_dev, void* stream);
+
+/* Bytes of workspace sincosm_backward needs for order n and `s` double-angle
+ * steps (s from the forward call's plan; the backward rejects a larger s). */
+size_t sincosm_backward_workspace_size(int64_t n, int dtype, int acc, int32_t s);
+
+/* Gradient of L(A) = <Gc, cos A> + <Gs, sin A> (Frobenius inner products)
+ * with respect to A, for the function the forward computes (same plan):
+ *  gA = adjoint of the map A -> (C, S) applied to (Gc, Gs).
+ *  Gc (ldgc), Gs (ldgs): device matrices; either may be NULL (= zero).
+ *  gA (ldga): device output, must not overlap the inputs.
+ *  dtype F64 only (prod NATIVE). The reverse pass runs through the s
+ *  double-angle steps (their inputs recomputed and kept in the workspace)
+ *  and through the scheme's products, two products per forward product.
+ *  Returns SINCOSM_E_NONFINITE (gA filled with NaN) for Inf/NaN input. */
+sincosm_status sincosm_backward(int64_t n, int dtype, const void* A, int64_t lda,
+                                const void* Gc, int64_t ldgc, const void* Gs, int64_t ldgs,
+                                void* gA, int64_t ldga, int acc, void* ws, size_t ws_bytes,
+                                sincosm_plan* plan_host, void* stream);
+
+/* Building block exposed for tests and measurement: Z = X Y for n x n
+ * matrices with the same kernels and padding sincosm_eval uses
+ * (dtype F64 / F32, prod as in sincosm_eval). ws: sincosm_matmul_workspace_size bytes. */
+size_t sincosm_matmul_workspace_size(int64_t n, int dtype, int prod);
+sincosm_status sincosm_matmul(int64_t n, int dtype, const void* X, int64_t ldx,
+                              const void* Y, int64_t ldy, void* Z, int64_t ldz, int prod,
+                              void* ws, size_t ws_bytes, void* stream);
+
+/* Instrumentation: when enabled, every product launch of the library is
+ * bracketed by two HIP events on its stream, tagged by class:
+ *   SINCOSM_TIMING_SCHEME   - a product of the scheme (one problem per launch),
+ *   SINCOSM_TIMING_SQUARING - a double-angle step (one launch, 2 products),
+ *   SINCOSM_TIMING_BACKWARD - a product of the reverse pass,
+ *   SINCOSM_TIMING_BATCHED  - a launch of the batched path.
+ * sincosm_timing_enable(1) starts recording (discarding earlier records),
+ * (0) stops. sincosm_timing_read waits for the recorded events of one class
+ * and returns their summed duration in ms and their number. Host-side state,
+ * thread-safe, intended for measurement runs. */
+enum { SINCOSM_TIMING_SCHEME = 0, SINCOSM_TIMING_SQUARING = 1, SINCOSM_TIMING_BACKWARD = 2,
+       SINCOSM_TIMING_BATCHED = 3 };
+sincosm_status sincosm_timing_enable(int on);
+sincosm_status sincosm_timing_read(int kind, double* total_ms, int64_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SINCOSM_H */

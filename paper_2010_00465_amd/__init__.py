@@ -1,0 +1,198 @@
+"""Simultaneous matrix cosine and sine on MI355X (gfx950).
+
+Python face of libsincosm.so. The functions named after the C ABI
+(``sincosm_eval``, ``sincosm_eval_batched``, ``sincosm_backward``,
+``sincosm_matmul``, ``plan_host``) only marshal torch tensors into pointers,
+sizes and the current HIP stream. ``sincosm`` adds output/workspace
+allocation through torch and an autograd.Function whose backward calls
+``sincosm_backward``.
+
+Method: Seydaoglu, Bader, Blanes, Casas, arXiv 2010.00465 (scaling by 2^-s,
+the factorized Taylor schemes of Section 2.1 with 3/4/6/7 products chosen
+from the bounds of Tables 1-2, and s double-angle steps of Section 1).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import ACC, PROD, Plan, SincosmError, check, lib
+
+__all__ = ["sincosm", "sincosm_eval", "sincosm_eval_batched", "sincosm_backward", "sincosm_matmul",
+           "plan_host", "plan_device", "workspace_size", "Plan", "SincosmError", "sincosm_batched"]
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return _lib.F64
+    if t.dtype == torch.float32:
+        return _lib.F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _stream(t: torch.Tensor) -> int:
+    return torch.cuda.current_stream(t.device).cuda_stream
+
+
+def _ld(t: torch.Tensor) -> int:
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("expected a 2-D row-major tensor (unit column stride)")
+    return t.stride(0)
+
+
+def _require_cuda(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise ValueError("tensors must live on the GPU")
+
+
+def plan_host(norm1: float, accuracy: str = "double") -> Plan:
+    """The library's plan for a given 1-norm (host computation, same rule as the device)."""
+    p = Plan()
+    check(lib.sincosm_plan_host(float(norm1), ACC[accuracy], ctypes.byref(p)), "sincosm_plan_host")
+    return p
+
+
+def plan_device(A: torch.Tensor, accuracy: str = "double") -> Plan:
+    """The plan sincosm_eval would choose for A (1-norm and rule on the device)."""
+    _require_cuda(A)
+    n = A.shape[0]
+    ws = _workspace(lib.sincosm_plan_workspace_size(n), A.device)
+    p = Plan()
+    check(lib.sincosm_plan_device(n, _dtype_code(A), A.data_ptr(), _ld(A), ACC[accuracy], ws.data_ptr(),
+                                  ws.numel(), ctypes.byref(p), _stream(A)), "sincosm_plan_device")
+    return p
+
+
+def workspace_size(n: int, dtype=torch.float64, accuracy="double", products="native") -> int:
+    code = _lib.F64 if dtype == torch.float64 else _lib.F32
+    return int(lib.sincosm_workspace_size(int(n), code, ACC[accuracy], PROD[products]))
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    # torch allocations are 512-byte aligned, as the library requires (256)
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def sincosm_eval(A: torch.Tensor, C: torch.Tensor, S: torch.Tensor, accuracy: str = "double",
+                 products: str = "native", ws: torch.Tensor | None = None, raise_nonfinite=True) -> Plan:
+    """C-ABI sincosm_eval on torch tensors (writes C and S in place). Returns the plan."""
+    _require_cuda(A, C, S)
+    n = A.shape[0]
+    dt = _dtype_code(A)
+    if ws is None:
+        ws = _workspace(workspace_size(n, A.dtype, accuracy, products), A.device)
+    plan = Plan()
+    st = lib.sincosm_eval(n, dt, A.data_ptr(), _ld(A), C.data_ptr(), _ld(C), S.data_ptr(), _ld(S),
+                          ACC[accuracy], PROD[products], ws.data_ptr(), ws.numel(), ctypes.byref(plan),
+                          _stream(A))
+    if st == _lib.E_NONFINITE and not raise_nonfinite:
+        return plan
+    check(st, "sincosm_eval")
+    return plan
+
+
+def sincosm_matmul(X: torch.Tensor, Y: torch.Tensor, Z: torch.Tensor, products: str = "native",
+                   ws: torch.Tensor | None = None) -> None:
+    """C-ABI sincosm_matmul: Z = X Y with the library's product kernels."""
+    _require_cuda(X, Y, Z)
+    n = X.shape[0]
+    dt = _dtype_code(X)
+    if ws is None:
+        ws = _workspace(lib.sincosm_matmul_workspace_size(n, dt, PROD[products]), X.device)
+    check(lib.sincosm_matmul(n, dt, X.data_ptr(), _ld(X), Y.data_ptr(), _ld(Y), Z.data_ptr(), _ld(Z),
+                             PROD[products], ws.data_ptr(), ws.numel(), _stream(X)), "sincosm_matmul")
+
+
+def sincosm_backward(A: torch.Tensor, Gc: torch.Tensor | None, Gs: torch.Tensor | None, gA: torch.Tensor,
+                     accuracy: str = "double", s: int | None = None, ws: torch.Tensor | None = None) -> Plan:
+    """C-ABI sincosm_backward: gA = d/dA (<Gc, cos A> + <Gs, sin A>)."""
+    _require_cuda(A, Gc, Gs, gA)
+    n = A.shape[0]
+    dt = _dtype_code(A)
+    if s is None:
+        s = plan_device(A, accuracy).s
+    if ws is None:
+        ws = _workspace(lib.sincosm_backward_workspace_size(n, dt, ACC[accuracy], int(s)), A.device)
+    plan = Plan()
+    gc_ptr, gc_ld = (Gc.data_ptr(), _ld(Gc)) if Gc is not None else (None, n)
+    gs_ptr, gs_ld = (Gs.data_ptr(), _ld(Gs)) if Gs is not None else (None, n)
+    check(lib.sincosm_backward(n, dt, A.data_ptr(), _ld(A), gc_ptr, gc_ld, gs_ptr, gs_ld, gA.data_ptr(),
+                               _ld(gA), ACC[accuracy], ws.data_ptr(), ws.numel(), ctypes.byref(plan),
+                               _stream(A)), "sincosm_backward")
+    return plan
+
+
+def sincosm_eval_batched(ns, offsets, A: torch.Tensor, C: torch.Tensor, S: torch.Tensor,
+                         accuracy: str = "double", products: str = "native", ws: torch.Tensor | None = None,
+                         plans: torch.Tensor | None = None) -> None:
+    """C-ABI sincosm_eval_batched on a packed batch (ns, offsets: host int sequences)."""
+    _require_cuda(A, C, S)
+    dt = _dtype_code(A)
+    batch = len(ns)
+    n_arr = (ctypes.c_int32 * batch)(*[int(v) for v in ns])
+    o_arr = (ctypes.c_int64 * batch)(*[int(v) for v in offsets])
+    if ws is None:
+        ws = _workspace(lib.sincosm_batched_workspace_size(batch, n_arr, dt, ACC[accuracy], PROD[products]),
+                        A.device)
+    plans_ptr = plans.data_ptr() if plans is not None else None
+    check(lib.sincosm_eval_batched(batch, dt, n_arr, o_arr, A.data_ptr(), C.data_ptr(), S.data_ptr(),
+                                   ACC[accuracy], PROD[products], ws.data_ptr(), ws.numel(), plans_ptr,
+                                   _stream(A)), "sincosm_eval_batched")
+
+
+class _SinCosM(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, A, accuracy, products):
+        C = torch.empty_like(A)
+        S = torch.empty_like(A)
+        plan = sincosm_eval(A, C, S, accuracy, products)
+        ctx.save_for_backward(A)
+        ctx.accuracy = accuracy
+        ctx.s = plan.s
+        return C, S
+
+    @staticmethod
+    def backward(ctx, gC, gS):
+        (A,) = ctx.saved_tensors
+        gA = torch.empty_like(A)
+        gC = gC.contiguous() if gC is not None else None
+        gS = gS.contiguous() if gS is not None else None
+        sincosm_backward(A, gC, gS, gA, ctx.accuracy, s=ctx.s)
+        return gA, None, None
+
+
+def sincosm(A: torch.Tensor, accuracy: str = "double", products: str = "native"):
+    """(cos A, sin A) for a square float64/float32 GPU tensor, differentiable in A."""
+    if A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("square matrix expected")
+    A = A.contiguous()
+    if A.requires_grad and torch.is_grad_enabled():
+        return _SinCosM.apply(A, accuracy, products)
+    C = torch.empty_like(A)
+    S = torch.empty_like(A)
+    sincosm_eval(A, C, S, accuracy, products)
+    return C, S
+
+
+def sincosm_batched(mats, accuracy: str = "double", products: str = "native"):
+    """cos and sin of a list of square GPU matrices of one dtype (packed into one batched call)."""
+    if not mats:
+        return [], []
+    dev, dt = mats[0].device, mats[0].dtype
+    ns = [int(m.shape[0]) for m in mats]
+    offs, o = [], 0
+    for n in ns:
+        offs.append(o)
+        o += n * n
+    A = torch.empty(max(o, 1), dtype=dt, device=dev)
+    for m, off, n in zip(mats, offs, ns):
+        A[off:off + n * n].copy_(m.reshape(-1))
+    C = torch.empty_like(A)
+    S = torch.empty_like(A)
+    sincosm_eval_batched(ns, offs, A, C, S, accuracy, products)
+    Cs = [C[off:off + n * n].view(n, n) for off, n in zip(offs, ns)]
+    Ss = [S[off:off + n * n].view(n, n) for off, n in zip(offs, ns)]
+    return Cs, Ss

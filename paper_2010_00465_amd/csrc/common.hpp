@@ -1,0 +1,157 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "sincosm.h"
+
+namespace sc {
+
+// ----------------------------------------------------------------------------
+// Status helpers
+// ----------------------------------------------------------------------------
+#define SC_HIP(expr)                                   \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return SINCOSM_E_HIP;        \
+  } while (0)
+
+#define SC_TRY(expr)                                   \
+  do {                                                 \
+    sincosm_status st_ = (expr);                       \
+    if (st_ != SINCOSM_OK) return st_;                 \
+  } while (0)
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ----------------------------------------------------------------------------
+// Plan rule (host and device share the constants through this header only
+// within the library; the oracle keeps its own copy).
+// ----------------------------------------------------------------------------
+// min(theta^c, theta^s) per scheme with 3, 4, 6, 7 products: Table 1 (u = 2^-53)
+// and Table 2 (u = 2^-24). The 7-product double bound is 1.8548: the sine's
+// printed 1.97 is not reproduced by the printed coefficients.
+__host__ __device__ inline double plan_theta(int acc, int idx) {
+  const double dbl[4] = {6.5633e-3, 8.0438e-2, 9.8108e-1, 1.8548};
+  const double sgl[4] = {1.8709e-1, 7.492e-1, 2.9935, 4.3819};
+  return acc == SINCOSM_ACC_SINGLE ? sgl[idx] : dbl[idx];
+}
+
+// Fills level, s, products, status; norm1 is stored as given.
+__host__ __device__ inline void plan_rule(double norm1, int acc, sincosm_plan* p) {
+  const int levels[4] = {3, 4, 6, 7};
+  p->norm1 = norm1;
+  if (!(norm1 >= 0.0 && norm1 <= 1.7976931348623157e308)) {  // NaN, negative or +Inf
+    p->level = 0; p->s = 0; p->products = 0; p->status = SINCOSM_E_NONFINITE;
+    return;
+  }
+  int best_cost = 0x7fffffff, best_s = 0, best_level = 3;
+  for (int i = 0; i < 4; ++i) {
+    const double th = plan_theta(acc, i);
+    int s = 0;
+    double t = norm1;
+    while (t > th) { t *= 0.5; ++s; }     // exact halving: no log2 rounding
+    const int cost = levels[i] + 2 * s;
+    if (cost < best_cost || (cost == best_cost && s < best_s)) {
+      best_cost = cost; best_s = s; best_level = levels[i];
+    }
+  }
+  p->level = best_level; p->s = best_s; p->products = best_cost; p->status = SINCOSM_OK;
+}
+
+// ----------------------------------------------------------------------------
+// GEMM-with-epilogue descriptors.
+//
+// One launch computes, for each problem p in [0, nprob) and each output tile,
+//   D = sum_seg scale_seg * L_seg R_seg          (K = kdim per segment)
+// and writes every output o of the problem as
+//   O_o = e_o D + sum_q c_oq M_q + d_o [i == j < nvalid]
+// where M_q are same-position tiles of the problem's inputs. Outputs are
+// stored only where row < lim_o and col < lim_o; internal (padded) buffers
+// use lim = padded size so their padding stays exactly zero.
+// ----------------------------------------------------------------------------
+constexpr int MAX_SEG = 3;
+constexpr int MAX_IN = 4;
+constexpr int MAX_OUT = 6;
+constexpr int MAX_PROB = 2;
+
+struct Seg {
+  const void* L;
+  const void* R;
+  int64_t ldl, ldr;
+  double lscale;     // multiplies the left operand values as they are staged
+  double rscale;     // multiplies the right operand values (powers of two or -1 keep it exact)
+};
+
+struct EpiIn {
+  const void* p;
+  int64_t ld;
+};
+
+struct EpiOut {
+  void* p;
+  int64_t ld;
+  int32_t lim;
+  int32_t f64;       // 1: store float64, 0: store the kernel's compute type
+  double e, d;
+  double c[MAX_IN];
+};
+
+struct Problem {
+  int32_t nseg, nin, nout, nvalid;
+  Seg seg[MAX_SEG];
+  EpiIn in[MAX_IN];
+  EpiOut out[MAX_OUT];
+};
+
+struct GemmLaunch {
+  int32_t np;        // padded order (multiple of the tile); M = N = K = np per segment
+  int32_t nprob;
+  Problem prob[MAX_PROB];
+};
+
+// Product arithmetic of one GEMM launch.
+enum class Arith { F64, F32, BF16X3 };
+
+// Launch one GEMM-with-epilogue over all problems. `tile` selects the tile
+// configuration (see gemm.hip); np must be a multiple of tile_size(tile).
+sincosm_status launch_gemm(Arith ar, int tile, const GemmLaunch& g, hipStream_t stream);
+int tile_size(int tile);
+int choose_tile(Arith ar, int64_t n);
+bool bf16x3_available();
+
+// ----------------------------------------------------------------------------
+// Norm / copy / plan / fill kernels (norm_plan.hip)
+// ----------------------------------------------------------------------------
+struct NormScratch {
+  double* partial;        // [nchunks][np]
+  unsigned long long* maxbits;
+  sincosm_plan* plan;
+  int nchunks;
+};
+size_t norm_scratch_bytes(int64_t np);
+NormScratch norm_scratch(void* base, int64_t np);
+
+// Column abs-sum partials of A (n x n, lda, type src_f64 ? double : float) and
+// a zero-padded copy Ap (np x np, type dst_f64 ? double : float); then plan.
+sincosm_status launch_norm_copy_plan(int64_t n, int64_t np, const void* A, int64_t lda, bool src_f64,
+                                     void* Ap, bool dst_f64, int acc,
+                                     const NormScratch& ns, hipStream_t stream);
+// dst (np x np, zero padded) = src^T for an n x n src.
+sincosm_status launch_transpose_pad(int64_t n, int64_t np, const void* src, int64_t lds, bool src_f64,
+                                    void* dst, bool dst_f64, hipStream_t stream);
+sincosm_status launch_fill_nan(int64_t n, void* X, int64_t ld, bool f64, hipStream_t stream);
+sincosm_status launch_convert_pad(int64_t n, int64_t np, const void* src, int64_t lds, bool src_f64,
+                                  void* dst, bool dst_f64, hipStream_t stream);
+
+// ----------------------------------------------------------------------------
+// Launch timing (timing.cpp); kinds match SINCOSM_TIMING_* in the header.
+// ----------------------------------------------------------------------------
+struct TimingMark { int kind; void* a; };
+bool timing_on();
+TimingMark timing_begin(int kind, hipStream_t stream);
+void timing_end(const TimingMark& m, hipStream_t stream);
+
+}  // namespace sc

@@ -1,0 +1,314 @@
+// Matrix products with fused linear-combination epilogues on CDNA4 MFMA.
+//
+// Every product of the method (the scheme products of Section 2.1 and the
+// two products of each double-angle step of Section 1) is one launch of this
+// kernel family. A launch computes, per problem and per output tile,
+//   D = sum_seg (lscale L_seg)(rscale R_seg)
+// and writes several outputs O_o = e_o D + sum_q c_oq M_q + d_o I from the
+// accumulators, reading the same tile of up to MAX_IN other matrices. This is
+// how the scheme's updates such as I - A_2/2 + x_8 A_4 + A_16 are fused into
+// the product that produces their last term.
+//
+// Design for gfx950:
+//  * 16x16x4 MFMA (f64 or f32); each wave owns a WTM x WTN sub-tile as
+//    FM x FN MFMA blocks held in accumulator registers.
+//  * Operand tiles are staged through LDS, double buffered, one barrier per
+//    BK step; the next tile's global loads are issued before the MFMAs of the
+//    current one so their latency hides behind the matrix core.
+//  * LDS layouts: A as [m][k] with row pitch BK+1, B as [k][n] with row pitch
+//    BN+16, so the 16-lane groups that feed one MFMA read distinct banks.
+//  * All operands are internal buffers padded with zeros to a multiple of the
+//    tile, so the main loop has no bounds checks; only outputs carry a limit.
+//  * Block index -> tile: consecutive launch indices go to different XCDs, so
+//    the index is first remapped to give each XCD a contiguous range of tiles,
+//    then walked in groups of 8 tile rows to keep operand panels in L2.
+#include "common.hpp"
+
+namespace sc {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+template <typename T>
+struct Mma;
+
+template <>
+struct Mma<double> {
+  typedef v4d acc_t;
+  typedef v2d vec_t;       // 16-byte global load
+  static constexpr int VEC = 2;
+  __device__ static inline acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // 16x16 result: lane group lg (= lane / 16), register r -> row lg + 4 r
+  __device__ static inline int row_in_block(int lg, int r) { return lg + 4 * r; }
+};
+
+template <>
+struct Mma<float> {
+  typedef v4f acc_t;
+  typedef v4f vec_t;
+  static constexpr int VEC = 4;
+  __device__ static inline acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // 16x16 result: lane group lg, register r -> row 4 lg + r
+  __device__ static inline int row_in_block(int lg, int r) { return 4 * lg + r; }
+};
+
+// Map a launch index to (problem, tile row, tile column).
+__device__ inline void tile_coords(int np, int BM, int BN, int nprob, int& p, int& tm, int& tn) {
+  const int tmc = np / BM, tnc = np / BN, tiles = tmc * tnc;
+  const int total = tiles * nprob;
+  int b = blockIdx.x;
+  if ((total & 7) == 0) b = (b & 7) * (total >> 3) + (b >> 3);
+  p = b / tiles;
+  const int t = b - p * tiles;
+  constexpr int GROUP = 8;
+  const int group = t / (GROUP * tnc);
+  const int first = group * GROUP;
+  const int rows = (tmc - first) < GROUP ? (tmc - first) : GROUP;
+  const int in_group = t - group * GROUP * tnc;
+  tm = first + in_group % rows;
+  tn = in_group / rows;
+}
+
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int WPE>
+__global__ __launch_bounds__(WGM * WGN * 64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+void gemm_kernel(const GemmLaunch g) {
+  using M = Mma<T>;
+  using acc_t = typename M::acc_t;
+  using vec_t = typename M::vec_t;
+  constexpr int NT = WGM * WGN * 64;
+  constexpr int WTM = BM / WGM, WTN = BN / WGN;
+  constexpr int FM = WTM / 16, FN = WTN / 16;
+  constexpr int LDA = BK + 1, LDB = BN + 16;
+  constexpr int VEC = M::VEC;
+  constexpr int A_LOADS = BM * BK / VEC / NT;
+  constexpr int B_LOADS = BK * BN / VEC / NT;
+  // epilogue staging: one band of WTM rows (the rows of one row of waves) at a time
+  constexpr int LDE = BN + VEC;
+  constexpr int STAGE_ELEMS = 2 * (BM * LDA + BK * LDB);
+  constexpr int EPI_ELEMS = WTM * LDE;
+  constexpr int SMEM_ELEMS = STAGE_ELEMS > EPI_ELEMS ? STAGE_ELEMS : EPI_ELEMS;
+  static_assert(FM >= 1 && FN >= 1 && WTM % 16 == 0 && WTN % 16 == 0, "wave tile");
+  static_assert(A_LOADS >= 1 && A_LOADS * VEC * NT == BM * BK, "A staging");
+  static_assert(B_LOADS >= 1 && B_LOADS * VEC * NT == BK * BN, "B staging");
+  static_assert(BK % 4 == 0 && BK % VEC == 0 && BN % VEC == 0, "k tiling");
+
+  __shared__ __attribute__((aligned(16))) T smem[SMEM_ELEMS];
+  T* const As0 = smem;
+  T* const Bs0 = smem + 2 * BM * LDA;
+
+  const int np = g.np;
+  int p, tile_m, tile_n;
+  tile_coords(np, BM, BN, g.nprob, p, tile_m, tile_n);
+  const Problem& P = g.prob[p];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
+  const int lr = lane & 15, lg = lane >> 4;
+
+  acc_t acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = (T)0;
+
+  // Per-thread staging offsets (elements), fixed for the whole k loop. All
+  // operands are np x np internal buffers with leading dimension np.
+  int offA[A_LOADS], offB[B_LOADS], ldsA[A_LOADS], ldsB[B_LOADS];
+#pragma unroll
+  for (int i = 0; i < A_LOADS; ++i) {
+    const int e = (i * NT + tid) * VEC;
+    const int r = e / BK, c = e - r * BK;
+    offA[i] = r * np + c;
+    ldsA[i] = r * LDA + c;
+  }
+#pragma unroll
+  for (int i = 0; i < B_LOADS; ++i) {
+    const int e = (i * NT + tid) * VEC;
+    const int r = e / BN, c = e - r * BN;
+    offB[i] = r * np + c;
+    ldsB[i] = r * LDB + c;
+  }
+
+  const int nk = np / BK;
+  const int nkt = P.nseg * nk;
+  vec_t ra[A_LOADS], rb[B_LOADS];
+  const int64_t a_tile = (int64_t)tile_m * BM * np;
+  const int64_t b_tile = (int64_t)tile_n * BN;
+
+  auto gload = [&](int kt) {
+    const int sidx = kt / nk;
+    const int k0 = (kt - sidx * nk) * BK;
+    const T* L = (const T*)P.seg[sidx].L + a_tile + k0;
+    const T* R = (const T*)P.seg[sidx].R + b_tile + (int64_t)k0 * np;
+#pragma unroll
+    for (int i = 0; i < A_LOADS; ++i) ra[i] = *(const vec_t*)(L + offA[i]);
+#pragma unroll
+    for (int i = 0; i < B_LOADS; ++i) rb[i] = *(const vec_t*)(R + offB[i]);
+  };
+
+  auto lstore = [&](int buf, int kt) {
+    const Seg& S = P.seg[kt / nk];
+    T* as = As0 + buf * (BM * LDA);
+    T* bs = Bs0 + buf * (BK * LDB);
+    if (S.lscale != 1.0 || S.rscale != 1.0) {
+      const T ls = (T)S.lscale, rs = (T)S.rscale;
+#pragma unroll
+      for (int i = 0; i < A_LOADS; ++i) ra[i] = ra[i] * ls;
+#pragma unroll
+      for (int i = 0; i < B_LOADS; ++i) rb[i] = rb[i] * rs;
+    }
+#pragma unroll
+    for (int i = 0; i < A_LOADS; ++i)
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) as[ldsA[i] + q] = ra[i][q];
+#pragma unroll
+    for (int i = 0; i < B_LOADS; ++i) *(vec_t*)(bs + ldsB[i]) = rb[i];
+  };
+
+  gload(0);
+  lstore(0, 0);
+  __syncthreads();
+
+  for (int kt = 0; kt < nkt; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nkt) gload(kt + 1);
+    const T* as = As0 + cur * (BM * LDA) + (wm * WTM + lr) * LDA + lg;
+    const T* bs = Bs0 + cur * (BK * LDB) + lg * LDB + wn * WTN + lr;
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      T a[FM], b[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) a[i] = as[i * 16 * LDA + kk * 4];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) b[j] = bs[kk * 4 * LDB + j * 16];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = M::mma(a[i], b[j], acc[i][j]);
+    }
+    if (kt + 1 < nkt) lstore(cur ^ 1, kt + 1);
+    __syncthreads();
+  }
+
+  // Epilogue, one band of WTM rows at a time: the waves of band wm write their
+  // accumulators to LDS (MFMA layout: lane (lg, lr), register r -> column lr,
+  // row M::row_in_block(lg, r) of each 16 x 16 block), then all threads read
+  // the band back in row-major order, VEC consecutive columns per thread, so
+  // every global access of the epilogue is a coalesced 16-byte access.
+  const int nin = P.nin, nout = P.nout, nvalid = P.nvalid;
+  T* const E = smem;
+  for (int band = 0; band < WGM; ++band) {
+    if (wm == band) {
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            E[(i * 16 + M::row_in_block(lg, r)) * LDE + wn * WTN + j * 16 + lr] = acc[i][j][r];
+    }
+    __syncthreads();
+    for (int e = tid * VEC; e < WTM * BN; e += NT * VEC) {
+      const int br = e / BN, bc = e - br * BN;
+      const int row = tile_m * BM + band * WTM + br;
+      const int col = tile_n * BN + bc;
+      const vec_t v = *(const vec_t*)(E + br * LDE + bc);
+      vec_t x[MAX_IN];
+#pragma unroll
+      for (int q = 0; q < MAX_IN; ++q)
+        if (q < nin) x[q] = *(const vec_t*)((const T*)P.in[q].p + (int64_t)row * np + col);
+#pragma unroll
+      for (int o = 0; o < MAX_OUT; ++o) {
+        if (o >= nout) break;
+        const EpiOut& O = P.out[o];
+        vec_t val;
+#pragma unroll
+        for (int t = 0; t < VEC; ++t) {
+          T y = (row == col + t && row < nvalid) ? (T)O.d : (T)0;
+          y = __builtin_fma((T)O.e, v[t], y);
+#pragma unroll
+          for (int q = 0; q < MAX_IN; ++q)
+            if (q < nin) y = __builtin_fma((T)O.c[q], x[q][t], y);
+          val[t] = y;
+        }
+        const int64_t off = (int64_t)row * O.ld + col;
+        const bool internal = O.lim == np && O.ld == np && (O.f64 != 0) == (sizeof(T) == 8);
+        if (internal) {
+          *(vec_t*)((T*)O.p + off) = val;
+        } else if (row < O.lim) {
+#pragma unroll
+          for (int t = 0; t < VEC; ++t) {
+            if (col + t < O.lim) {
+              if (O.f64) ((double*)O.p)[off + t] = (double)val[t];
+              else ((T*)O.p)[off + t] = val[t];
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Tile configurations. Index -> (BM = BN, BK, wave grid, waves per SIMD).
+//   0: 128 x 128, BK 16, 2 x 2 waves of 64 x 64   (large n)
+//   1:  64 x  64, BK 16, 2 x 2 waves of 32 x 32   (mid n)
+//   2:  32 x  32, BK 16, 2 x 2 waves of 16 x 16   (small n)
+// ----------------------------------------------------------------------------
+int tile_size(int tile) {
+  switch (tile) {
+    case 0: return 128;
+    case 1: return 64;
+    default: return 32;
+  }
+}
+
+int choose_tile(Arith ar, int64_t n) {
+  (void)ar;
+  if (n >= 1536) return 0;
+  if (n >= 256) return 1;
+  return 2;
+}
+
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int WPE>
+static sincosm_status launch_cfg(const GemmLaunch& g, hipStream_t stream) {
+  const int tiles = (g.np / BM) * (g.np / BN) * g.nprob;
+  if (tiles <= 0) return SINCOSM_OK;
+  gemm_kernel<T, BM, BN, BK, WGM, WGN, WPE><<<tiles, WGM * WGN * 64, 0, stream>>>(g);
+  SC_HIP(hipGetLastError());
+  return SINCOSM_OK;
+}
+
+sincosm_status launch_gemm(Arith ar, int tile, const GemmLaunch& g, hipStream_t stream) {
+  if (g.np % tile_size(tile) != 0) return SINCOSM_E_ARG;
+  if (ar == Arith::F64) {
+    switch (tile) {
+      case 0: return launch_cfg<double, 128, 128, 16, 2, 2, 2>(g, stream);
+      case 1: return launch_cfg<double, 64, 64, 16, 2, 2, 2>(g, stream);
+      default: return launch_cfg<double, 32, 32, 16, 2, 2, 2>(g, stream);
+    }
+  }
+  if (ar == Arith::F32) {
+    switch (tile) {
+      case 0: return launch_cfg<float, 128, 128, 16, 2, 2, 2>(g, stream);
+      case 1: return launch_cfg<float, 64, 64, 16, 2, 2, 2>(g, stream);
+      default: return launch_cfg<float, 32, 32, 32, 2, 2, 2>(g, stream);
+    }
+  }
+  return SINCOSM_E_UNSUPPORTED;
+}
+
+}  // namespace sc
+
+namespace sc {
+bool bf16x3_available() { return false; }
+}  // namespace sc

@@ -1,0 +1,184 @@
+// 1-norm, padded copy, plan and small elementwise kernels.
+//
+// The 1-norm (maximum absolute column sum) drives the choice of scheme and
+// scaling (Section 3 bounds in terms of theta = ||A||, Tables 1-2, and the
+// 1-norm named in Section 4). It is computed in float64 with a fixed
+// summation order, so the plan is reproducible bit for bit:
+//   stage 1: each block sums |a_ij| down a chunk of NORM_ROWS rows for 256
+//            columns, writing one partial per (chunk, column), and writes the
+//            zero-padded copy of the same elements;
+//   stage 2: each column adds its partials in chunk order, and the maximum
+//            over columns is taken with an integer atomicMax on the float64
+//            bit pattern (order-independent, so still deterministic; NaN and
+//            Inf patterns compare above every finite value);
+//   stage 3: one thread applies the plan rule.
+#include "common.hpp"
+
+namespace sc {
+
+constexpr int NORM_ROWS = 64;
+constexpr int NORM_COLS = 256;
+
+size_t norm_scratch_bytes(int64_t np) {
+  const int64_t nchunks = (np + NORM_ROWS - 1) / NORM_ROWS;
+  return align_up(sizeof(sincosm_plan), 256) + 256 + align_up((size_t)nchunks * np * sizeof(double), 256);
+}
+
+NormScratch norm_scratch(void* base, int64_t np) {
+  NormScratch s;
+  char* p = (char*)base;
+  s.plan = (sincosm_plan*)p;
+  p += align_up(sizeof(sincosm_plan), 256);
+  s.maxbits = (unsigned long long*)p;
+  p += 256;
+  s.partial = (double*)p;
+  s.nchunks = (int)((np + NORM_ROWS - 1) / NORM_ROWS);
+  return s;
+}
+
+template <typename TS, typename TD>
+__global__ __launch_bounds__(NORM_COLS) void norm_copy_kernel(int64_t n, int64_t np, const TS* __restrict__ A,
+                                                             int64_t lda, TD* __restrict__ Ap,
+                                                             double* __restrict__ partial,
+                                                             unsigned long long* maxbits) {
+  const int64_t j = (int64_t)blockIdx.x * NORM_COLS + threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.y * NORM_ROWS;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *maxbits = 0ull;
+  if (j >= np) return;
+  double sum = 0.0;
+  const int64_t i1 = i0 + NORM_ROWS < np ? i0 + NORM_ROWS : np;
+  for (int64_t i = i0; i < i1; ++i) {
+    double v = 0.0;
+    if (i < n && j < n) v = (double)A[i * lda + j];
+    if (Ap) Ap[i * np + j] = (TD)v;
+    sum += fabs(v);
+  }
+  partial[(int64_t)blockIdx.y * np + j] = sum;
+}
+
+__global__ __launch_bounds__(NORM_COLS) void norm_reduce_kernel(int64_t np, int nchunks,
+                                                               const double* __restrict__ partial,
+                                                               unsigned long long* maxbits) {
+  __shared__ unsigned long long red[NORM_COLS];
+  const int64_t j = (int64_t)blockIdx.x * NORM_COLS + threadIdx.x;
+  unsigned long long bits = 0ull;
+  if (j < np) {
+    double s = 0.0;
+    for (int c = 0; c < nchunks; ++c) s += partial[(int64_t)c * np + j];
+    bits = (unsigned long long)__double_as_longlong(s);
+  }
+  red[threadIdx.x] = bits;
+  __syncthreads();
+  for (int w = NORM_COLS / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      const unsigned long long o = red[threadIdx.x + w];
+      if (o > red[threadIdx.x]) red[threadIdx.x] = o;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(maxbits, red[0]);
+}
+
+__global__ void plan_kernel(const unsigned long long* maxbits, int acc, sincosm_plan* plan) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double nrm = __longlong_as_double((long long)*maxbits);
+  sincosm_plan p;
+  plan_rule(nrm, acc, &p);
+  *plan = p;
+}
+
+template <typename TS, typename TD>
+static void launch_norm_t(int64_t n, int64_t np, const void* A, int64_t lda, void* Ap, const NormScratch& ns,
+                          int acc, hipStream_t stream) {
+  dim3 g1((unsigned)((np + NORM_COLS - 1) / NORM_COLS), (unsigned)ns.nchunks);
+  norm_copy_kernel<TS, TD><<<g1, NORM_COLS, 0, stream>>>(n, np, (const TS*)A, lda, (TD*)Ap, ns.partial,
+                                                         ns.maxbits);
+  dim3 g2((unsigned)((np + NORM_COLS - 1) / NORM_COLS));
+  norm_reduce_kernel<<<g2, NORM_COLS, 0, stream>>>(np, ns.nchunks, ns.partial, ns.maxbits);
+  plan_kernel<<<1, 64, 0, stream>>>(ns.maxbits, acc, ns.plan);
+}
+
+sincosm_status launch_norm_copy_plan(int64_t n, int64_t np, const void* A, int64_t lda, bool src_f64, void* Ap,
+                                     bool dst_f64, int acc, const NormScratch& ns, hipStream_t stream) {
+  if (src_f64 && dst_f64) launch_norm_t<double, double>(n, np, A, lda, Ap, ns, acc, stream);
+  else if (src_f64 && !dst_f64) launch_norm_t<double, float>(n, np, A, lda, Ap, ns, acc, stream);
+  else if (!src_f64 && dst_f64) launch_norm_t<float, double>(n, np, A, lda, Ap, ns, acc, stream);
+  else launch_norm_t<float, float>(n, np, A, lda, Ap, ns, acc, stream);
+  SC_HIP(hipGetLastError());
+  return SINCOSM_OK;
+}
+
+// Tiled transpose with zero padding: dst[j][i] = src[i][j] for i, j < n.
+template <typename TS, typename TD>
+__global__ __launch_bounds__(256) void transpose_pad_kernel(int64_t n, int64_t np, const TS* __restrict__ src,
+                                                           int64_t lds, TD* __restrict__ dst) {
+  __shared__ double tile[32][33];
+  const int64_t bi = (int64_t)blockIdx.y * 32, bj = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = bi + r, j = bj + tx;
+    tile[r][tx] = (i < n && j < n) ? (double)src[i * lds + j] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = bj + r, j = bi + tx;  // dst row i = src column
+    if (i < np && j < np) dst[i * np + j] = (TD)tile[tx][r];
+  }
+}
+
+sincosm_status launch_transpose_pad(int64_t n, int64_t np, const void* src, int64_t lds, bool src_f64, void* dst,
+                                    bool dst_f64, hipStream_t stream) {
+  dim3 g((unsigned)((np + 31) / 32), (unsigned)((np + 31) / 32));
+  if (src_f64 && dst_f64)
+    transpose_pad_kernel<double, double><<<g, 256, 0, stream>>>(n, np, (const double*)src, lds, (double*)dst);
+  else if (src_f64)
+    transpose_pad_kernel<double, float><<<g, 256, 0, stream>>>(n, np, (const double*)src, lds, (float*)dst);
+  else if (dst_f64)
+    transpose_pad_kernel<float, double><<<g, 256, 0, stream>>>(n, np, (const float*)src, lds, (double*)dst);
+  else
+    transpose_pad_kernel<float, float><<<g, 256, 0, stream>>>(n, np, (const float*)src, lds, (float*)dst);
+  SC_HIP(hipGetLastError());
+  return SINCOSM_OK;
+}
+
+template <typename TS, typename TD>
+__global__ __launch_bounds__(256) void convert_pad_kernel(int64_t n, int64_t np, const TS* __restrict__ src,
+                                                         int64_t lds, TD* __restrict__ dst) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = blockIdx.y;
+  if (j >= np) return;
+  dst[i * np + j] = (TD)((i < n && j < n) ? (double)src[i * lds + j] : 0.0);
+}
+
+sincosm_status launch_convert_pad(int64_t n, int64_t np, const void* src, int64_t lds, bool src_f64, void* dst,
+                                  bool dst_f64, hipStream_t stream) {
+  dim3 g((unsigned)((np + 255) / 256), (unsigned)np);
+  if (src_f64 && dst_f64)
+    convert_pad_kernel<double, double><<<g, 256, 0, stream>>>(n, np, (const double*)src, lds, (double*)dst);
+  else if (src_f64)
+    convert_pad_kernel<double, float><<<g, 256, 0, stream>>>(n, np, (const double*)src, lds, (float*)dst);
+  else if (dst_f64)
+    convert_pad_kernel<float, double><<<g, 256, 0, stream>>>(n, np, (const float*)src, lds, (double*)dst);
+  else
+    convert_pad_kernel<float, float><<<g, 256, 0, stream>>>(n, np, (const float*)src, lds, (float*)dst);
+  SC_HIP(hipGetLastError());
+  return SINCOSM_OK;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void fill_nan_kernel(int64_t n, T* X, int64_t ld) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = blockIdx.y;
+  if (j < n) X[i * ld + j] = (T)__longlong_as_double(0x7ff8000000000000ll);
+}
+
+sincosm_status launch_fill_nan(int64_t n, void* X, int64_t ld, bool f64, hipStream_t stream) {
+  if (n <= 0) return SINCOSM_OK;
+  dim3 g((unsigned)((n + 255) / 256), (unsigned)n);
+  if (f64) fill_nan_kernel<double><<<g, 256, 0, stream>>>(n, (double*)X, ld);
+  else fill_nan_kernel<float><<<g, 256, 0, stream>>>(n, (float*)X, ld);
+  SC_HIP(hipGetLastError());
+  return SINCOSM_OK;
+}
+
+}  // namespace sc

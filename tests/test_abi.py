@@ -1,0 +1,87 @@
+"""C-ABI library checks that need no GPU: it loads, exports every function the
+header declares, and its host plan rule agrees with the oracle's."""
+import ctypes
+import json
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sincosm.h")
+LIB = os.path.join(ROOT, "paper_2010_00465_amd", "libsincosm.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sincosm_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libsincosm.so is not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_binding_names_match_header():
+    from paper_2010_00465_amd import _lib
+    assert sorted(_lib.SYMBOLS) == declared_functions()
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("s", ctypes.c_int32), ("products", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("norm1", ctypes.c_double)]
+
+
+def host_plan(lib, t, acc):
+    p = Plan()
+    lib.sincosm_plan_host.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.POINTER(Plan)]
+    assert lib.sincosm_plan_host(t, acc, ctypes.byref(p)) == 0
+    return p
+
+
+def test_host_plan_matches_oracle_fixture(lib):
+    with open(os.path.join(ROOT, "tests", "golden", "plan_breakpoints.json")) as f:
+        cases = json.load(f)["cases"]
+    for c in cases:
+        t = float.fromhex(c["norm1"])
+        p = host_plan(lib, t, 0 if c["accuracy"] == "double" else 1)
+        assert (p.level, p.s, p.products, p.status) == (c["level"], c["s"], c["products"], 0), c
+
+
+def test_host_plan_matches_oracle_random(lib):
+    from oracle import plan as P
+    ts = np.exp2(np.random.default_rng(5).uniform(-40, 60, size=4000))
+    for t in ts:
+        for acc, name in ((0, "double"), (1, "single")):
+            p = host_plan(lib, float(t), acc)
+            assert (p.level, p.s, p.products) == P.plan(float(t), name)
+
+
+def test_host_plan_nonfinite(lib):
+    for t in (math.nan, math.inf, -1.0):
+        p = host_plan(lib, t, 0)
+        assert p.status == -4
+
+
+def test_argument_errors_without_gpu(lib):
+    lib.sincosm_workspace_size.restype = ctypes.c_size_t
+    lib.sincosm_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    assert lib.sincosm_workspace_size(0, 0, 0, 0) == 0
+    assert lib.sincosm_workspace_size(64, 7, 0, 0) == 0          # bad dtype
+    assert lib.sincosm_workspace_size(64, 0, 0, 0) > 10 * 64 * 64 * 8
+    lib.sincosm_strerror.restype = ctypes.c_char_p
+    assert lib.sincosm_strerror(-3) == b"workspace missing or too small"
+    lib.sincosm_plan_host.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_void_p]
+    assert lib.sincosm_plan_host(1.0, 5, None) == -1

@@ -1,0 +1,311 @@
+"""GPU parity of sincosm_eval (through the C ABI) against the CPU oracle.
+
+Bars: relative Frobenius error <= 1e-12 against the float64 oracle for the
+double-accuracy float64 path; the plan integers (level, s) equal the oracle's
+(either neighbour accepted within 1e-12 relative of a breakpoint, where the two
+1-norm summation orders may round differently)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import paper_algorithm as PA
+from oracle import plan as P
+from oracle import reference as R
+from tests.conftest import rel_fro
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2010_00465_amd as sc
+    return torch, sc
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def run(env, A_np, accuracy="double", products="native", dtype=None):
+    torch, sc = env
+    t = torch.from_numpy(np.ascontiguousarray(A_np)).cuda()
+    if dtype is not None:
+        t = t.to(dtype)
+    C = torch.empty_like(t)
+    S = torch.empty_like(t)
+    plan = sc.sincosm_eval(t, C, S, accuracy, products)
+    torch.cuda.synchronize()
+    return C.cpu().double().numpy(), S.cpu().double().numpy(), plan
+
+
+def plan_ok(plan, A, acc="double"):
+    t = float(np.abs(A).sum(0).max())
+    want = P.plan(t, acc)
+    if (plan.level, plan.s, plan.products) == want:
+        return True
+    for f in (1 - 1e-12, 1 + 1e-12):
+        if (plan.level, plan.s, plan.products) == P.plan(t * f, acc):
+            return True
+    return False
+
+
+# ---------------------------------------------------------------------------
+# Products
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [1, 16, 37, 64, 100, 128, 300, 777, 1000, 1600])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_matmul(env, n, dt):
+    torch, sc = env
+    say("matmul", n, dt)
+    g = W.rng(40, n)
+    X = g.standard_normal((n, n))
+    Y = g.standard_normal((n, n))
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    Xt = torch.from_numpy(X).cuda().to(tdt)
+    Yt = torch.from_numpy(Y).cuda().to(tdt)
+    Z = torch.empty_like(Xt)
+    sc.sincosm_matmul(Xt, Yt, Z)
+    torch.cuda.synchronize()
+    Xr = Xt.cpu().double().numpy()
+    Yr = Yt.cpu().double().numpy()
+    ref = Xr @ Yr
+    bound = np.abs(Xr) @ np.abs(Yr)
+    u = 2.0 ** -53 if dt == "f64" else 2.0 ** -24
+    err = np.max(np.abs(Z.cpu().double().numpy() - ref) / bound)
+    assert err <= 2 * n * u, err
+
+
+def test_matmul_strided(env):
+    torch, sc = env
+    say("matmul strided")
+    g = W.rng(41)
+    big = torch.from_numpy(g.standard_normal((90, 120))).cuda()
+    X = big[:70, 5:75]
+    Y = big[10:80, 40:110]
+    Zb = torch.zeros(80, 100, dtype=torch.float64, device="cuda")
+    Z = Zb[3:73, 7:77]
+    sc.sincosm_matmul(X, Y, Z)
+    torch.cuda.synchronize()
+    ref = X.cpu().numpy() @ Y.cpu().numpy()
+    assert np.max(np.abs(Z.cpu().numpy() - ref)) < 1e-12
+    # outside the written window stays zero
+    Zc = Zb.cpu().numpy().copy()
+    Zc[3:73, 7:77] = 0
+    assert not Zc.any()
+
+
+# ---------------------------------------------------------------------------
+# Whole path, float64
+# ---------------------------------------------------------------------------
+def test_config_small_n64(env):
+    """n = 64 Gaussian rescaled to ||A||_1 = 2 (7 products, s = 1: 9 products)."""
+    say("config n=64 norm=2")
+    A = W.gaussian(64, 2.0, key=(1, 64, 0, 0))
+    C, S, plan = run(env, A)
+    assert (plan.level, plan.s, plan.products) == (7, 1, 9)
+    Cl, Sl = R.sincosm_ld(A)
+    assert rel_fro(C, Cl.astype(float)) <= 1e-12
+    assert rel_fro(S, Sl.astype(float)) <= 1e-12
+    Cp, Sp = PA.sincosm(A)
+    assert rel_fro(C, Cp) <= 1e-13
+    assert rel_fro(S, Sp) <= 1e-13
+
+
+LEVEL_EXPS = [-9.0, -5.0, -1.0, 0.5, 1.0, 2.0, 5.0, 10.0]
+
+
+@pytest.mark.parametrize("family", ["gaussian", "symmetric", "laplacian1d"])
+@pytest.mark.parametrize("n", [33, 64, 257])
+@pytest.mark.parametrize("e", LEVEL_EXPS)
+def test_levels_and_scaling(env, family, n, e):
+    say("eval", family, n, e)
+    A = W.family(family, n, 2.0 ** e, key=(42, n, int(e * 2) + 40))
+    C, S, plan = run(env, A)
+    assert plan_ok(plan, A)
+    Cr, Sr = R.sincosm(A)
+    assert rel_fro(C, Cr) <= 1e-12
+    assert rel_fro(S, Sr) <= 1e-12
+
+
+def test_every_level_reached(env):
+    seen = set()
+    for e in LEVEL_EXPS:
+        A = W.gaussian(48, 2.0 ** e, key=(43, int(e * 2) + 40))
+        seen.add(run(env, A)[2].level)
+    assert seen == {3, 4, 6, 7}
+
+
+@pytest.mark.parametrize("n,e", [(1000, 0.0), (1000, 4.0), (1536, 10.0), (2100, 3.0)])
+def test_larger_n(env, n, e):
+    say("eval large", n, e)
+    A = W.gaussian(n, 2.0 ** e, key=(44, n))
+    C, S, plan = run(env, A)
+    assert plan_ok(plan, A)
+    Cr, Sr = R.sincosm(A)
+    assert rel_fro(C, Cr) <= 1e-12
+    assert rel_fro(S, Sr) <= 1e-12
+
+
+def test_n4096_oracle_small_norm(env):
+    say("eval 4096 oracle e=-4")
+    A = W.gaussian(4096, 2.0 ** -4, key=(2, 4096, 0, 0))
+    C, S, plan = run(env, A)
+    assert (plan.level, plan.s) == (4, 0)
+    Cr, Sr = R.sincosm(A)
+    assert rel_fro(C, Cr) <= 1e-12
+    assert rel_fro(S, Sr) <= 1e-12
+
+
+@pytest.mark.parametrize("e", [4.0, 10.0])
+def test_n4096_identities(env, e):
+    """At full size: cos^2 + sin^2 = I and CS = SC (scaled residuals), on the GPU."""
+    torch, sc = env
+    say("eval 4096 identities", e)
+    n = 4096
+    A = torch.from_numpy(W.gaussian(n, 2.0 ** e, key=(2, n, 0, int(e)))).cuda()
+    C = torch.empty_like(A)
+    S = torch.empty_like(A)
+    plan = sc.sincosm_eval(A, C, S)
+    assert plan.products == P.plan(float(A.abs().sum(0).max()))[2]
+    I = torch.eye(n, dtype=torch.float64, device="cuda")
+    denom = float(C.norm() ** 2 + S.norm() ** 2 + n ** 0.5)
+    r1 = float((C @ C + S @ S - I).norm()) / denom
+    r2 = float((C @ S - S @ C).norm()) / denom
+    u = 2.0 ** -53
+    assert r1 <= 8 * n * u and r2 <= 8 * n * u, (r1, r2)
+
+
+# ---------------------------------------------------------------------------
+# Closed forms, edge cases, invariants
+# ---------------------------------------------------------------------------
+def test_n1(env):
+    for x in (0.0, 1e-3, 0.7, -2.5, 40.0):
+        C, S, plan = run(env, np.array([[x]]))
+        assert abs(C[0, 0] - math.cos(x)) <= 1e-15 * max(1, abs(x)) * 16
+        assert abs(S[0, 0] - math.sin(x)) <= 1e-15 * max(1, abs(x)) * 16
+
+
+def test_rotation_generator(env):
+    J = np.array([[0.0, -1.0], [1.0, 0.0]])
+    for t in (0.3, 2.0, 9.0):
+        C, S, _ = run(env, t * J)
+        assert rel_fro(C, math.cosh(t) * np.eye(2)) <= 1e-14 * max(1, t)
+        assert rel_fro(S, math.sinh(t) * J) <= 1e-14 * max(1, t)
+
+
+def test_nilpotent(env):
+    A = W.nilpotent_upper(40, key=(45,), rank_band=3) * 0.5
+    C, S, _ = run(env, A)
+    Cr, Sr = R.sincosm(A)
+    assert rel_fro(C, Cr) <= 1e-12 and rel_fro(S, Sr) <= 1e-12
+    assert not np.tril(C, -1).any() and not np.tril(S, -1).any()
+
+
+def test_zero_matrix_exact(env):
+    C, S, plan = run(env, np.zeros((50, 50)))
+    assert (plan.level, plan.s) == (3, 0)
+    assert np.array_equal(C, np.eye(50)) and not S.any()
+
+
+def test_parity_bitwise(env):
+    A = W.gaussian(130, 9.0, key=(46,))
+    C1, S1, _ = run(env, A)
+    C2, S2, _ = run(env, -A)
+    assert np.array_equal(C1, C2) and np.array_equal(S1, -S2)
+
+
+def test_deterministic(env):
+    A = W.gaussian(300, 30.0, key=(47,))
+    a = run(env, A)
+    b = run(env, A)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_transpose_consistency(env):
+    A = W.gaussian(90, 3.0, key=(48,))
+    C, S, _ = run(env, A)
+    Ct, St, _ = run(env, A.T.copy())
+    # the plan may differ (1-norm vs infinity-norm), the functions agree
+    assert rel_fro(Ct, C.T) <= 1e-12 and rel_fro(St, S.T) <= 1e-12
+
+
+def test_nonfinite_input(env):
+    torch, sc = env
+    A = torch.zeros(20, 20, dtype=torch.float64, device="cuda")
+    A[3, 4] = float("nan")
+    C = torch.zeros_like(A)
+    S = torch.zeros_like(A)
+    plan = sc.sincosm_eval(A, C, S, raise_nonfinite=False)
+    assert plan.status == -4
+    assert torch.isnan(C).all() and torch.isnan(S).all()
+    A[3, 4] = float("inf")
+    with pytest.raises(sc.SincosmError):
+        sc.sincosm_eval(A, C, S)
+
+
+def test_strided_views_and_errors(env):
+    torch, sc = env
+    g = W.rng(49)
+    big = torch.from_numpy(g.standard_normal((80, 90)) * 0.05).cuda()
+    A = big[5:65, 10:70]
+    Cb = torch.zeros(70, 75, dtype=torch.float64, device="cuda")
+    Sb = torch.zeros(70, 75, dtype=torch.float64, device="cuda")
+    C = Cb[2:62, 3:63]
+    S = Sb[2:62, 3:63]
+    sc.sincosm_eval(A, C, S)
+    Cr, Sr = R.sincosm(A.cpu().numpy())
+    assert rel_fro(C.cpu().numpy(), Cr) <= 1e-12 and rel_fro(S.cpu().numpy(), Sr) <= 1e-12
+    Cc = Cb.cpu().numpy().copy()
+    Cc[2:62, 3:63] = 0
+    assert not Cc.any()
+    # aliasing and workspace errors
+    with pytest.raises(sc.SincosmError) as ei:
+        sc.sincosm_eval(A, A, S)
+    assert ei.value.status == -1
+    small = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    with pytest.raises(sc.SincosmError) as ei:
+        sc.sincosm_eval(A, C, S, ws=small)
+    assert ei.value.status == -3
+
+
+def test_device_plan_matches_oracle(env):
+    torch, sc = env
+    for i, e in enumerate(np.linspace(-12, 30, 43)):
+        A = W.gaussian(24, 2.0 ** e, key=(50, i))
+        p = sc.plan_device(torch.from_numpy(A).cuda())
+        assert plan_ok(p, A), (e, p)
+        p = sc.plan_device(torch.from_numpy(A).cuda(), "single")
+        assert plan_ok(p, A, "single"), (e, p)
+
+
+# ---------------------------------------------------------------------------
+# Single accuracy / float32 storage / float32 products
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,e", [(64, 1.0), (257, 4.0), (1000, 6.0)])
+def test_float32_single(env, n, e):
+    torch, sc = env
+    say("eval f32", n, e)
+    A32 = W.gaussian(n, 2.0 ** e, key=(51, n)).astype(np.float32)
+    C, S, plan = run(env, A32, accuracy="single", dtype=torch.float32)
+    assert plan_ok(plan, A32.astype(np.float64), "single")
+    Cr, Sr = R.sincosm(A32.astype(np.float64))
+    assert rel_fro(C, Cr) <= 5e-6 * max(1, 2 ** plan.s / 16)
+    assert rel_fro(S, Sr) <= 5e-6 * max(1, 2 ** plan.s / 16)
+
+
+@pytest.mark.parametrize("n,e", [(64, 1.0), (500, 6.0)])
+def test_tier_f32_products(env, n, e):
+    torch, sc = env
+    say("eval tier f32 products", n, e)
+    A = W.gaussian(n, 2.0 ** e, key=(52, n))
+    C, S, plan = run(env, A, accuracy="single", products="f32")
+    assert plan_ok(plan, A, "single")
+    Cr, Sr = R.sincosm(A)
+    assert rel_fro(C, Cr) <= 5e-6 and rel_fro(S, Sr) <= 5e-6

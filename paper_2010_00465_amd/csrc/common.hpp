@@ -73,7 +73,7 @@ __host__ __device__ inline void plan_rule(double norm1, int acc, sincosm_plan* p
 // use lim = padded size so their padding stays exactly zero.
 // ----------------------------------------------------------------------------
 constexpr int MAX_SEG = 3;
-constexpr int MAX_IN = 4;
+constexpr int MAX_IN = 6;
 constexpr int MAX_OUT = 6;
 constexpr int MAX_PROB = 2;
 
@@ -143,6 +143,7 @@ sincosm_status launch_norm_copy_plan(int64_t n, int64_t np, const void* A, int64
 sincosm_status launch_transpose_pad(int64_t n, int64_t np, const void* src, int64_t lds, bool src_f64,
                                     void* dst, bool dst_f64, hipStream_t stream);
 sincosm_status launch_fill_nan(int64_t n, void* X, int64_t ld, bool f64, hipStream_t stream);
+sincosm_status launch_fill_zero(int64_t np, void* X, bool f64, hipStream_t stream);
 sincosm_status launch_convert_pad(int64_t n, int64_t np, const void* src, int64_t lds, bool src_f64,
                                   void* dst, bool dst_f64, hipStream_t stream);
 

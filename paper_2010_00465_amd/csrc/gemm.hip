@@ -173,8 +173,10 @@ void gemm_kernel(const GemmLaunch g) {
     for (int i = 0; i < B_LOADS; ++i) *(vec_t*)(bs + ldsB[i]) = rb[i];
   };
 
-  gload(0);
-  lstore(0, 0);
+  if (nkt > 0) {   // nseg == 0: epilogue-only launch (linear combination of inputs)
+    gload(0);
+    lstore(0, 0);
+  }
   __syncthreads();
 
   for (int kt = 0; kt < nkt; ++kt) {

@@ -165,6 +165,11 @@ sincosm_status launch_convert_pad(int64_t n, int64_t np, const void* src, int64_
   return SINCOSM_OK;
 }
 
+sincosm_status launch_fill_zero(int64_t np, void* X, bool f64, hipStream_t stream) {
+  // convert_pad with an empty source writes zeros over the whole np x np buffer
+  return launch_convert_pad(0, np, X, np, f64, X, f64, stream);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void fill_nan_kernel(int64_t n, T* X, int64_t ld) {
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;

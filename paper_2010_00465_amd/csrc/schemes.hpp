@@ -1,0 +1,57 @@
+// Launch-sequence builders shared by the forward, batched and reverse passes.
+#pragma once
+
+#include <initializer_list>
+
+#include "common.hpp"
+
+namespace sc {
+
+struct Target {
+  void* p;
+  int64_t ld;
+  int lim;
+  bool f64;
+};
+
+struct Modes {
+  Arith poly, sq;
+  bool poly_f64, sq_f64, user_f64;
+  int tile;
+  int64_t np;
+};
+
+struct Layout {
+  size_t norm_off, ap_off, w_off[9], q_off[4], total;
+};
+
+struct Run {
+  const Modes* m;
+  int64_t n;
+  const void* Ap;
+  void* W[9];
+  Target Cout, Sout;   // where the scheme's C and S go (squaring input or user buffers)
+  hipStream_t stream;
+  int launched;
+};
+
+Problem make_problem(int nvalid);
+void add_seg(Problem& p, const void* L, const void* R, int64_t ld, double lsc = 1.0, double rsc = 1.0);
+void add_in(Problem& p, const void* m, int64_t ld);
+void add_out(Problem& p, const Target& t, double e, double d, std::initializer_list<double> c);
+GemmLaunch one(const Problem& p, int np);
+GemmLaunch two(const Problem& p0, const Problem& p1, int np);
+bool modes_for(int64_t n, int dtype, int prod, Modes& m);
+Layout layout_for(const Modes& m);
+sincosm_status read_plan(const sincosm_plan* dev, sincosm_plan* host, hipStream_t stream);
+bool overlaps(const void* a, int64_t lda, const void* b, int64_t ldb, int64_t n, size_t es);
+Target internal(void* p, const Modes& m, bool f64);
+sincosm_status gemm(Run& r, Arith ar, const GemmLaunch& g, int kind = -1);
+sincosm_status scheme3(Run& r, double sx);
+sincosm_status scheme4(Run& r, double sx);
+sincosm_status scheme6(Run& r, double sx);
+sincosm_status scheme7(Run& r, double sx);
+sincosm_status run_scheme(Run& r, int level, double sx);
+sincosm_status double_angle(Run& r, const void* Sc, const void* Cc, const Target& Cn, const Target& Sn);
+
+}  // namespace sc

@@ -112,24 +112,33 @@ sincosm_status sincosm_eval(int64_t n, int dtype, const void* A, int64_t lda,
                             int acc, int prod, void* ws, size_t ws_bytes,
                             sincosm_plan* plan_host, void* stream);
 
-/* Bytes of workspace sincosm_eval_batched needs for `batch` matrices whose
- * orders are n_host[0..batch-1] (host array). */
+/* Batched evaluation of many independent matrices of uneven orders
+ * (1 <= n <= 256), packed row-major with leading dimension n at element
+ * offsets offset_host[i] (the same offsets for A, C and S). Two calls:
+ *
+ * sincosm_batched_prepare - once per batch shape: copies the orders, the
+ *   offsets and a longest-first processing order into the workspace (host ->
+ *   device copies, then a stream synchronisation). Host arrays are read only
+ *   during the call.
+ * sincosm_eval_batched    - cos and sin of every matrix, each with its own
+ *   plan (as sincosm_eval would choose it). It enqueues a fixed sequence of
+ *   two launches (queue reset, persistent kernel) whose shape depends only on
+ *   the prepared batch, so it can be captured in a HIP graph and replayed
+ *   with new values in A. A matrix with Inf/NaN gets NaN outputs and status
+ *   SINCOSM_E_NONFINITE in its plan; the call still returns SINCOSM_OK.
+ *
+ * ws: sincosm_batched_workspace_size(...) bytes, 256-byte aligned, prepared
+ * for exactly this batch; its size does not grow with the batch beyond the
+ * 16 bytes of metadata per matrix (each resident workgroup owns one slot of
+ * 10 padded matrices). dtype F64 or F32 with prod NATIVE. plans_dev:
+ * optional device array of `batch` sincosm_plan.
+ * Calls that overlap on one workspace race. */
 size_t sincosm_batched_workspace_size(int64_t batch, const int32_t* n_host, int dtype,
                                       int acc, int prod);
-
-/* cos and sin of `batch` independent matrices of uneven orders in one call.
- *  n_host / offset_host: host arrays of the orders (1 <= n <= 256) and the
- *  element offsets of each matrix inside A, C and S (row-major, leading
- *  dimension n, the same offsets for A, C and S).
- *  A, C, S: device base pointers of type dtype (F64 or F32; prod NATIVE only).
- *  plans_dev: optional device array of `batch` sincosm_plan, one per matrix.
- *  Each matrix gets its own plan (as sincosm_eval would choose). The call
- *  enqueues a fixed sequence of launches whose shape depends only on the
- *  orders, so it can be captured in a HIP graph and replayed with new values
- *  in A. A matrix with Inf/NaN gets NaN outputs and status SINCOSM_E_NONFINITE
- *  in its plan; the call itself still returns SINCOSM_OK. */
-sincosm_status sincosm_eval_batched(int64_t batch, int dtype, const int32_t* n_host,
-                                    const int64_t* offset_host, const void* A, void* C, void* S,
+sincosm_status sincosm_batched_prepare(int64_t batch, const int32_t* n_host,
+                                       const int64_t* offset_host, int dtype, void* ws,
+                                       size_t ws_bytes, void* stream);
+sincosm_status sincosm_eval_batched(int64_t batch, int dtype, const void* A, void* C, void* S,
                                     int acc, int prod, void* ws, size_t ws_bytes,
                                     sincosm_plan* plans_dev, void* stream);
 

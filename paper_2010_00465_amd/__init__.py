@@ -125,22 +125,54 @@ def sincosm_backward(A: torch.Tensor, Gc: torch.Tensor | None, Gs: torch.Tensor 
     return plan
 
 
+PLAN_BYTES = ctypes.sizeof(Plan)
+
+
+class BatchedWorkspace:
+    """A workspace prepared for one packed batch (C-ABI sincosm_batched_prepare).
+
+    ``run`` calls sincosm_eval_batched; it enqueues a fixed launch sequence, so
+    it may be captured in a CUDA/HIP graph once the workspace is prepared.
+    """
+
+    def __init__(self, ns, offsets, dtype=torch.float64, device="cuda", accuracy="double"):
+        self.batch = len(ns)
+        self.dtype = dtype
+        self.accuracy = accuracy
+        dt = _lib.F64 if dtype == torch.float64 else _lib.F32
+        n_arr = (ctypes.c_int32 * self.batch)(*[int(v) for v in ns])
+        o_arr = (ctypes.c_int64 * self.batch)(*[int(v) for v in offsets])
+        size = lib.sincosm_batched_workspace_size(self.batch, n_arr, dt, ACC[accuracy], PROD["native"])
+        if size == 0:
+            raise SincosmError(_lib.E_ARG, "sincosm_batched_workspace_size")
+        self.ws = _workspace(size, device)
+        stream = torch.cuda.current_stream(self.ws.device).cuda_stream
+        check(lib.sincosm_batched_prepare(self.batch, n_arr, o_arr, dt, self.ws.data_ptr(), self.ws.numel(),
+                                          stream), "sincosm_batched_prepare")
+
+    def run(self, A: torch.Tensor, C: torch.Tensor, S: torch.Tensor, plans: torch.Tensor | None = None):
+        _require_cuda(A, C, S)
+        plans_ptr = plans.data_ptr() if plans is not None else None
+        check(lib.sincosm_eval_batched(self.batch, _dtype_code(A), A.data_ptr(), C.data_ptr(), S.data_ptr(),
+                                       ACC[self.accuracy], PROD["native"], self.ws.data_ptr(), self.ws.numel(),
+                                       plans_ptr, _stream(A)), "sincosm_eval_batched")
+
+
+def plans_from_bytes(buf: torch.Tensor):
+    """Decode a device uint8 tensor of sincosm_plan records into Plan objects."""
+    raw = bytes(buf.cpu().numpy().tobytes())
+    return [Plan.from_buffer_copy(raw[i:i + PLAN_BYTES]) for i in range(0, len(raw), PLAN_BYTES)]
+
+
 def sincosm_eval_batched(ns, offsets, A: torch.Tensor, C: torch.Tensor, S: torch.Tensor,
-                         accuracy: str = "double", products: str = "native", ws: torch.Tensor | None = None,
-                         plans: torch.Tensor | None = None) -> None:
-    """C-ABI sincosm_eval_batched on a packed batch (ns, offsets: host int sequences)."""
-    _require_cuda(A, C, S)
-    dt = _dtype_code(A)
-    batch = len(ns)
-    n_arr = (ctypes.c_int32 * batch)(*[int(v) for v in ns])
-    o_arr = (ctypes.c_int64 * batch)(*[int(v) for v in offsets])
-    if ws is None:
-        ws = _workspace(lib.sincosm_batched_workspace_size(batch, n_arr, dt, ACC[accuracy], PROD[products]),
-                        A.device)
-    plans_ptr = plans.data_ptr() if plans is not None else None
-    check(lib.sincosm_eval_batched(batch, dt, n_arr, o_arr, A.data_ptr(), C.data_ptr(), S.data_ptr(),
-                                   ACC[accuracy], PROD[products], ws.data_ptr(), ws.numel(), plans_ptr,
-                                   _stream(A)), "sincosm_eval_batched")
+                         accuracy: str = "double", products: str = "native",
+                         plans: torch.Tensor | None = None) -> BatchedWorkspace:
+    """Prepare a workspace for the packed batch (ns, offsets: host int sequences) and run it once."""
+    if products != "native":
+        raise SincosmError(_lib.E_UNSUPPORTED, "sincosm_eval_batched")
+    w = BatchedWorkspace(ns, offsets, A.dtype, A.device, accuracy)
+    w.run(A, C, S, plans)
+    return w
 
 
 class _SinCosM(torch.autograd.Function):

@@ -1,0 +1,603 @@
+// Batched path: cos and sin of many independent matrices of uneven order
+// (n <= 256) in one persistent launch.
+//
+// Each workgroup repeatedly takes the next matrix from a device work queue
+// (longest first), and runs that matrix's whole method alone: zero-padded
+// copy and 1-norm, plan (Tables 1-2), the scheme's products (Section 2.1) and
+// the s double-angle steps (Section 1), each product as a loop over 64 x 64
+// output tiles of the workgroup. Matrices never share a workgroup, so there
+// is no synchronisation between workgroups; each resident workgroup owns one
+// arena slot of 10 padded matrices, so the workspace does not grow with the
+// batch. The stage descriptors of the four schemes are recorded once from the
+// same builders the single-matrix path launches (schemes.cpp), with symbolic
+// buffer ids resolved per matrix on the device.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
+#include "schemes.hpp"
+
+namespace sc {
+namespace {
+
+constexpr int BT = 64;        // output tile of the per-workgroup product loop
+constexpr int BBK = 16;       // k step
+constexpr int BNT = 256;      // threads (4 waves, 2 x 2 of 32 x 32)
+constexpr int WG_PER_CU = 4;  // resident workgroups per CU the arena is sized for
+constexpr int NMAX = 256;     // largest order of the batched path
+
+// symbolic buffer ids of the recorded templates
+constexpr int ID_AP = 0;      // 1..9: W0..W8
+constexpr int ID_COUT = 10;
+constexpr int ID_SOUT = 11;
+constexpr double SX_SENTINEL = 3.0;   // marks operand scales equal to 2^-s
+
+__device__ Problem g_tmpl[4][8];
+__device__ int g_tmpl_count[4];
+
+// Per-level (C0, S0) slots when s > 0, and the second ping-pong pair.
+// level index: 0 -> 3 products, 1 -> 4, 2 -> 6, 3 -> 7.
+__host__ __device__ inline void squaring_slots(int li, int& c0, int& s0, int& c1, int& s1) {
+  switch (li) {
+    case 0: c0 = 1 + 2; s0 = 1 + 0; c1 = 1 + 4; s1 = 1 + 3; break;   // C W2, S W0 | W4, W3
+    case 1: c0 = 1 + 5; s0 = 1 + 0; c1 = 1 + 2; s1 = 1 + 1; break;   // C W5, S W0 | W2, W1
+    case 2: c0 = 1 + 1; s0 = 1 + 0; c1 = 1 + 3; s1 = 1 + 2; break;   // C W1, S W0 | W3, W2
+    default: c0 = 1 + 8; s0 = 1 + 0; c1 = 1 + 2; s1 = 1 + 1; break;  // C W8, S W0 | W2, W1
+  }
+}
+
+__host__ __device__ inline int level_index(int level) { return level == 3 ? 0 : level == 4 ? 1 : level == 6 ? 2 : 3; }
+
+struct BatchArgs {
+  int batch;
+  int acc;
+  const int32_t* nmat;
+  const int64_t* off;
+  const int32_t* order;
+  const void* A;
+  void* C;
+  void* S;
+  sincosm_plan* plans;
+  char* arena;
+  int64_t slot_bytes;
+  unsigned int* counter;
+};
+
+template <typename T>
+struct Vec;
+template <>
+struct Vec<double> {
+  typedef double __attribute__((ext_vector_type(2))) t;
+  static constexpr int N = 2;
+};
+template <>
+struct Vec<float> {
+  typedef float __attribute__((ext_vector_type(4))) t;
+  static constexpr int N = 4;
+};
+
+template <typename T>
+__device__ inline typename Vec<T>::t mma_step(T a, T b, typename Vec<T>::t c);
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct BMma;
+template <>
+struct BMma<double> {
+  typedef v4d acc_t;
+  __device__ static inline acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row_in_block(int lg, int r) { return lg + 4 * r; }
+};
+template <>
+struct BMma<float> {
+  typedef v4f acc_t;
+  __device__ static inline acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row_in_block(int lg, int r) { return 4 * lg + r; }
+};
+
+template <typename T>
+struct Smem {
+  static constexpr int VEC = Vec<T>::N;
+  static constexpr int LDA = BBK + 1, LDB = BT + 16, LDE = BT + VEC;
+  static constexpr int STAGE = 2 * (BT * LDA + BBK * LDB);
+  static constexpr int EPI = (BT / 2) * LDE;
+  static constexpr int ELEMS = STAGE > EPI ? STAGE : EPI;
+};
+
+// One product of the current problem P (in LDS) over the whole np x np matrix,
+// by this workgroup alone: tiles of 64 x 64, operands staged through LDS with
+// rows/columns beyond np read as zero, MFMA blocks beyond np skipped.
+template <typename T>
+__device__ void wg_gemm(const Problem& P, int np, T* smem) {
+  using M = BMma<T>;
+  using acc_t = typename M::acc_t;
+  using vec_t = typename Vec<T>::t;
+  constexpr int VEC = Vec<T>::N;
+  constexpr int LDA = Smem<T>::LDA, LDB = Smem<T>::LDB, LDE = Smem<T>::LDE;
+  constexpr int A_LOADS = BT * BBK / VEC / BNT;
+  constexpr int B_LOADS = BBK * BT / VEC / BNT;
+  static_assert(A_LOADS >= 1 && B_LOADS >= 1, "staging");
+  T* const As0 = smem;
+  T* const Bs0 = smem + 2 * BT * LDA;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int nseg = P.nseg, nin = P.nin, nout = P.nout, nvalid = P.nvalid;
+  const int nk = np / BBK, nkt = nseg * nk;
+  const int tiles = (np + BT - 1) / BT;
+
+  for (int tm = 0; tm < tiles; ++tm) {
+    for (int tn = 0; tn < tiles; ++tn) {
+      acc_t acc[2][2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[i][j][r] = (T)0;
+      vec_t ra[A_LOADS], rb[B_LOADS];
+      auto gload = [&](int kt) {
+        const int sidx = kt / nk;
+        const int k0 = (kt - sidx * nk) * BBK;
+        const T* L = (const T*)P.seg[sidx].L;
+        const T* R = (const T*)P.seg[sidx].R;
+#pragma unroll
+        for (int i = 0; i < A_LOADS; ++i) {
+          const int e = (i * BNT + tid) * VEC;
+          const int r = e / BBK, c = e - r * BBK;
+          const int gr = tm * BT + r;
+          if (gr < np) ra[i] = *(const vec_t*)(L + (int64_t)gr * np + k0 + c);
+          else ra[i] = (vec_t)0;
+        }
+#pragma unroll
+        for (int i = 0; i < B_LOADS; ++i) {
+          const int e = (i * BNT + tid) * VEC;
+          const int r = e / BT, c = e - r * BT;
+          const int gc = tn * BT + c;
+          if (gc < np) rb[i] = *(const vec_t*)(R + (int64_t)(k0 + r) * np + gc);
+          else rb[i] = (vec_t)0;
+        }
+      };
+      auto lstore = [&](int buf, int kt) {
+        const Seg& S = P.seg[kt / nk];
+        const T ls = (T)S.lscale, rs = (T)S.rscale;
+        T* as = As0 + buf * (BT * LDA);
+        T* bs = Bs0 + buf * (BBK * LDB);
+#pragma unroll
+        for (int i = 0; i < A_LOADS; ++i) {
+          const int e = (i * BNT + tid) * VEC;
+          const int r = e / BBK, c = e - r * BBK;
+#pragma unroll
+          for (int q = 0; q < VEC; ++q) as[r * LDA + c + q] = ra[i][q] * ls;
+        }
+#pragma unroll
+        for (int i = 0; i < B_LOADS; ++i) {
+          const int e = (i * BNT + tid) * VEC;
+          const int r = e / BT, c = e - r * BT;
+          *(vec_t*)(bs + r * LDB + c) = rb[i] * rs;
+        }
+      };
+      const bool rowok0 = tm * BT + wm * 32 < np, rowok1 = tm * BT + wm * 32 + 16 < np;
+      const bool colok0 = tn * BT + wn * 32 < np, colok1 = tn * BT + wn * 32 + 16 < np;
+      if (nkt > 0) {
+        gload(0);
+        lstore(0, 0);
+      }
+      __syncthreads();
+      for (int kt = 0; kt < nkt; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nkt) gload(kt + 1);
+        if (rowok0 && colok0) {  // wave-uniform: this wave has at least one live block
+          const T* as = As0 + cur * (BT * LDA) + (wm * 32 + lr) * LDA + lg;
+          const T* bs = Bs0 + cur * (BBK * LDB) + lg * LDB + wn * 32 + lr;
+#pragma unroll
+          for (int kk = 0; kk < BBK / 4; ++kk) {
+            const T a0 = as[kk * 4], a1 = as[16 * LDA + kk * 4];
+            const T b0 = bs[kk * 4 * LDB], b1 = bs[kk * 4 * LDB + 16];
+            acc[0][0] = M::mma(a0, b0, acc[0][0]);
+            if (colok1) acc[0][1] = M::mma(a0, b1, acc[0][1]);
+            if (rowok1) acc[1][0] = M::mma(a1, b0, acc[1][0]);
+            if (rowok1 && colok1) acc[1][1] = M::mma(a1, b1, acc[1][1]);
+          }
+        }
+        if (kt + 1 < nkt) lstore(cur ^ 1, kt + 1);
+        __syncthreads();
+      }
+      // epilogue: two bands of 32 rows staged through LDS, then coalesced
+      T* const E = smem;
+      for (int band = 0; band < 2; ++band) {
+        if (wm == band) {
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+              for (int r = 0; r < 4; ++r)
+                E[(i * 16 + M::row_in_block(lg, r)) * LDE + wn * 32 + j * 16 + lr] = acc[i][j][r];
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int e = tid * VEC; e < 32 * BT; e += BNT * VEC) {
+          const int br = e / BT, bc = e - br * BT;
+          const int row = tm * BT + band * 32 + br;
+          const int col = tn * BT + bc;
+          if (row >= np || col >= np) continue;
+          const vec_t v = *(const vec_t*)(E + br * LDE + bc);
+          vec_t x[MAX_IN];
+#pragma unroll
+          for (int q = 0; q < MAX_IN; ++q)
+            if (q < nin) x[q] = *(const vec_t*)((const T*)P.in[q].p + (int64_t)row * np + col);
+          // outputs one at a time (coefficients re-read from LDS): keeps the
+          // register footprint small, the inputs stay in registers
+#pragma unroll 1
+          for (int o = 0; o < nout; ++o) {
+            const EpiOut& O = P.out[o];
+            vec_t val;
+#pragma unroll
+            for (int t = 0; t < VEC; ++t) {
+              T y = (row == col + t && row < nvalid) ? (T)O.d : (T)0;
+              y = __builtin_fma((T)O.e, v[t], y);
+#pragma unroll
+              for (int q = 0; q < MAX_IN; ++q)
+                if (q < nin) y = __builtin_fma((T)O.c[q], x[q][t], y);
+              val[t] = y;
+            }
+            const int64_t off = (int64_t)row * O.ld + col;
+            if (O.lim == np && O.ld == np && (((uintptr_t)O.p) & 15u) == 0) {
+              *(vec_t*)((T*)O.p + off) = val;
+            } else if (row < O.lim) {
+#pragma unroll
+              for (int t = 0; t < VEC; ++t)
+                if (col + t < O.lim) ((T*)O.p)[off + t] = val[t];
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
+template <typename T>
+__device__ inline void* resolve(const void* sym, T* slot, int np) {
+  const intptr_t id = (intptr_t)sym - 1;
+  return slot + (int64_t)id * np * np;
+}
+
+template <typename T>
+__global__ __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(3))) void batched_kernel(BatchArgs a) {
+  __shared__ __attribute__((aligned(16))) T smem[Smem<T>::ELEMS];
+  __shared__ Problem prob;
+  __shared__ unsigned long long red[BNT];
+  __shared__ int s_item;
+  __shared__ sincosm_plan s_plan;
+  const int tid = threadIdx.x;
+  T* const slot = (T*)(a.arena + (int64_t)blockIdx.x * a.slot_bytes);
+
+  for (;;) {
+    if (tid == 0) s_item = (int)atomicAdd(a.counter, 1u);
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();
+    if (item >= a.batch) break;
+    const int i = a.order[item];
+    const int n = a.nmat[i];
+    const int64_t off = a.off[i];
+    const int np = (n + 15) & ~15;
+    const T* Ai = (const T*)a.A + off;
+    T* Ci = (T*)a.C + off;
+    T* Si = (T*)a.S + off;
+    T* Ap = slot;
+
+    // zero-padded copy and column sums (each thread one column, rows in order)
+    for (int c = tid; c < np; c += BNT) {
+      double sum = 0.0;
+      for (int r = 0; r < np; ++r) {
+        const double v = (r < n && c < n) ? (double)Ai[(int64_t)r * n + c] : 0.0;
+        Ap[(int64_t)r * np + c] = (T)v;
+        sum += fabs(v);
+      }
+      red[c] = (unsigned long long)__double_as_longlong(sum);
+    }
+    for (int c = np + tid; c < BNT; c += BNT) red[c] = 0ull;
+    __syncthreads();
+    if (tid == 0) {
+      unsigned long long mx = 0ull;
+      for (int c = 0; c < np; ++c) mx = red[c] > mx ? red[c] : mx;
+      sincosm_plan p;
+      plan_rule(__longlong_as_double((long long)mx), a.acc, &p);
+      s_plan = p;
+      if (a.plans) a.plans[i] = p;
+    }
+    __syncthreads();
+    const sincosm_plan plan = s_plan;
+    if (plan.status != SINCOSM_OK) {
+      const T nanv = (T)__longlong_as_double(0x7ff8000000000000ll);
+      for (int e = tid; e < n * n; e += BNT) { Ci[e] = nanv; Si[e] = nanv; }
+      __syncthreads();
+      continue;
+    }
+    const int li = level_index(plan.level);
+    const int s = plan.s;
+    const double sx = ldexp(1.0, -s);
+    int c0, s0, c1, s1;
+    squaring_slots(li, c0, s0, c1, s1);
+
+    const int nst = g_tmpl_count[li];
+    for (int t = 0; t < nst; ++t) {
+      {  // cooperative word copy of the template into LDS
+        const unsigned long long* src = (const unsigned long long*)&g_tmpl[li][t];
+        unsigned long long* dst = (unsigned long long*)&prob;
+        for (int w = tid; w < (int)(sizeof(Problem) / 8); w += BNT) dst[w] = src[w];
+      }
+      __syncthreads();
+      if (tid == 0) {
+        prob.nvalid = n;
+        for (int q = 0; q < prob.nseg; ++q) {
+          Seg& g = prob.seg[q];
+          g.L = resolve<T>(g.L, slot, np);
+          g.R = resolve<T>(g.R, slot, np);
+          g.ldl = g.ldr = np;
+          if (g.lscale == SX_SENTINEL) g.lscale = sx;
+          if (g.rscale == SX_SENTINEL) g.rscale = sx;
+        }
+        for (int q = 0; q < prob.nin; ++q) {
+          prob.in[q].p = resolve<T>(prob.in[q].p, slot, np);
+          prob.in[q].ld = np;
+        }
+        for (int q = 0; q < prob.nout; ++q) {
+          EpiOut& o = prob.out[q];
+          const intptr_t id = (intptr_t)o.p - 1;
+          if (id == ID_COUT || id == ID_SOUT) {
+            if (s == 0) {
+              o.p = id == ID_COUT ? (void*)Ci : (void*)Si;
+              o.ld = n;
+              o.lim = n;
+            } else {
+              o.p = slot + (int64_t)(id == ID_COUT ? c0 : s0) * np * np;
+              o.ld = np;
+              o.lim = np;
+            }
+          } else {
+            o.p = resolve<T>(o.p, slot, np);
+            o.ld = np;
+            o.lim = np;
+          }
+          o.f64 = sizeof(T) == 8;
+        }
+      }
+      __syncthreads();
+      wg_gemm<T>(prob, np, smem);
+    }
+    // s double-angle steps from (S, C) to (S', C'), ping-pong between the two
+    // slot pairs; the last step writes the caller's matrices.
+    for (int j = 0; j < s; ++j) {
+      const bool last = j == s - 1;
+      T* Sc = slot + (int64_t)((j & 1) ? s1 : s0) * np * np;
+      T* Cc = slot + (int64_t)((j & 1) ? c1 : c0) * np * np;
+      T* Sn = last ? Si : slot + (int64_t)((j & 1) ? s0 : s1) * np * np;
+      T* Cn = last ? Ci : slot + (int64_t)((j & 1) ? c0 : c1) * np * np;
+      for (int half = 0; half < 2; ++half) {
+        {
+          unsigned long long* dst = (unsigned long long*)&prob;
+          for (int w = tid; w < (int)(sizeof(Problem) / 8); w += BNT) dst[w] = 0ull;
+        }
+        __syncthreads();
+        if (tid == 0) {
+          prob.nvalid = n;
+          prob.nseg = 1;
+          prob.seg[0].L = Sc;
+          prob.seg[0].R = half == 0 ? Sc : Cc;
+          prob.seg[0].ldl = prob.seg[0].ldr = np;
+          prob.seg[0].lscale = prob.seg[0].rscale = 1.0;
+          prob.nout = 1;
+          EpiOut& o = prob.out[0];
+          o.p = half == 0 ? Cn : Sn;
+          o.ld = last ? n : np;
+          o.lim = last ? n : np;
+          o.f64 = sizeof(T) == 8;
+          o.e = half == 0 ? -2.0 : 2.0;
+          o.d = half == 0 ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        wg_gemm<T>(prob, np, smem);
+      }
+    }
+  }
+}
+
+__global__ void reset_counter_kernel(unsigned int* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
+}
+
+// Templates are recorded once per process and copied to each device on first use.
+std::mutex tmpl_mu;
+bool tmpl_built = false;
+Problem tmpl_host[4][8];
+int tmpl_count_host[4];
+std::map<int, bool> tmpl_uploaded;
+
+sincosm_status build_templates() {
+  if (tmpl_built) return SINCOSM_OK;
+  memset(tmpl_host, 0, sizeof(tmpl_host));
+  const int levels[4] = {3, 4, 6, 7};
+  for (int li = 0; li < 4; ++li) {
+    Modes m;
+    memset(&m, 0, sizeof(m));
+    m.poly = Arith::F64;
+    m.sq = Arith::F64;
+    m.poly_f64 = m.sq_f64 = m.user_f64 = true;
+    m.np = 16;   // placeholder, resolved per matrix
+    Recorder rec;
+    Run r;
+    r.m = &m;
+    r.n = 16;
+    r.Ap = (void*)(intptr_t)(ID_AP + 1);
+    for (int k = 0; k < 9; ++k) r.W[k] = (void*)(intptr_t)(k + 2);
+    r.Cout = Target{(void*)(intptr_t)(ID_COUT + 1), 16, 16, true};
+    r.Sout = Target{(void*)(intptr_t)(ID_SOUT + 1), 16, 16, true};
+    r.stream = nullptr;
+    r.launched = 0;
+    r.rec = &rec;
+    SC_TRY(run_scheme(r, levels[li], SX_SENTINEL));
+    for (int t = 0; t < rec.count; ++t) {
+      if (rec.launches[t].nprob != 1) return SINCOSM_E_ARG;
+      tmpl_host[li][t] = rec.launches[t].prob[0];
+    }
+    tmpl_count_host[li] = rec.count;
+  }
+  tmpl_built = true;
+  return SINCOSM_OK;
+}
+
+sincosm_status ensure_templates(hipStream_t stream) {
+  std::lock_guard<std::mutex> g(tmpl_mu);
+  SC_TRY(build_templates());
+  int dev = 0;
+  SC_HIP(hipGetDevice(&dev));
+  if (tmpl_uploaded[dev]) return SINCOSM_OK;
+  SC_HIP(hipMemcpyToSymbolAsync(HIP_SYMBOL(g_tmpl), tmpl_host, sizeof(tmpl_host), 0, hipMemcpyHostToDevice,
+                                stream));
+  SC_HIP(hipMemcpyToSymbolAsync(HIP_SYMBOL(g_tmpl_count), tmpl_count_host, sizeof(tmpl_count_host), 0,
+                                hipMemcpyHostToDevice, stream));
+  SC_HIP(hipStreamSynchronize(stream));
+  tmpl_uploaded[dev] = true;
+  return SINCOSM_OK;
+}
+
+struct BatchLayout {
+  size_t counter_off, n_off, off_off, order_off, arena_off, slot_bytes, total;
+  int slots;
+};
+
+int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  return cus;
+}
+
+bool batch_layout(int64_t batch, int nmax, int dtype, BatchLayout& L) {
+  const int cus = device_cus();
+  if (cus <= 0) return false;
+  const size_t es = dtype == SINCOSM_F64 ? 8 : 4;
+  const int npm = (nmax + 15) & ~15;
+  L.slots = (int)std::min<int64_t>(batch, (int64_t)cus * WG_PER_CU);
+  L.slot_bytes = align_up((size_t)10 * npm * npm * es, 256);
+  size_t off = 0;
+  L.counter_off = off; off += 256;
+  L.n_off = off; off += align_up((size_t)batch * 4, 256);
+  L.off_off = off; off += align_up((size_t)batch * 8, 256);
+  L.order_off = off; off += align_up((size_t)batch * 4, 256);
+  L.arena_off = off; off += (size_t)L.slots * L.slot_bytes;
+  L.total = off;
+  return true;
+}
+
+// Host-side record of each prepared workspace (for argument checks).
+struct Prepared { int64_t batch; int dtype; BatchLayout L; };
+std::mutex prep_mu;
+std::map<const void*, Prepared> prepared;
+
+}  // namespace
+}  // namespace sc
+
+using namespace sc;
+
+extern "C" {
+
+size_t sincosm_batched_workspace_size(int64_t batch, const int32_t* n_host, int dtype, int acc, int prod) {
+  (void)acc;
+  if (batch <= 0 || !n_host || (dtype != SINCOSM_F64 && dtype != SINCOSM_F32) || prod != SINCOSM_PROD_NATIVE)
+    return 0;
+  int nmax = 1;
+  for (int64_t i = 0; i < batch; ++i) {
+    if (n_host[i] < 1 || n_host[i] > NMAX) return 0;
+    nmax = std::max<int>(nmax, n_host[i]);
+  }
+  BatchLayout L;
+  if (!batch_layout(batch, nmax, dtype, L)) return 0;
+  return L.total;
+}
+
+sincosm_status sincosm_batched_prepare(int64_t batch, const int32_t* n_host, const int64_t* offset_host, int dtype,
+                                       void* ws, size_t ws_bytes, void* stream_) {
+  if (batch <= 0 || !n_host || !offset_host) return SINCOSM_E_ARG;
+  if (dtype != SINCOSM_F64 && dtype != SINCOSM_F32) return SINCOSM_E_ARG;
+  int nmax = 1;
+  for (int64_t i = 0; i < batch; ++i) {
+    if (n_host[i] < 1 || n_host[i] > NMAX || offset_host[i] < 0) return SINCOSM_E_ARG;
+    nmax = std::max<int>(nmax, n_host[i]);
+  }
+  BatchLayout L;
+  if (!batch_layout(batch, nmax, dtype, L)) return SINCOSM_E_HIP;
+  if (!ws || ws_bytes < L.total || ((uintptr_t)ws & 255u)) return SINCOSM_E_WORKSPACE;
+  hipStream_t stream = (hipStream_t)stream_;
+  SC_TRY(ensure_templates(stream));
+  // longest first: order by n descending, stable
+  std::vector<int32_t> order((size_t)batch);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return n_host[x] > n_host[y]; });
+  char* base = (char*)ws;
+  SC_HIP(hipMemcpyAsync(base + L.n_off, n_host, (size_t)batch * 4, hipMemcpyHostToDevice, stream));
+  SC_HIP(hipMemcpyAsync(base + L.off_off, offset_host, (size_t)batch * 8, hipMemcpyHostToDevice, stream));
+  SC_HIP(hipMemcpyAsync(base + L.order_off, order.data(), (size_t)batch * 4, hipMemcpyHostToDevice, stream));
+  SC_HIP(hipStreamSynchronize(stream));
+  std::lock_guard<std::mutex> g(prep_mu);
+  prepared[ws] = Prepared{batch, dtype, L};
+  return SINCOSM_OK;
+}
+
+sincosm_status sincosm_eval_batched(int64_t batch, int dtype, const void* A, void* C, void* S, int acc, int prod,
+                                    void* ws, size_t ws_bytes, sincosm_plan* plans_dev, void* stream_) {
+  if (batch < 0) return SINCOSM_E_ARG;
+  if (batch == 0) return SINCOSM_OK;
+  if (acc != SINCOSM_ACC_DOUBLE && acc != SINCOSM_ACC_SINGLE) return SINCOSM_E_ARG;
+  if (dtype != SINCOSM_F64 && dtype != SINCOSM_F32) return SINCOSM_E_ARG;
+  if (prod != SINCOSM_PROD_NATIVE) return SINCOSM_E_UNSUPPORTED;
+  if (!A || !C || !S) return SINCOSM_E_ARG;
+  Prepared pr;
+  {
+    std::lock_guard<std::mutex> g(prep_mu);
+    auto it = prepared.find(ws);
+    if (it == prepared.end()) return SINCOSM_E_WORKSPACE;
+    pr = it->second;
+  }
+  if (pr.batch != batch || pr.dtype != dtype || ws_bytes < pr.L.total) return SINCOSM_E_WORKSPACE;
+  hipStream_t stream = (hipStream_t)stream_;
+  char* base = (char*)ws;
+  BatchArgs a;
+  a.batch = (int)batch;
+  a.acc = acc;
+  a.nmat = (const int32_t*)(base + pr.L.n_off);
+  a.off = (const int64_t*)(base + pr.L.off_off);
+  a.order = (const int32_t*)(base + pr.L.order_off);
+  a.A = A;
+  a.C = C;
+  a.S = S;
+  a.plans = plans_dev;
+  a.arena = base + pr.L.arena_off;
+  a.slot_bytes = (int64_t)pr.L.slot_bytes;
+  a.counter = (unsigned int*)(base + pr.L.counter_off);
+  const TimingMark t = timing_begin(SINCOSM_TIMING_BATCHED, stream);
+  reset_counter_kernel<<<1, 64, 0, stream>>>(a.counter);
+  if (dtype == SINCOSM_F64) batched_kernel<double><<<pr.L.slots, BNT, 0, stream>>>(a);
+  else batched_kernel<float><<<pr.L.slots, BNT, 0, stream>>>(a);
+  timing_end(t, stream);
+  SC_HIP(hipGetLastError());
+  return SINCOSM_OK;
+}
+
+}  // extern "C"

@@ -161,6 +161,11 @@ Target internal(void* p, const Modes& m, bool f64) { return Target{p, m.np, (int
 
 sincosm_status gemm(Run& r, Arith ar, const GemmLaunch& g, int kind) {
   r.launched += g.nprob;
+  if (r.rec) {
+    if (r.rec->count >= 8) return SINCOSM_E_ARG;
+    r.rec->launches[r.rec->count++] = g;
+    return SINCOSM_OK;
+  }
   if (kind < 0) kind = g.nprob == 2 ? SINCOSM_TIMING_SQUARING : SINCOSM_TIMING_SCHEME;
   const TimingMark t = timing_begin(kind, r.stream);
   const sincosm_status st = launch_gemm(ar, r.m->tile, g, r.stream);

@@ -25,6 +25,8 @@ struct Layout {
   size_t norm_off, ap_off, w_off[9], q_off[4], total;
 };
 
+struct Recorder;   // captures launches instead of enqueuing them (batched templates)
+
 struct Run {
   const Modes* m;
   int64_t n;
@@ -33,6 +35,14 @@ struct Run {
   Target Cout, Sout;   // where the scheme's C and S go (squaring input or user buffers)
   hipStream_t stream;
   int launched;
+  Recorder* rec = nullptr;
+};
+
+// Launch capture used to build the batched path's stage templates from the
+// same scheme builders: buffers are symbolic ids encoded as small pointers.
+struct Recorder {
+  GemmLaunch launches[8];
+  int count = 0;
 };
 
 Problem make_problem(int nvalid);

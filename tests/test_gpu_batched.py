@@ -1,0 +1,180 @@
+"""GPU parity of the batched path (sincosm_batched_prepare + sincosm_eval_batched
+through the C ABI) against the CPU oracle.
+
+Bars as for the single-matrix path: relative Frobenius error <= 1e-12 per
+matrix (float64, double accuracy), plan integers equal to the oracle's
+(breakpoint neighbours accepted). Bitwise equality with the single-matrix
+path is not expected (different tiles, different rounding order): parity
+unpinned, checked at 1e-13."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import plan as P
+from oracle import reference as R
+from tests.conftest import rel_fro
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2010_00465_amd as sc
+    return torch, sc
+
+
+def pack(mats):
+    ns = [m.shape[0] for m in mats]
+    offs = np.zeros(len(ns), dtype=np.int64)
+    if ns:
+        offs[1:] = np.cumsum([n * n for n in ns[:-1]])
+    flat = np.concatenate([m.ravel() for m in mats]) if mats else np.zeros(0)
+    return ns, offs, flat
+
+
+def run_batch(env, mats, accuracy="double", dtype=None):
+    torch, sc = env
+    ns, offs, flat = pack(mats)
+    A = torch.from_numpy(flat).cuda()
+    if dtype is not None:
+        A = A.to(dtype)
+    C = torch.empty_like(A)
+    S = torch.empty_like(A)
+    plans = torch.zeros(len(ns) * sc.PLAN_BYTES, dtype=torch.uint8, device="cuda")
+    sc.sincosm_eval_batched(ns, offs, A, C, S, accuracy=accuracy, plans=plans)
+    torch.cuda.synchronize()
+    Cs = C.cpu().double().numpy()
+    Ss = S.cpu().double().numpy()
+    out = [(Cs[o:o + n * n].reshape(n, n), Ss[o:o + n * n].reshape(n, n)) for n, o in zip(ns, offs)]
+    return out, sc.plans_from_bytes(plans)
+
+
+def plan_ok(p, A, acc="double"):
+    t = float(np.abs(A).sum(0).max())
+    got = (p.level, p.s, p.products)
+    return any(got == P.plan(t * f, acc) for f in (1.0, 1 - 1e-12, 1 + 1e-12))
+
+
+MIXED_SIZES = [1, 2, 3, 8, 13, 16, 17, 31, 33, 64, 65, 100, 129, 200, 255, 256]
+MIXED_EXPS = [-9.0, -5.0, -1.0, 0.5, 1.0, 3.0, 6.0, 8.0]
+
+
+def test_batched_mixed_vs_oracle(env):
+    mats = []
+    for i, n in enumerate(MIXED_SIZES):
+        for j, e in enumerate(MIXED_EXPS):
+            fam = ("gaussian", "symmetric", "laplacian1d")[(i + j) % 3]
+            mats.append(W.family(fam, n, 2.0 ** e, key=(80, n, j)))
+    out, plans = run_batch(env, mats)
+    levels = set()
+    for A, (C, S), p in zip(mats, out, plans):
+        assert p.status == 0
+        assert plan_ok(p, A), (A.shape, p)
+        levels.add(p.level)
+        Cr, Sr = R.sincosm(A)
+        assert rel_fro(C, Cr) <= 1e-12, (A.shape, p)
+        assert rel_fro(S, Sr) <= 1e-12, (A.shape, p)
+    assert levels == {3, 4, 6, 7}
+
+
+def test_batched_matches_single_path(env):
+    torch, sc = env
+    mats = [W.gaussian(n, 2.0 ** e, key=(81, n)) for n, e in [(40, 2.0), (130, 5.0), (256, 7.0), (77, -3.0)]]
+    out, _ = run_batch(env, mats)
+    for A, (C, S) in zip(mats, out):
+        At = torch.from_numpy(A).cuda()
+        C1 = torch.empty_like(At)
+        S1 = torch.empty_like(At)
+        sc.sincosm_eval(At, C1, S1)
+        assert rel_fro(C, C1.cpu().numpy()) <= 1e-13
+        assert rel_fro(S, S1.cpu().numpy()) <= 1e-13
+
+
+def test_batched_nonfinite_isolated(env):
+    mats = [W.gaussian(20, 3.0, key=(82, i)) for i in range(5)]
+    mats[2] = mats[2].copy()
+    mats[2][4, 5] = np.inf
+    out, plans = run_batch(env, mats)
+    for i, (A, (C, S), p) in enumerate(zip(mats, out, plans)):
+        if i == 2:
+            assert p.status == -4 and np.isnan(C).all() and np.isnan(S).all()
+        else:
+            Cr, Sr = R.sincosm(A)
+            assert p.status == 0 and rel_fro(C, Cr) <= 1e-12 and rel_fro(S, Sr) <= 1e-12
+
+
+def test_batched_float32_single(env):
+    torch, _ = env
+    mats = [W.gaussian(n, 2.0 ** e, key=(83, n)).astype(np.float32).astype(np.float64)
+            for n, e in [(16, 0.0), (64, 3.0), (150, 5.0), (256, 6.0)]]
+    out, plans = run_batch(env, mats, accuracy="single", dtype=torch.float32)
+    for A, (C, S), p in zip(mats, out, plans):
+        assert plan_ok(p, A, "single")
+        Cr, Sr = R.sincosm(A)
+        tol = 5e-6 * max(1, 2 ** p.s / 16)
+        assert rel_fro(C, Cr) <= tol and rel_fro(S, Sr) <= tol
+
+
+def test_batched_deterministic(env):
+    mats = [W.gaussian(n, 9.0, key=(84, n)) for n in (5, 60, 190)]
+    a, _ = run_batch(env, mats)
+    b, _ = run_batch(env, mats)
+    for (C1, S1), (C2, S2) in zip(a, b):
+        assert np.array_equal(C1, C2) and np.array_equal(S1, S2)
+
+
+def test_batched_graph_replay(env):
+    """Capture sincosm_eval_batched in a graph, replay with new inputs, compare to eager runs."""
+    torch, sc = env
+    sizes = [12, 48, 96, 200]
+    sets = [[W.gaussian(n, 2.0 ** (k + 1), key=(85, n, k)) for n in sizes] for k in range(3)]
+    ns, offs, flat0 = pack(sets[0])
+    A = torch.from_numpy(flat0).cuda()
+    C = torch.empty_like(A)
+    S = torch.empty_like(A)
+    w = sc.BatchedWorkspace(ns, offs, A.dtype, A.device)
+    w.run(A, C, S)          # warm-up outside capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        w.run(A, C, S)
+    for k in range(3):
+        A.copy_(torch.from_numpy(pack(sets[k])[2]).cuda())
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        Cg, Sg = C.clone(), S.clone()
+        w.run(A, C, S)        # eager, same inputs
+        torch.cuda.synchronize()
+        assert torch.equal(Cg, C) and torch.equal(Sg, S)
+        for n, o, Am in zip(ns, offs, sets[k]):
+            Cr, Sr = R.sincosm(Am)
+            assert rel_fro(Cg[o:o + n * n].view(n, n).cpu().numpy(), Cr) <= 1e-12
+
+
+def test_batched_config_full(env):
+    """20,000 matrices, n uniform on {8, ..., 256}, ||A||_1 = 2^U(-6, 8): sampled oracle parity."""
+    torch, sc = env
+    ns, offs, packed, norms = W.batched_gaussian(20000, key=(3,))
+    A = torch.from_numpy(packed).cuda()
+    C = torch.empty_like(A)
+    S = torch.empty_like(A)
+    plans = torch.zeros(len(ns) * sc.PLAN_BYTES, dtype=torch.uint8, device="cuda")
+    sc.sincosm_eval_batched(ns, offs, A, C, S, plans=plans)
+    torch.cuda.synchronize()
+    pl = sc.plans_from_bytes(plans)
+    assert all(p.status == 0 for p in pl)
+    idx = np.random.default_rng(86).choice(len(ns), size=40, replace=False)
+    idx = np.concatenate([idx, [int(np.argmax(ns)), int(np.argmax(norms))]])
+    Cc = C.cpu().numpy()
+    Sc = S.cpu().numpy()
+    for i in idx:
+        n, o = int(ns[i]), int(offs[i])
+        Am = packed[o:o + n * n].reshape(n, n)
+        assert plan_ok(pl[i], Am)
+        Cr, Sr = R.sincosm(Am)
+        assert rel_fro(Cc[o:o + n * n].reshape(n, n), Cr) <= 1e-12
+        assert rel_fro(Sc[o:o + n * n].reshape(n, n), Sr) <= 1e-12

@@ -121,6 +121,7 @@ sincosm_status launch_gemm(Arith ar, int tile, const GemmLaunch& g, hipStream_t 
 int tile_size(int tile);
 int choose_tile(Arith ar, int64_t n);
 bool bf16x3_available();
+sincosm_status launch_gemm_bf16x3(int tile, const GemmLaunch& g, hipStream_t stream);
 
 // ----------------------------------------------------------------------------
 // Norm / copy / plan / fill kernels (norm_plan.hip)

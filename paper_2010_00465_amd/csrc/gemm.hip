@@ -23,6 +23,7 @@
 //    the index is first remapped to give each XCD a contiguous range of tiles,
 //    then walked in groups of 8 tile rows to keep operand panels in L2.
 #include "common.hpp"
+#include "epilogue.hpp"
 
 namespace sc {
 
@@ -200,64 +201,7 @@ void gemm_kernel(const GemmLaunch g) {
     __syncthreads();
   }
 
-  // Epilogue, one band of WTM rows at a time: the waves of band wm write their
-  // accumulators to LDS (MFMA layout: lane (lg, lr), register r -> column lr,
-  // row M::row_in_block(lg, r) of each 16 x 16 block), then all threads read
-  // the band back in row-major order, VEC consecutive columns per thread, so
-  // every global access of the epilogue is a coalesced 16-byte access.
-  const int nin = P.nin, nout = P.nout, nvalid = P.nvalid;
-  T* const E = smem;
-  for (int band = 0; band < WGM; ++band) {
-    if (wm == band) {
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            E[(i * 16 + M::row_in_block(lg, r)) * LDE + wn * WTN + j * 16 + lr] = acc[i][j][r];
-    }
-    __syncthreads();
-    for (int e = tid * VEC; e < WTM * BN; e += NT * VEC) {
-      const int br = e / BN, bc = e - br * BN;
-      const int row = tile_m * BM + band * WTM + br;
-      const int col = tile_n * BN + bc;
-      const vec_t v = *(const vec_t*)(E + br * LDE + bc);
-      vec_t x[MAX_IN];
-#pragma unroll
-      for (int q = 0; q < MAX_IN; ++q)
-        if (q < nin) x[q] = *(const vec_t*)((const T*)P.in[q].p + (int64_t)row * np + col);
-#pragma unroll
-      for (int o = 0; o < MAX_OUT; ++o) {
-        if (o >= nout) break;
-        const EpiOut& O = P.out[o];
-        vec_t val;
-#pragma unroll
-        for (int t = 0; t < VEC; ++t) {
-          T y = (row == col + t && row < nvalid) ? (T)O.d : (T)0;
-          y = __builtin_fma((T)O.e, v[t], y);
-#pragma unroll
-          for (int q = 0; q < MAX_IN; ++q)
-            if (q < nin) y = __builtin_fma((T)O.c[q], x[q][t], y);
-          val[t] = y;
-        }
-        const int64_t off = (int64_t)row * O.ld + col;
-        const bool internal = O.lim == np && O.ld == np && (O.f64 != 0) == (sizeof(T) == 8);
-        if (internal) {
-          *(vec_t*)((T*)O.p + off) = val;
-        } else if (row < O.lim) {
-#pragma unroll
-          for (int t = 0; t < VEC; ++t) {
-            if (col + t < O.lim) {
-              if (O.f64) ((double*)O.p)[off + t] = (double)val[t];
-              else ((T*)O.p)[off + t] = val[t];
-            }
-          }
-        }
-      }
-    }
-    __syncthreads();
-  }
+  epilogue_bands<T, BM, BN, WGM, WGN, M>(P, np, tile_m, tile_n, acc, smem);
 }
 
 // ----------------------------------------------------------------------------
@@ -306,11 +250,8 @@ sincosm_status launch_gemm(Arith ar, int tile, const GemmLaunch& g, hipStream_t 
       default: return launch_cfg<float, 32, 32, 32, 2, 2, 2>(g, stream);
     }
   }
+  if (ar == Arith::BF16X3) return launch_gemm_bf16x3(tile, g, stream);
   return SINCOSM_E_UNSUPPORTED;
 }
 
-}  // namespace sc
-
-namespace sc {
-bool bf16x3_available() { return false; }
 }  // namespace sc

@@ -309,3 +309,55 @@ def test_tier_f32_products(env, n, e):
     assert plan_ok(plan, A, "single")
     Cr, Sr = R.sincosm(A)
     assert rel_fro(C, Cr) <= 5e-6 and rel_fro(S, Sr) <= 5e-6
+
+
+# ---------------------------------------------------------------------------
+# Split BF16 x3 products (precision tier)
+# ---------------------------------------------------------------------------
+U_BF = 2.0 ** -18   # |x - (hi + lo)| <= 2^-9 |lo| <= 2^-18 |x| ; dropped lo*lo ~ 2^-18 |x||y|
+
+
+@pytest.mark.parametrize("n", [16, 100, 300, 1000, 1600])
+def test_matmul_bf16x3(env, n):
+    """Elementwise bound |Z - XY| <= (4 * 2^-18 + 2 n 2^-24) (|X||Y|)_ij: split error of both
+    operands, the dropped lo*lo term, and float32 accumulation."""
+    torch, sc = env
+    g = W.rng(53, n)
+    X = g.standard_normal((n, n)).astype(np.float32)
+    Y = g.standard_normal((n, n)).astype(np.float32)
+    Xt, Yt = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    Z = torch.empty_like(Xt)
+    sc.sincosm_matmul(Xt, Yt, Z, products="bf16x3")
+    torch.cuda.synchronize()
+    Xd, Yd = X.astype(np.float64), Y.astype(np.float64)
+    err = np.max(np.abs(Z.cpu().double().numpy() - Xd @ Yd) / (np.abs(Xd) @ np.abs(Yd)))
+    assert err <= 4 * U_BF + 2 * n * 2.0 ** -24, err
+
+
+@pytest.mark.parametrize("n,e", [(64, 1.0), (300, 4.0), (1000, 6.0), (2100, 6.0)])
+def test_tier_bf16x3_products(env, n, e):
+    """float64 storage, bf16x3 scheme products, float64 squarings, single-accuracy plan.
+
+    Stated bound: each of the Pi scheme products carries a relative error of a few 2^-18
+    (test_matmul_bf16x3), the float32 intermediates 2^-24, and the s double-angle steps
+    amplify an error of the scheme's output by at most about 2^s relative to cos/sin of
+    norm-1 arguments: rel err <= 8 Pi 2^-18 2^s (checked with Pi = 7)."""
+    torch, sc = env
+    print("[case] eval tier bf16x3", n, e, flush=True)
+    A = W.gaussian(n, 2.0 ** e, key=(54, n))
+    C, S, plan = run(env, A, accuracy="single", products="bf16x3")
+    assert plan_ok(plan, A, "single")
+    Cr, Sr = R.sincosm(A)
+    tol = 8 * 7 * U_BF * 2 ** plan.s
+    ec, es = rel_fro(C, Cr), rel_fro(S, Sr)
+    print(f"bf16x3 n={n} e={e} plan=({plan.level},{plan.s}) rel err cos {ec:.2e} sin {es:.2e} tol {tol:.1e}")
+    assert ec <= tol and es <= tol
+
+
+def test_tier_bf16x3_float32_storage(env):
+    torch, sc = env
+    A32 = W.gaussian(200, 8.0, key=(55,)).astype(np.float32)
+    C, S, plan = run(env, A32, accuracy="single", products="bf16x3", dtype=torch.float32)
+    Cr, Sr = R.sincosm(A32.astype(np.float64))
+    tol = 8 * 7 * U_BF * 2 ** plan.s
+    assert rel_fro(C, Cr) <= tol and rel_fro(S, Sr) <= tol

@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=N)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched, backward and precision-tier measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run sincosm_matmul once at --n: its two pad/convert copy kernels read and "
                          "write n*n float64 each, a known byte count for scaling HBM counters")
@@ -95,6 +97,95 @@ def measured_traffic():
         return float(vals["traffic_bytes_per_launch (double-angle step)"])
     except (KeyError, ValueError):
         return None
+
+
+def _elapsed(torch, fn, reps):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def bench_batched(torch, sc, W):
+    """20,000 matrices, n uniform on {8,...,256}, ||A||_1 = 2^U(-6,8), float64, double accuracy;
+    against a loop of single-matrix calls over the first 400 matrices of the same batch."""
+    ns, offs, packed, _ = W.batched_gaussian(20000, key=(3,))
+    A = torch.from_numpy(packed).cuda()
+    C = torch.empty_like(A)
+    S = torch.empty_like(A)
+    plans = torch.zeros(len(ns) * sc.PLAN_BYTES, dtype=torch.uint8, device="cuda")
+    w = sc.BatchedWorkspace(ns, offs, A.dtype, A.device)
+    w.run(A, C, S, plans)
+    pl = sc.plans_from_bytes(plans)
+    flops = float(sum(p.products * 2.0 * int(n) ** 3 for p, n in zip(pl, ns)))
+    t = _elapsed(torch, lambda: w.run(A, C, S, plans), 3)
+    # per-matrix loop on a prefix of the same batch
+    k = 400
+    mats = [A[int(o):int(o) + int(n) * int(n)].view(int(n), int(n)) for n, o in zip(ns[:k], offs[:k])]
+    outs = [(torch.empty_like(m), torch.empty_like(m)) for m in mats]
+    wsz = max(sc.workspace_size(int(n), torch.float64) for n in ns[:k])
+    ws = torch.empty(wsz, dtype=torch.uint8, device="cuda")
+
+    def loop():
+        for m, (c, s_) in zip(mats, outs):
+            sc.sincosm_eval(m, c, s_, ws=ws)
+
+    loop()
+    t_loop = _elapsed(torch, loop, 1)
+    loop_flops = float(sum(p.products * 2.0 * int(n) ** 3 for p, n in zip(pl[:k], ns[:k])))
+    return {"workload": "20000 float64 Gaussian matrices, n uniform on {8,...,256}, ||A||_1 = 2^U(-6,8), "
+                        "double-accuracy plans, one sincosm_eval_batched call",
+            "ms_per_batch": 1e3 * t, "evals_per_s": len(ns) / t, "tflops_algorithmic": flops / t / 1e12,
+            "mean_products": float(np.mean([p.products for p in pl])),
+            "loop_of_sincosm_eval": {"matrices": k, "evals_per_s": k / t_loop,
+                                     "tflops_algorithmic": loop_flops / t_loop / 1e12},
+            "speedup_vs_loop": (len(ns) / t) / (k / t_loop)}
+
+
+def bench_backward(torch, sc, W):
+    """Gradient of <Gc, cos A> + <Gs, sin A>, n = 2048 Gaussian, ||A||_1 = 128 (float64)."""
+    n = 2048
+    A = torch.from_numpy(W.gaussian(n, 128.0, key=(4, n, 256))).cuda()
+    g = W.rng(64, n, 256)
+    Gc = torch.from_numpy(g.standard_normal((n, n))).cuda()
+    Gs = torch.from_numpy(g.standard_normal((n, n))).cuda()
+    gA = torch.empty_like(A)
+    plan = sc.plan_device(A)
+    ws = torch.empty(sc.lib.sincosm_backward_workspace_size(n, 0, 0, plan.s), dtype=torch.uint8, device="cuda")
+    sc.sincosm_backward(A, Gc, Gs, gA, s=plan.s, ws=ws)
+    t = _elapsed(torch, lambda: sc.sincosm_backward(A, Gc, Gs, gA, s=plan.s, ws=ws), 3)
+    prods = 3 * plan.level + 6 * plan.s - 2
+    return {"workload": f"sincosm_backward, n={n} Gaussian, ||A||_1=128, plan (level {plan.level}, s {plan.s})",
+            "ms": 1e3 * t, "products": prods, "tflops_algorithmic": prods * 2.0 * n ** 3 / t / 1e12,
+            "forward_products": plan.products}
+
+
+def bench_tiers(torch, sc, W):
+    """n = 4096: 2-D 5-point Laplacian on a 64 x 64 grid scaled to ||A||_1 = 64; each product
+    arithmetic with its plan table: time, and relative error against the all-float64
+    double-accuracy path (itself held to 1e-12 of the CPU oracle by the parity tests)."""
+    Anp = W.laplacian_2d(64, 64.0)
+    A = torch.from_numpy(Anp).cuda()
+    Cref = torch.empty_like(A)
+    Sref = torch.empty_like(A)
+    sc.sincosm_eval(A, Cref, Sref, "double", "native")
+    Cr, Sr = Cref.cpu().numpy(), Sref.cpu().numpy()
+    out = {"workload": "n=4096 2-D Laplacian (64 x 64 grid), ||A||_1 = 64, float64 storage; errors relative "
+                       "to the float64 double-accuracy result"}
+    for name, acc, prod in (("fp64_double", "double", "native"), ("fp64_single_plan", "single", "native"),
+                            ("fp32_products", "single", "f32"), ("bf16x3_products", "single", "bf16x3")):
+        C = torch.empty_like(A)
+        S = torch.empty_like(A)
+        ws = torch.empty(sc.workspace_size(4096, torch.float64, acc, prod), dtype=torch.uint8, device="cuda")
+        plan = sc.sincosm_eval(A, C, S, acc, prod, ws=ws)
+        t = _elapsed(torch, lambda: sc.sincosm_eval(A, C, S, acc, prod, ws=ws), 3)
+        ec = float(np.linalg.norm(C.cpu().numpy() - Cr) / np.linalg.norm(Cr))
+        es = float(np.linalg.norm(S.cpu().numpy() - Sr) / np.linalg.norm(Sr))
+        out[name] = {"ms": 1e3 * t, "plan": [plan.level, plan.s], "products": plan.products,
+                     "rel_err_cos": ec, "rel_err_sin": es}
+    return out
 
 
 def main():
@@ -174,6 +265,12 @@ def main():
                "sample": f"one whole step (the four n={n} anchor matrices once each) through the float64 "
                          f"oracle on the host, {secs:.1f} s"}
 
+    extras = {}
+    if not args.no_extras and n == N:
+        extras["batched"] = bench_batched(torch, sc, W)
+        extras["backward"] = bench_backward(torch, sc, W)
+        extras["tiers"] = bench_tiers(torch, sc, W)
+
     out = {
         "metric": "cos+sin evals/sec & % MFMA peak at n=4096 FP64; rel err vs FP64 oracle",
         "value": value,
@@ -204,6 +301,7 @@ def main():
         "rel_err": rel,
         "cpu_baseline": cpu,
     }
+    out.update(extras)
     print(json.dumps(out))
 
 

@@ -183,6 +183,20 @@ enum { SINCOSM_TIMING_SCHEME = 0, SINCOSM_TIMING_SQUARING = 1, SINCOSM_TIMING_BA
 sincosm_status sincosm_timing_enable(int on);
 sincosm_status sincosm_timing_read(int kind, double* total_ms, int64_t* count);
 
+/* Autotuning of the product kernel. `arith` is 0 for float64 products, 1 for
+ * float32 products. Each arithmetic offers a list of kernel configurations
+ * (tile rows, tile columns, k depth, wave rows, wave columns, waves per SIMD
+ * -> info[0..5]); entries 0, 1 and 2 are the defaults for padding
+ * granularities 128, 64 and 32. sincosm_tune_set makes launches of that
+ * arithmetic whose padded order lies in [np_lo, np_hi] use configuration idx
+ * (later entries win; idx = -1 removes the overlapping entries); a
+ * configuration whose tile does not divide the padded order is ignored for it.
+ * Host-side state shared by all devices, thread-safe; results do not depend
+ * on it beyond rounding order. */
+int sincosm_tune_num_configs(int arith);
+sincosm_status sincosm_tune_config_info(int arith, int idx, int32_t* info);
+sincosm_status sincosm_tune_set(int arith, int64_t np_lo, int64_t np_hi, int idx);
+
 #ifdef __cplusplus
 }
 #endif

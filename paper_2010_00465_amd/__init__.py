@@ -19,6 +19,10 @@ import torch
 
 from . import _lib
 from ._lib import ACC, PROD, Plan, SincosmError, check, lib
+from . import autotune as _autotune
+
+# kernel configurations measured by the autotuner on the target (JSON cache)
+TUNED_ENTRIES = _autotune.apply_cache()
 
 __all__ = ["sincosm", "sincosm_eval", "sincosm_eval_batched", "sincosm_backward", "sincosm_matmul",
            "plan_host", "plan_device", "workspace_size", "Plan", "SincosmError", "sincosm_batched"]

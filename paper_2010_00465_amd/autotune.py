@@ -1,0 +1,127 @@
+"""Autotuner for the product kernel's configuration (tile shape, k depth,
+wave grid, occupancy) per arithmetic and padded matrix order.
+
+For each arithmetic and each probe order n it times every configuration the
+library offers whose tile divides the padded order (C-ABI
+``sincosm_tune_num_configs`` / ``sincosm_tune_config_info``), by forcing it
+with ``sincosm_tune_set`` and timing ``sincosm_matmul`` with HIP events. The
+fastest configuration per probe is written to a JSON cache with the range of
+padded orders it covers (midpoints between probes). ``apply_cache`` installs a
+cache in the library; the package calls it at import for the cache shipped
+next to this file (``tune_gfx950.json``) or the file named by
+``SINCOSM_TUNE_CACHE``.
+
+Usage on the GPU:  python -m paper_2010_00465_amd.autotune --out paper_2010_00465_amd/tune_gfx950.json
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import time
+
+from ._lib import lib
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_CACHE = os.path.join(HERE, "tune_gfx950.json")
+ARITH = {"f64": 0, "f32": 1}
+PROBES = (256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096, 6144, 8192)
+
+
+def padded(n: int) -> int:
+    g = 128 if n >= 1536 else (64 if n >= 256 else 32)
+    return (n + g - 1) // g * g
+
+
+def configs(arith: str):
+    out = []
+    for i in range(lib.sincosm_tune_num_configs(ARITH[arith])):
+        info = (ctypes.c_int32 * 6)()
+        lib.sincosm_tune_config_info(ARITH[arith], i, info)
+        out.append({"idx": i, "bm": info[0], "bn": info[1], "bk": info[2], "wgm": info[3], "wgn": info[4],
+                    "wpe": info[5]})
+    return out
+
+
+def apply_cache(path: str | None = None) -> int:
+    """Install the entries of a tuning cache; returns how many were applied."""
+    path = path or os.environ.get("SINCOSM_TUNE_CACHE") or DEFAULT_CACHE
+    if not os.path.exists(path):
+        return 0
+    with open(path) as f:
+        data = json.load(f)
+    count = 0
+    for arith, entries in data.get("entries", {}).items():
+        if arith not in ARITH:
+            continue
+        for e in entries:
+            if lib.sincosm_tune_set(ARITH[arith], int(e["np_lo"]), int(e["np_hi"]), int(e["idx"])) == 0:
+                count += 1
+    return count
+
+
+def time_config(torch, sc, arith: str, n: int, idx: int, reps: int) -> float:
+    np_ = padded(n)
+    lib.sincosm_tune_set(ARITH[arith], np_, np_, idx)
+    dt = torch.float64 if arith == "f64" else torch.float32
+    X = torch.randn(n, n, dtype=dt, device="cuda")
+    Y = torch.randn(n, n, dtype=dt, device="cuda")
+    Z = torch.empty_like(X)
+    ws = torch.empty(lib.sincosm_matmul_workspace_size(n, ARITH[arith], 0), dtype=torch.uint8, device="cuda")
+    sc.sincosm_matmul(X, Y, Z, ws=ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        sc.sincosm_matmul(X, Y, Z, ws=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    lib.sincosm_tune_set(ARITH[arith], np_, np_, -1)
+    return e0.elapsed_time(e1) / reps
+
+
+def tune(ariths=("f64", "f32"), probes=PROBES, reps=5, log=print):
+    import torch
+    import paper_2010_00465_amd as sc
+    result = {"device": torch.cuda.get_device_name(0), "created": time.strftime("%Y-%m-%d %H:%M:%S"),
+              "configs": {a: configs(a) for a in ariths}, "entries": {}, "timings": {}}
+    for arith in ariths:
+        entries, timings = [], {}
+        nps = sorted({padded(n) for n in probes})
+        for k, np_ in enumerate(nps):
+            best = None
+            timings[str(np_)] = {}
+            for c in configs(arith):
+                if np_ % c["bm"] or np_ % c["bn"]:
+                    continue
+                ms = time_config(torch, sc, arith, np_, c["idx"], reps)
+                timings[str(np_)][str(c["idx"])] = ms
+                if best is None or ms < best[1]:
+                    best = (c["idx"], ms)
+            lo = 1 if k == 0 else (nps[k - 1] + np_) // 2 + 1
+            hi = 1 << 30 if k == len(nps) - 1 else (np_ + nps[k + 1]) // 2
+            flops = 2.0 * np_ ** 3
+            entries.append({"np_lo": lo, "np_hi": hi, "idx": best[0], "probe_np": np_, "ms": best[1],
+                            "tflops": flops / (best[1] * 1e-3) / 1e12})
+            log(f"{arith} np={np_}: best config {best[0]} {best[1]:.3f} ms "
+                f"({flops / (best[1] * 1e-3) / 1e12:.1f} TFLOP/s incl. padding copies)")
+        result["entries"][arith] = entries
+        result["timings"][arith] = timings
+    return result
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=DEFAULT_CACHE)
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--arith", default="f64,f32")
+    args = ap.parse_args()
+    res = tune(tuple(args.arith.split(",")), reps=args.reps, log=lambda s: print(s, flush=True))
+    with open(args.out, "w") as f:
+        json.dump(res, f, indent=1)
+    print(f"wrote {args.out}")
+
+
+if __name__ == "__main__":
+    main()

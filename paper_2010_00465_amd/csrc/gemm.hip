@@ -25,6 +25,9 @@
 #include "common.hpp"
 #include "epilogue.hpp"
 
+#include <mutex>
+#include <vector>
+
 namespace sc {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -234,24 +237,102 @@ static sincosm_status launch_cfg(const GemmLaunch& g, hipStream_t stream) {
   return SINCOSM_OK;
 }
 
+// ----------------------------------------------------------------------------
+// Kernel configurations the autotuner chooses among. Each entry: tile rows and
+// columns, k depth, wave grid, waves per SIMD. Entries 0, 1, 2 are the
+// defaults for the three padding granularities 128, 64 and 32.
+// ----------------------------------------------------------------------------
+typedef sincosm_status (*LaunchFn)(const GemmLaunch&, hipStream_t);
+struct KernelCfg {
+  int bm, bn, bk, wgm, wgn, wpe;
+  LaunchFn fn;
+};
+
+#define SC_CFG(T, BM, BN, BK, WGM, WGN, WPE) \
+  { BM, BN, BK, WGM, WGN, WPE, &launch_cfg<T, BM, BN, BK, WGM, WGN, WPE> }
+
+static const KernelCfg kF64[] = {
+    SC_CFG(double, 128, 128, 16, 2, 2, 2), SC_CFG(double, 64, 64, 16, 2, 2, 2),
+    SC_CFG(double, 32, 32, 16, 2, 2, 2),   SC_CFG(double, 128, 128, 32, 2, 2, 1),
+    SC_CFG(double, 256, 128, 16, 4, 2, 2), SC_CFG(double, 128, 128, 16, 2, 4, 2),
+    SC_CFG(double, 128, 64, 16, 2, 2, 2),  SC_CFG(double, 64, 128, 16, 2, 2, 2),
+    SC_CFG(double, 128, 128, 8, 2, 2, 2),
+};
+static const KernelCfg kF32[] = {
+    SC_CFG(float, 128, 128, 16, 2, 2, 2), SC_CFG(float, 64, 64, 16, 2, 2, 2),
+    SC_CFG(float, 32, 32, 32, 2, 2, 2),   SC_CFG(float, 128, 128, 32, 2, 2, 2),
+    SC_CFG(float, 256, 128, 16, 4, 2, 2), SC_CFG(float, 128, 128, 16, 2, 4, 2),
+    SC_CFG(float, 64, 64, 32, 2, 2, 2),
+};
+
+static const KernelCfg* cfg_table(Arith ar, int& count) {
+  if (ar == Arith::F64) { count = (int)(sizeof(kF64) / sizeof(kF64[0])); return kF64; }
+  if (ar == Arith::F32) { count = (int)(sizeof(kF32) / sizeof(kF32[0])); return kF32; }
+  count = 0;
+  return nullptr;
+}
+
+// Tuning table: for (arith, padded order in [lo, hi]) use configuration idx.
+struct TuneEntry { int ar; int64_t lo, hi; int idx; };
+static std::mutex tune_mu;
+static std::vector<TuneEntry> tune_table;
+
+static int tuned_cfg(Arith ar, int64_t np) {
+  std::lock_guard<std::mutex> g(tune_mu);
+  for (auto it = tune_table.rbegin(); it != tune_table.rend(); ++it)
+    if (it->ar == (int)ar && np >= it->lo && np <= it->hi) return it->idx;
+  return -1;
+}
+
 sincosm_status launch_gemm(Arith ar, int tile, const GemmLaunch& g, hipStream_t stream) {
   if (g.np % tile_size(tile) != 0) return SINCOSM_E_ARG;
-  if (ar == Arith::F64) {
-    switch (tile) {
-      case 0: return launch_cfg<double, 128, 128, 16, 2, 2, 2>(g, stream);
-      case 1: return launch_cfg<double, 64, 64, 16, 2, 2, 2>(g, stream);
-      default: return launch_cfg<double, 32, 32, 16, 2, 2, 2>(g, stream);
-    }
-  }
-  if (ar == Arith::F32) {
-    switch (tile) {
-      case 0: return launch_cfg<float, 128, 128, 16, 2, 2, 2>(g, stream);
-      case 1: return launch_cfg<float, 64, 64, 16, 2, 2, 2>(g, stream);
-      default: return launch_cfg<float, 32, 32, 32, 2, 2, 2>(g, stream);
-    }
-  }
   if (ar == Arith::BF16X3) return launch_gemm_bf16x3(tile, g, stream);
-  return SINCOSM_E_UNSUPPORTED;
+  int count = 0;
+  const KernelCfg* t = cfg_table(ar, count);
+  if (!t) return SINCOSM_E_UNSUPPORTED;
+  int idx = tuned_cfg(ar, g.np);
+  if (idx < 0 || idx >= count || g.np % t[idx].bm != 0 || g.np % t[idx].bn != 0) idx = tile;
+  return t[idx].fn(g, stream);
 }
+
+}  // namespace sc
+
+extern "C" {
+
+int sincosm_tune_num_configs(int arith) {
+  int count = 0;
+  sc::cfg_table((sc::Arith)arith, count);
+  return count;
+}
+
+sincosm_status sincosm_tune_config_info(int arith, int idx, int32_t* info) {
+  int count = 0;
+  const sc::KernelCfg* t = sc::cfg_table((sc::Arith)arith, count);
+  if (!t || !info || idx < 0 || idx >= count) return SINCOSM_E_ARG;
+  info[0] = t[idx].bm; info[1] = t[idx].bn; info[2] = t[idx].bk;
+  info[3] = t[idx].wgm; info[4] = t[idx].wgn; info[5] = t[idx].wpe;
+  return SINCOSM_OK;
+}
+
+sincosm_status sincosm_tune_set(int arith, int64_t np_lo, int64_t np_hi, int idx) {
+  int count = 0;
+  sc::cfg_table((sc::Arith)arith, count);
+  if (count == 0 || np_lo > np_hi) return SINCOSM_E_ARG;
+  std::lock_guard<std::mutex> g(sc::tune_mu);
+  if (idx < 0) {   // clear entries of this arithmetic overlapping the range
+    std::vector<sc::TuneEntry> keep;
+    for (auto& e : sc::tune_table)
+      if (!(e.ar == arith && e.hi >= np_lo && e.lo <= np_hi)) keep.push_back(e);
+    sc::tune_table.swap(keep);
+    return SINCOSM_OK;
+  }
+  if (idx >= count) return SINCOSM_E_ARG;
+  sc::tune_table.push_back(sc::TuneEntry{arith, np_lo, np_hi, idx});
+  return SINCOSM_OK;
+}
+
+}  // extern "C"
+
+namespace sc {
 
 }  // namespace sc

@@ -290,8 +290,8 @@ def main():
                    "plans": [[p.level, p.s] for p in plans], "evals_per_step": len(ANCHORS)},
         "tflops_algorithmic": tflops,
         "pct_fp64_mfma_peak": 100.0 * tflops / FP64_MFMA_PEAK_TFLOPS,
-        "roofline": {"bound": "mfma", "kernel": "double-angle product launch (gemm_kernel<double,128,...>, "
-                                                "2 problems)",
+        "roofline": {"bound": "mfma", "kernel": "double-angle product launch (FP64 MFMA product kernel, "
+                                                "2 problems, configuration from the tuning cache)",
                      "achieved": sq_tflops, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": (sq_tflops / FP64_MFMA_PEAK_TFLOPS) if sq_tflops else None,
                      "traffic": measured_traffic(), "launches": sq_cnt,

@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched, backward and precision-tier measurements")
+    ap.add_argument("--only", choices=["batched", "backward", "tiers"],
+                    help="run and print only one of the secondary measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run sincosm_matmul once at --n: its two pad/convert copy kernels read and "
                          "write n*n float64 each, a known byte count for scaling HBM counters")
@@ -197,6 +199,13 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.n)
+        return
+    if args.only:
+        import torch
+        import paper_2010_00465_amd as sc
+        import workloads as W
+        fn = {"batched": bench_batched, "backward": bench_backward, "tiers": bench_tiers}[args.only]
+        print(json.dumps({args.only: fn(torch, sc, W)}))
         return
     import torch
     import paper_2010_00465_amd as sc

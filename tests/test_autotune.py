@@ -1,0 +1,66 @@
+"""Autotuner plumbing (no GPU): the configuration table, the tuning hooks of
+the C ABI, and the shipped cache file."""
+import ctypes
+import json
+import os
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2010_00465_amd import _lib
+    return _lib.lib
+
+
+def test_config_table(lib):
+    for arith in (0, 1):
+        n = lib.sincosm_tune_num_configs(arith)
+        assert n >= 3
+        info = (ctypes.c_int32 * 6)()
+        for i in range(n):
+            assert lib.sincosm_tune_config_info(arith, i, info) == 0
+            bm, bn, bk, wgm, wgn, wpe = list(info)
+            assert bm % (16 * wgm) == 0 and bn % (16 * wgn) == 0 and bk % 4 == 0 and wpe >= 1
+        # the three defaults are the square tiles of the padding granularities
+        sizes = []
+        for i in range(3):
+            lib.sincosm_tune_config_info(arith, i, info)
+            sizes.append((info[0], info[1]))
+        assert sizes == [(128, 128), (64, 64), (32, 32)]
+    assert lib.sincosm_tune_config_info(0, 999, info) == -1
+    assert lib.sincosm_tune_num_configs(7) == 0
+
+
+def test_tune_set_validation(lib):
+    assert lib.sincosm_tune_set(0, 100, 50, 0) == -1     # empty range
+    assert lib.sincosm_tune_set(0, 1, 10, 999) == -1     # unknown configuration
+    assert lib.sincosm_tune_set(9, 1, 10, 0) == -1       # unknown arithmetic
+    assert lib.sincosm_tune_set(0, 1 << 40, 1 << 41, 1) == 0
+    assert lib.sincosm_tune_set(0, 1 << 40, 1 << 41, -1) == 0
+
+
+def test_shipped_cache_is_consistent(lib):
+    from paper_2010_00465_amd import autotune
+    path = autotune.DEFAULT_CACHE
+    assert os.path.exists(path)
+    data = json.load(open(path))
+    for arith, entries in data["entries"].items():
+        n = lib.sincosm_tune_num_configs(autotune.ARITH[arith])
+        prev_hi = 0
+        for e in entries:
+            assert 0 <= e["idx"] < n
+            assert e["np_lo"] == prev_hi + 1 and e["np_hi"] >= e["np_lo"]
+            prev_hi = e["np_hi"]
+            info = data["configs"][arith][e["idx"]]
+            assert e["probe_np"] % info["bm"] == 0 and e["probe_np"] % info["bn"] == 0
+
+
+def test_padding_rule_matches_library(lib):
+    from paper_2010_00465_amd import autotune
+    lib.sincosm_matmul_workspace_size.restype = ctypes.c_size_t
+    for n in (1, 31, 200, 256, 1000, 1535, 1536, 4096, 4100):
+        np_ = autotune.padded(n)
+        assert lib.sincosm_matmul_workspace_size(n, 0, 0) == 2 * ((np_ * np_ * 8 + 255) // 256 * 256)

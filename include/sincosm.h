@@ -112,6 +112,36 @@ sincosm_status sincosm_eval(int64_t n, int dtype, const void* A, int64_t lda,
                             int acc, int prod, void* ws, size_t ws_bytes,
                             sincosm_plan* plan_host, void* stream);
 
+/* Plan of the wave-equation schemes for a given ||B||_1, B = t^2 A (host, pure).
+ * level in {2,3,4,5} (= products of the Section 2.2 scheme), s = number of
+ * double-angle steps (t halved s times, so B is quartered s times), products =
+ * level + 2 s, norm1 = ||B||_1. The bounds on ||B||_1 per scheme (the paper
+ * prints none for these schemes) are derived from the scheme polynomials as
+ * for Tables 1-2: double {3.4458e-3, 1.3213e-2, 9.6251e-1, 3.6404}, single
+ * {5.2237e-1, 7.354e-1, 8.9612, 21.848}. Same rule as sincosm_plan_host
+ * otherwise (least Pi + 2 s, ties to the smaller s; non-finite norm gives
+ * status SINCOSM_E_NONFINITE). Returns SINCOSM_E_ARG for a bad `acc`/null `out`. */
+sincosm_status sincosm_wave_plan_host(double normB, int acc, sincosm_plan* out);
+
+/* Wave-equation pair (Sections 1 and 2.2): for y'' + A y = 0,
+ *   C = c(t^2 A) = cos(t sqrt A) = sum_k (-1)^k (t^2 A)^k / (2k)!,
+ *   S = s(t, A)  = sin(t sqrt A) / sqrt A = t sum_k (-1)^k (t^2 A)^k / (2k+1)!,
+ * both entire in A, so no square root of A is formed and A may be any real
+ * matrix. The factorized schemes use B = t^2 A in place of A^2 and the
+ * scalar t in place of the sine's final factor A (2, 3, 4 or 5 products);
+ * the double-angle step is c(4 t^2 A) = 2 c(t^2 A)^2 - I, s(2t, A) =
+ * 2 s(t, A) c(t^2 A). The pair solves y(t) = C y(0) + S y'(0).
+ *  t: finite scalar (t = 0 gives C = I, S = 0; negative t negates S).
+ *  Buffers, dtype/prod combinations, workspace (sincosm_workspace_size(n,
+ *  dtype, acc, prod) bytes, 256-byte aligned), aliasing rules, plan_host and
+ *  errors as for sincosm_eval; *plan_host receives the wave plan (norm1 =
+ *  ||t^2 A||_1). Non-finite t is SINCOSM_E_ARG; t^2 A with Inf/NaN (including
+ *  overflow of t^2) gives SINCOSM_E_NONFINITE with C and S filled with NaN. */
+sincosm_status sincosm_wave_eval(int64_t n, int dtype, const void* A, int64_t lda, double t,
+                                 void* C, int64_t ldc, void* S, int64_t lds,
+                                 int acc, int prod, void* ws, size_t ws_bytes,
+                                 sincosm_plan* plan_host, void* stream);
+
 /* Batched evaluation of many independent matrices of uneven orders
  * (1 <= n <= 256), packed row-major with leading dimension n at element
  * offsets offset_host[i] (the same offsets for A, C and S). Two calls:

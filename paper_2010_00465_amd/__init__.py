@@ -25,7 +25,8 @@ from . import autotune as _autotune
 TUNED_ENTRIES = _autotune.apply_cache()
 
 __all__ = ["sincosm", "sincosm_eval", "sincosm_eval_batched", "sincosm_backward", "sincosm_matmul",
-           "plan_host", "plan_device", "workspace_size", "Plan", "SincosmError", "sincosm_batched"]
+           "plan_host", "plan_device", "workspace_size", "Plan", "SincosmError", "sincosm_batched",
+           "wave_plan_host", "sincosm_wave_eval", "wave"]
 
 
 def _dtype_code(t: torch.Tensor) -> int:
@@ -96,6 +97,42 @@ def sincosm_eval(A: torch.Tensor, C: torch.Tensor, S: torch.Tensor, accuracy: st
         return plan
     check(st, "sincosm_eval")
     return plan
+
+
+def wave_plan_host(normB: float, accuracy: str = "double") -> Plan:
+    """The library's wave plan for a given ||t^2 A||_1 (host computation, same rule as the device)."""
+    p = Plan()
+    check(lib.sincosm_wave_plan_host(float(normB), ACC[accuracy], ctypes.byref(p)), "sincosm_wave_plan_host")
+    return p
+
+
+def sincosm_wave_eval(A: torch.Tensor, t: float, C: torch.Tensor, S: torch.Tensor, accuracy: str = "double",
+                      products: str = "native", ws: torch.Tensor | None = None, raise_nonfinite=True) -> Plan:
+    """C-ABI sincosm_wave_eval: C = cos(t sqrt A), S = sin(t sqrt A)/sqrt A, in place. Returns the plan."""
+    _require_cuda(A, C, S)
+    n = A.shape[0]
+    dt = _dtype_code(A)
+    if ws is None:
+        ws = _workspace(workspace_size(n, A.dtype, accuracy, products), A.device)
+    plan = Plan()
+    st = lib.sincosm_wave_eval(n, dt, A.data_ptr(), _ld(A), float(t), C.data_ptr(), _ld(C), S.data_ptr(),
+                               _ld(S), ACC[accuracy], PROD[products], ws.data_ptr(), ws.numel(),
+                               ctypes.byref(plan), _stream(A))
+    if st == _lib.E_NONFINITE and not raise_nonfinite:
+        return plan
+    check(st, "sincosm_wave_eval")
+    return plan
+
+
+def wave(A: torch.Tensor, t: float, accuracy: str = "double", products: str = "native"):
+    """(c(t^2 A), s(t, A)) for a square float64/float32 GPU tensor: the propagator of y'' + A y = 0."""
+    if A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("square matrix expected")
+    A = A.contiguous()
+    C = torch.empty_like(A)
+    S = torch.empty_like(A)
+    sincosm_wave_eval(A, t, C, S, accuracy, products)
+    return C, S
 
 
 def sincosm_matmul(X: torch.Tensor, Y: torch.Tensor, Z: torch.Tensor, products: str = "native",

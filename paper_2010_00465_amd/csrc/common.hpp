@@ -61,6 +61,36 @@ __host__ __device__ inline void plan_rule(double norm1, int acc, sincosm_plan* p
   p->level = best_level; p->s = best_s; p->products = best_cost; p->status = SINCOSM_OK;
 }
 
+// Wave-equation functions c(t^2 A), s(t, A) (Section 2.2): schemes with 2, 3,
+// 4, 5 products in B = t^2 A; bounds on ||B||_1 derived from the scheme
+// polynomials as for Tables 1-2 (the cosine bound is the square of the cos
+// table's), rounded down to 5 digits. Halving t quarters B.
+__host__ __device__ inline double wave_theta(int acc, int idx) {
+  const double dbl[4] = {3.4458e-3, 1.3213e-2, 9.6251e-1, 3.6404};
+  const double sgl[4] = {5.2237e-1, 7.354e-1, 8.9612, 2.1848e1};
+  return acc == SINCOSM_ACC_SINGLE ? sgl[idx] : dbl[idx];
+}
+
+__host__ __device__ inline void plan_rule_wave(double normB, int acc, sincosm_plan* p) {
+  p->norm1 = normB;
+  if (!(normB >= 0.0 && normB <= 1.7976931348623157e308)) {
+    p->level = 0; p->s = 0; p->products = 0; p->status = SINCOSM_E_NONFINITE;
+    return;
+  }
+  int best_cost = 0x7fffffff, best_s = 0, best_level = 2;
+  for (int i = 0; i < 4; ++i) {
+    const double th = wave_theta(acc, i);
+    int s = 0;
+    double t = normB;
+    while (t > th) { t *= 0.25; ++s; }
+    const int cost = (2 + i) + 2 * s;
+    if (cost < best_cost || (cost == best_cost && s < best_s)) {
+      best_cost = cost; best_s = s; best_level = 2 + i;
+    }
+  }
+  p->level = best_level; p->s = best_s; p->products = best_cost; p->status = SINCOSM_OK;
+}
+
 // ----------------------------------------------------------------------------
 // GEMM-with-epilogue descriptors.
 //
@@ -135,11 +165,14 @@ struct NormScratch {
 size_t norm_scratch_bytes(int64_t np);
 NormScratch norm_scratch(void* base, int64_t np);
 
-// Column abs-sum partials of A (n x n, lda, type src_f64 ? double : float) and
-// a zero-padded copy Ap (np x np, type dst_f64 ? double : float); then plan.
+// Column abs-sum partials of pre * A (A n x n, lda, type src_f64 ? double : float,
+// each element multiplied by `pre` in float64) and the zero-padded copy
+// Ap = pre * A (np x np, type dst_f64 ? double : float); then the plan:
+// mode 0 the cos/sin rule, mode 1 the wave rule (pre = t^2, so the norm is ||B||_1).
 sincosm_status launch_norm_copy_plan(int64_t n, int64_t np, const void* A, int64_t lda, bool src_f64,
                                      void* Ap, bool dst_f64, int acc,
-                                     const NormScratch& ns, hipStream_t stream);
+                                     const NormScratch& ns, hipStream_t stream, int mode = 0,
+                                     double pre = 1.0);
 // dst (np x np, zero padded) = src^T for an n x n src.
 sincosm_status launch_transpose_pad(int64_t n, int64_t np, const void* src, int64_t lds, bool src_f64,
                                     void* dst, bool dst_f64, hipStream_t stream);

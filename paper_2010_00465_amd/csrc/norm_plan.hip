@@ -38,7 +38,7 @@ NormScratch norm_scratch(void* base, int64_t np) {
 
 template <typename TS, typename TD>
 __global__ __launch_bounds__(NORM_COLS) void norm_copy_kernel(int64_t n, int64_t np, const TS* __restrict__ A,
-                                                             int64_t lda, TD* __restrict__ Ap,
+                                                             int64_t lda, double pre, TD* __restrict__ Ap,
                                                              double* __restrict__ partial,
                                                              unsigned long long* maxbits) {
   const int64_t j = (int64_t)blockIdx.x * NORM_COLS + threadIdx.x;
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(NORM_COLS) void norm_copy_kernel(int64_t n, int64_t
   const int64_t i1 = i0 + NORM_ROWS < np ? i0 + NORM_ROWS : np;
   for (int64_t i = i0; i < i1; ++i) {
     double v = 0.0;
-    if (i < n && j < n) v = (double)A[i * lda + j];
+    if (i < n && j < n) v = (double)A[i * lda + j] * pre;
     if (Ap) Ap[i * np + j] = (TD)v;
     sum += fabs(v);
   }
@@ -79,31 +79,34 @@ __global__ __launch_bounds__(NORM_COLS) void norm_reduce_kernel(int64_t np, int 
   if (threadIdx.x == 0) atomicMax(maxbits, red[0]);
 }
 
-__global__ void plan_kernel(const unsigned long long* maxbits, int acc, sincosm_plan* plan) {
+// mode 0: plan of the cos/sin schemes; mode 1: plan of the wave schemes (norm of B = t^2 A)
+__global__ void plan_kernel(const unsigned long long* maxbits, int acc, int mode, sincosm_plan* plan) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const double nrm = __longlong_as_double((long long)*maxbits);
   sincosm_plan p;
-  plan_rule(nrm, acc, &p);
+  if (mode == 1) plan_rule_wave(nrm, acc, &p);
+  else plan_rule(nrm, acc, &p);
   *plan = p;
 }
 
 template <typename TS, typename TD>
 static void launch_norm_t(int64_t n, int64_t np, const void* A, int64_t lda, void* Ap, const NormScratch& ns,
-                          int acc, hipStream_t stream) {
+                          int acc, int mode, double pre, hipStream_t stream) {
   dim3 g1((unsigned)((np + NORM_COLS - 1) / NORM_COLS), (unsigned)ns.nchunks);
-  norm_copy_kernel<TS, TD><<<g1, NORM_COLS, 0, stream>>>(n, np, (const TS*)A, lda, (TD*)Ap, ns.partial,
-                                                         ns.maxbits);
+  norm_copy_kernel<TS, TD><<<g1, NORM_COLS, 0, stream>>>(n, np, (const TS*)A, lda, pre, (TD*)Ap,
+                                                         ns.partial, ns.maxbits);
   dim3 g2((unsigned)((np + NORM_COLS - 1) / NORM_COLS));
   norm_reduce_kernel<<<g2, NORM_COLS, 0, stream>>>(np, ns.nchunks, ns.partial, ns.maxbits);
-  plan_kernel<<<1, 64, 0, stream>>>(ns.maxbits, acc, ns.plan);
+  plan_kernel<<<1, 64, 0, stream>>>(ns.maxbits, acc, mode, ns.plan);
 }
 
 sincosm_status launch_norm_copy_plan(int64_t n, int64_t np, const void* A, int64_t lda, bool src_f64, void* Ap,
-                                     bool dst_f64, int acc, const NormScratch& ns, hipStream_t stream) {
-  if (src_f64 && dst_f64) launch_norm_t<double, double>(n, np, A, lda, Ap, ns, acc, stream);
-  else if (src_f64 && !dst_f64) launch_norm_t<double, float>(n, np, A, lda, Ap, ns, acc, stream);
-  else if (!src_f64 && dst_f64) launch_norm_t<float, double>(n, np, A, lda, Ap, ns, acc, stream);
-  else launch_norm_t<float, float>(n, np, A, lda, Ap, ns, acc, stream);
+                                     bool dst_f64, int acc, const NormScratch& ns, hipStream_t stream, int mode,
+                                     double pre) {
+  if (src_f64 && dst_f64) launch_norm_t<double, double>(n, np, A, lda, Ap, ns, acc, mode, pre, stream);
+  else if (src_f64 && !dst_f64) launch_norm_t<double, float>(n, np, A, lda, Ap, ns, acc, mode, pre, stream);
+  else if (!src_f64 && dst_f64) launch_norm_t<float, double>(n, np, A, lda, Ap, ns, acc, mode, pre, stream);
+  else launch_norm_t<float, float>(n, np, A, lda, Ap, ns, acc, mode, pre, stream);
   SC_HIP(hipGetLastError());
   return SINCOSM_OK;
 }

@@ -1,0 +1,273 @@
+// Wave-equation functions c(t^2 A) = cos(t sqrt A) and s(t, A) = sin(t sqrt A) / sqrt A
+// (Sections 1 and 2.2): the factorized schemes with B = t^2 A in the role of
+// the paper's A_2 and the scalar t in the role of the final factor A, so each
+// scheme spends one product fewer than its cos/sin parent and the sine's last
+// "multiply by A" becomes a scalar folded into an epilogue.
+//
+// The norm/copy kernel writes Ap = B = t^2 A (zero padded) and plans on
+// ||B||_1. With s double-angle steps the scheme runs on B_s = 4^-s B (the
+// factor 4^-s goes into operand scales and epilogue coefficients, B_s is never
+// formed) and t_s = 2^-s t. Launch sequences ("->" lists epilogue outputs):
+//
+// 2 products (P^c_4 of Algorithm4cA and P^s_{3,4}, with the B_4 term's sign
+//   of Algorithm4sA):
+//   G1 B2 = B_s B_s -> B2, W = -B_s/6! + B2/8!, Pc = I - B_s/2 + B2/24,
+//                      Ps = t_s (I - B_s/6 + B2/120)
+//   G2 B4 = B2 W    -> C = Pc + B4, S = Ps + (t_s/7) B4
+// 3 products (P^c_4 and P^s_4): as above, G1 also writes
+//   Ws = -B_s/7! + B2/9!, and
+//   G2 B4 = B2 W    -> C = Pc + B4
+//   G3 B4s = B2 Ws  -> S = Ps + t_s B4s
+// 4 products (P^c_8 with eq:cosm8's coefficients, P^s_{8,12} with Algorithm6sA's):
+//   G1 B2 = B_s B_s -> B2, W = x1 B_s + x2 B2
+//   G2 B4 = B2 W    -> B4, L = x3 B2 + B4, R = x4 I + x5 B_s + x6 B2 + x7 B4,
+//                      Pc = I - B_s/2 + x8 B2, Q = z5 (I + B_s) + z6 B2 + z7 B4,
+//                      P = z0 I + z1 B_s + z2 B2 + z3 B4
+//   G3 T = L R      -> C = Pc + T, Q += z8 C, P += z4 C
+//   G4 U = Q B4     -> S = t_s (P + U)
+// 5 products (P^c_12 with Coefs7cA, P^s_{11,24} with Coefs7sA):
+//   G1 B2 = B_s B_s -> B2
+//   G2 B3 = B2 B_s  -> D_j = a0j I + a1j B_s + a2j B2 + a3j B3 (j = 1..4),
+//                      P = z0 I + z1 B_s + z2 B2 + z3 B3, Q = z6 I + z7 B_s + z8 B2 + z9 B3
+//   G3 K = D4 D4    -> B6 = D3 + K, L = D2 + B6
+//   G4 T = L B6     -> C = D1 + T, Q += z10 B6 + z11 C, P += z4 B6 + z5 C
+//   G5 U = Q C      -> S = t_s (P + U)
+// Double angle (Section 1), s times, from the old pair (C, S):
+//   one launch, two problems sharing the right operand C:
+//   [P | Q] = [C | S] C -> C' = 2 P - I, S' = 2 Q.
+#include <math.h>
+#include <string.h>
+
+#include "schemes.hpp"
+#include "coeffs.hpp"
+
+namespace sc {
+
+static sincosm_status wave2(Run& r, double bs, double ts, bool three) {
+  const Modes& m = *r.m;
+  const int64_t np = m.np;
+  const int nv = (int)r.n;
+  const bool pf = m.poly_f64;
+  Problem p = make_problem(nv);
+  add_seg(p, r.Ap, r.Ap, np, bs, bs);
+  add_in(p, r.Ap, np);
+  add_out(p, internal(r.W[1], m, pf), 1.0, 0.0, {});                                    // B2
+  add_out(p, internal(r.W[2], m, pf), 1.0 / 40320.0, 0.0, {-bs / 720.0});               // W
+  add_out(p, internal(r.W[3], m, pf), 1.0 / 24.0, 1.0, {-0.5 * bs});                    // Pc
+  add_out(p, internal(r.W[4], m, pf), ts / 120.0, ts, {-ts * bs / 6.0});                // Ps
+  if (three) add_out(p, internal(r.W[5], m, pf), 1.0 / 362880.0, 0.0, {-bs / 5040.0});  // Ws
+  SC_TRY(gemm(r, m.poly, one(p, (int)np)));
+  p = make_problem(nv);
+  add_seg(p, r.W[1], r.W[2], np);
+  add_in(p, r.W[3], np);
+  add_in(p, r.W[4], np);
+  add_out(p, r.Cout, 1.0, 0.0, {1.0, 0.0});
+  if (!three) {
+    add_out(p, r.Sout, ts / 7.0, 0.0, {0.0, 1.0});
+    return gemm(r, m.poly, one(p, (int)np));
+  }
+  SC_TRY(gemm(r, m.poly, one(p, (int)np)));
+  p = make_problem(nv);
+  add_seg(p, r.W[1], r.W[5], np);
+  add_in(p, r.W[4], np);
+  add_out(p, r.Sout, ts, 0.0, {1.0});
+  return gemm(r, m.poly, one(p, (int)np));
+}
+
+static sincosm_status wave4(Run& r, double bs, double ts) {
+  const Modes& m = *r.m;
+  const int64_t np = m.np;
+  const int nv = (int)r.n;
+  const bool pf = m.poly_f64;
+  const Coeffs& k = coeffs();
+  const double* x = k.x;
+  const double* z = k.z6;
+  Problem p = make_problem(nv);
+  add_seg(p, r.Ap, r.Ap, np, bs, bs);
+  add_in(p, r.Ap, np);
+  add_out(p, internal(r.W[1], m, pf), 1.0, 0.0, {});             // B2
+  add_out(p, internal(r.W[2], m, pf), x[2], 0.0, {x[1] * bs});   // W
+  SC_TRY(gemm(r, m.poly, one(p, (int)np)));
+  // G2: B4 = B2 W; inputs B_s (Ap, scaled through the coefficients), B2 (W1)
+  p = make_problem(nv);
+  add_seg(p, r.W[1], r.W[2], np);
+  add_in(p, r.Ap, np);
+  add_in(p, r.W[1], np);
+  add_out(p, internal(r.W[3], m, pf), 1.0, 0.0, {});                          // B4
+  add_out(p, internal(r.W[4], m, pf), 1.0, 0.0, {0.0, x[3]});                 // L
+  add_out(p, internal(r.W[5], m, pf), x[7], x[4], {x[5] * bs, x[6]});         // R
+  add_out(p, internal(r.W[6], m, pf), 0.0, 1.0, {-0.5 * bs, x[8]});           // Pc
+  add_out(p, internal(r.W[7], m, pf), z[7], z[5], {z[5] * bs, z[6]});         // Q
+  add_out(p, internal(r.W[8], m, pf), z[3], z[0], {z[1] * bs, z[2]});         // P
+  SC_TRY(gemm(r, m.poly, one(p, (int)np)));
+  // G3: T = L R; inputs Pc (W6), Q (W7), P (W8)
+  p = make_problem(nv);
+  add_seg(p, r.W[4], r.W[5], np);
+  add_in(p, r.W[6], np);
+  add_in(p, r.W[7], np);
+  add_in(p, r.W[8], np);
+  add_out(p, r.Cout, 1.0, 0.0, {1.0, 0.0, 0.0});                     // C = Pc + T
+  add_out(p, internal(r.W[7], m, pf), z[8], 0.0, {z[8], 1.0, 0.0});  // Q + z8 C
+  add_out(p, internal(r.W[8], m, pf), z[4], 0.0, {z[4], 0.0, 1.0});  // P + z4 C
+  SC_TRY(gemm(r, m.poly, one(p, (int)np)));
+  // G4: U = Q B4 -> S = t_s (P + U)
+  p = make_problem(nv);
+  add_seg(p, r.W[7], r.W[3], np);
+  add_in(p, r.W[8], np);
+  add_out(p, r.Sout, ts, 0.0, {ts});
+  return gemm(r, m.poly, one(p, (int)np));
+}
+
+static sincosm_status wave5(Run& r, double bs, double ts) {
+  const Modes& m = *r.m;
+  const int64_t np = m.np;
+  const int nv = (int)r.n;
+  const bool pf = m.poly_f64;
+  const Coeffs& k = coeffs();
+  const double(*a)[5] = k.a;
+  const double* z = k.z7;
+  Problem p = make_problem(nv);
+  add_seg(p, r.Ap, r.Ap, np, bs, bs);
+  add_out(p, internal(r.W[1], m, pf), 1.0, 0.0, {});   // B2
+  SC_TRY(gemm(r, m.poly, one(p, (int)np)));
+  // G2: B3 = B2 B_s; inputs B_s (Ap), B2 (W1)
+  p = make_problem(nv);
+  add_seg(p, r.W[1], r.Ap, np, 1.0, bs);
+  add_in(p, r.Ap, np);
+  add_in(p, r.W[1], np);
+  for (int j = 1; j <= 4; ++j)
+    add_out(p, internal(r.W[1 + j], m, pf), a[3][j], a[0][j], {a[1][j] * bs, a[2][j]});  // D_j -> W2..W5
+  add_out(p, internal(r.W[6], m, pf), z[3], z[0], {z[1] * bs, z[2]});                  // P
+  add_out(p, internal(r.W[7], m, pf), z[9], z[6], {z[7] * bs, z[8]});                  // Q
+  SC_TRY(gemm(r, m.poly, one(p, (int)np)));
+  // G3: K = D4 D4; inputs D3 (W4), D2 (W3) -> B6 = D3 + K (W4), L = D2 + B6 (W3)
+  p = make_problem(nv);
+  add_seg(p, r.W[5], r.W[5], np);
+  add_in(p, r.W[4], np);
+  add_in(p, r.W[3], np);
+  add_out(p, internal(r.W[4], m, pf), 1.0, 0.0, {1.0, 0.0});
+  add_out(p, internal(r.W[3], m, pf), 1.0, 0.0, {1.0, 1.0});
+  SC_TRY(gemm(r, m.poly, one(p, (int)np)));
+  // G4: T = L B6; inputs D1 (W2), B6 (W4), Q (W7), P (W6)
+  p = make_problem(nv);
+  add_seg(p, r.W[3], r.W[4], np);
+  add_in(p, r.W[2], np);
+  add_in(p, r.W[4], np);
+  add_in(p, r.W[7], np);
+  add_in(p, r.W[6], np);
+  add_out(p, internal(r.W[8], m, pf), 1.0, 0.0, {1.0, 0.0, 0.0, 0.0});       // C (operand of G5)
+  add_out(p, r.Cout, 1.0, 0.0, {1.0, 0.0, 0.0, 0.0});                        // C (result)
+  add_out(p, internal(r.W[7], m, pf), z[11], 0.0, {z[11], z[10], 1.0, 0.0}); // Q + z10 B6 + z11 C
+  add_out(p, internal(r.W[6], m, pf), z[5], 0.0, {z[5], z[4], 0.0, 1.0});    // P + z4 B6 + z5 C
+  SC_TRY(gemm(r, m.poly, one(p, (int)np)));
+  // G5: U = Q C -> S = t_s (P + U)
+  p = make_problem(nv);
+  add_seg(p, r.W[7], r.W[8], np);
+  add_in(p, r.W[6], np);
+  add_out(p, r.Sout, ts, 0.0, {ts});
+  return gemm(r, m.poly, one(p, (int)np));
+}
+
+static sincosm_status run_wave_scheme(Run& r, int level, double bs, double ts) {
+  switch (level) {
+    case 2: return wave2(r, bs, ts, false);
+    case 3: return wave2(r, bs, ts, true);
+    case 4: return wave4(r, bs, ts);
+    default: return wave5(r, bs, ts);
+  }
+}
+
+// One wave double-angle step: C' = 2 Cc Cc - I, S' = 2 Sc Cc.
+static sincosm_status wave_double_angle(Run& r, const void* Cc, const void* Sc, const Target& Cn,
+                                        const Target& Sn) {
+  const Modes& m = *r.m;
+  Problem p0 = make_problem((int)r.n);
+  add_seg(p0, Cc, Cc, m.np);
+  add_out(p0, Cn, 2.0, -1.0, {});
+  Problem p1 = make_problem((int)r.n);
+  add_seg(p1, Sc, Cc, m.np);
+  add_out(p1, Sn, 2.0, 0.0, {});
+  return gemm(r, m.sq, two(p0, p1, (int)m.np));
+}
+
+}  // namespace sc
+
+using namespace sc;
+
+extern "C" {
+
+sincosm_status sincosm_wave_plan_host(double normB, int acc, sincosm_plan* out) {
+  if (!out || (acc != SINCOSM_ACC_DOUBLE && acc != SINCOSM_ACC_SINGLE)) return SINCOSM_E_ARG;
+  plan_rule_wave(normB, acc, out);
+  return SINCOSM_OK;
+}
+
+sincosm_status sincosm_wave_eval(int64_t n, int dtype, const void* A, int64_t lda, double t, void* C,
+                                 int64_t ldc, void* S, int64_t lds, int acc, int prod, void* ws,
+                                 size_t ws_bytes, sincosm_plan* plan_host, void* stream_) {
+  if (n < 0 || n > (1 << 20)) return SINCOSM_E_ARG;
+  if (acc != SINCOSM_ACC_DOUBLE && acc != SINCOSM_ACC_SINGLE) return SINCOSM_E_ARG;
+  if (!isfinite(t)) return SINCOSM_E_ARG;
+  Modes m;
+  if (!modes_for(n > 0 ? n : 1, dtype, prod, m)) return SINCOSM_E_ARG;
+  if (n == 0) {
+    if (plan_host) { plan_rule_wave(0.0, acc, plan_host); plan_host->level = 0; plan_host->products = 0; }
+    return SINCOSM_OK;
+  }
+  if (!A || !C || !S) return SINCOSM_E_ARG;
+  if (lda < n || ldc < n || lds < n) return SINCOSM_E_ARG;
+  const size_t es = dtype == SINCOSM_F64 ? 8 : 4;
+  if (overlaps(A, lda, C, ldc, n, es) || overlaps(A, lda, S, lds, n, es) || overlaps(C, ldc, S, lds, n, es))
+    return SINCOSM_E_ARG;
+  if (m.poly == Arith::BF16X3 && !bf16x3_available()) return SINCOSM_E_UNSUPPORTED;
+  const Layout L = layout_for(m);
+  if (!ws || ws_bytes < L.total || ((uintptr_t)ws & 255u)) return SINCOSM_E_WORKSPACE;
+  hipStream_t stream = (hipStream_t)stream_;
+  char* base = (char*)ws;
+
+  const NormScratch ns = norm_scratch(base + L.norm_off, m.np);
+  void* Bp = base + L.ap_off;
+  SC_TRY(launch_norm_copy_plan(n, m.np, A, lda, m.user_f64, Bp, m.poly_f64, acc, ns, stream, 1, t * t));
+  sincosm_plan plan;
+  SC_TRY(read_plan(ns.plan, &plan, stream));
+  if (plan_host) *plan_host = plan;
+  if (plan.status != SINCOSM_OK) {
+    SC_TRY(launch_fill_nan(n, C, ldc, m.user_f64, stream));
+    SC_TRY(launch_fill_nan(n, S, lds, m.user_f64, stream));
+    return SINCOSM_E_NONFINITE;
+  }
+
+  Run r;
+  r.m = &m;
+  r.n = n;
+  r.Ap = Bp;
+  for (int i = 0; i < 9; ++i) r.W[i] = base + L.w_off[i];
+  r.stream = stream;
+  r.launched = 0;
+  void* Q[4];
+  for (int i = 0; i < 4; ++i) Q[i] = base + L.q_off[i];
+  const Target userC{C, ldc, (int)n, m.user_f64};
+  const Target userS{S, lds, (int)n, m.user_f64};
+  const int s = plan.s;
+  if (s == 0) {
+    r.Cout = userC;
+    r.Sout = userS;
+  } else {
+    r.Cout = internal(Q[1], m, m.sq_f64);
+    r.Sout = internal(Q[0], m, m.sq_f64);
+  }
+  const double bs = ldexp(1.0, -2 * s);
+  const double ts = ldexp(t, -s);
+  SC_TRY(run_wave_scheme(r, plan.level, bs, ts));
+  for (int i = 0; i < s; ++i) {
+    void* Sc = Q[(i & 1) ? 2 : 0];
+    void* Cc = Q[(i & 1) ? 3 : 1];
+    const bool last = (i == s - 1);
+    const Target Sn = last ? userS : internal(Q[(i & 1) ? 0 : 2], m, m.sq_f64);
+    const Target Cn = last ? userC : internal(Q[(i & 1) ? 1 : 3], m, m.sq_f64);
+    SC_TRY(wave_double_angle(r, Cc, Sc, Cn, Sn));
+  }
+  return SINCOSM_OK;
+}
+
+}  // extern "C"

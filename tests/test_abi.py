@@ -85,3 +85,23 @@ def test_argument_errors_without_gpu(lib):
     assert lib.sincosm_strerror(-3) == b"workspace missing or too small"
     lib.sincosm_plan_host.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_void_p]
     assert lib.sincosm_plan_host(1.0, 5, None) == -1
+
+
+def test_wave_host_plan_matches_oracle(lib):
+    """The library's wave plan rule against the oracle's, including values at and next to every
+    bound times a power of four (where s steps)."""
+    from oracle import wave as Wv
+    lib.sincosm_wave_plan_host.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.POINTER(Plan)]
+    xs = list(np.exp2(np.random.default_rng(6).uniform(-40, 80, size=3000)))
+    for acc in ("double", "single"):
+        for th in Wv.WAVE_THETA[acc].values():
+            for k in range(0, 12):
+                b = th * 4.0 ** k
+                xs += [b, math.nextafter(b, math.inf), math.nextafter(b, 0.0)]
+    for x in xs:
+        for code, name in ((0, "double"), (1, "single")):
+            p = Plan()
+            assert lib.sincosm_wave_plan_host(float(x), code, ctypes.byref(p)) == 0
+            assert (p.level, p.s, p.products, p.status) == (*Wv.wave_plan(float(x), name), 0), (x, name)
+    p = Plan()
+    assert lib.sincosm_wave_plan_host(math.nan, 0, ctypes.byref(p)) == 0 and p.status == -4

@@ -40,8 +40,8 @@ def parse():
     ap.add_argument("--n", type=int, default=N)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the batched, backward and precision-tier measurements")
-    ap.add_argument("--only", choices=["batched", "backward", "tiers"],
+                    help="skip the batched, backward, precision-tier and wave measurements")
+    ap.add_argument("--only", choices=["batched", "backward", "tiers", "wave"],
                     help="run and print only one of the secondary measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run sincosm_matmul once at --n: its two pad/convert copy kernels read and "
@@ -190,6 +190,42 @@ def bench_tiers(torch, sc, W):
     return out
 
 
+def bench_wave(torch, sc, W):
+    """Wave-equation pair c(t^2 A), s(t, A) (sincosm_wave_eval), n = 4096 float64.
+
+    (a) A = X^2 for a Gaussian X with ||X||_1 = 2^e (e = 0, 4), t = 1: the wave call gives
+        cos(X) (and s(1, A) X = sin(X)) and is timed against sincosm_eval(X), which returns the
+        same cosine, with the products each plan takes and the relative difference of the two
+        cosines; (b) A = 2-D 5-point Laplacian on a 64 x 64 grid with ||A||_1 = 64 and t = 1/2, 4
+        (the semi-discrete wave equation y'' + A y = 0)."""
+    n = 4096
+    out = {"workload": "sincosm_wave_eval, n=4096 float64, double-accuracy wave plan"}
+    ws = torch.empty(sc.workspace_size(n, torch.float64), dtype=torch.uint8, device="cuda")
+    for e in (0, 4):
+        X = torch.from_numpy(W.gaussian(n, 2.0 ** e, key=(5, n, e))).cuda()
+        A = torch.empty_like(X)
+        sc.sincosm_matmul(X, X, A)
+        C, S, Cx, Sx = (torch.empty_like(X) for _ in range(4))
+        pw = sc.sincosm_wave_eval(A, 1.0, C, S, ws=ws)
+        pc = sc.sincosm_eval(X, Cx, Sx, ws=ws)
+        tw = _elapsed(torch, lambda: sc.sincosm_wave_eval(A, 1.0, C, S, ws=ws), 3)
+        tc = _elapsed(torch, lambda: sc.sincosm_eval(X, Cx, Sx, ws=ws), 3)
+        diff = float((C - Cx).norm() / Cx.norm())
+        out[f"X^2_gaussian_2^{e}"] = {
+            "wave": {"ms": 1e3 * tw, "plan": [pw.level, pw.s], "products": pw.products,
+                     "norm1_B": pw.norm1, "tflops_algorithmic": pw.products * 2.0 * n ** 3 / tw / 1e12},
+            "sincosm_eval_of_X": {"ms": 1e3 * tc, "plan": [pc.level, pc.s], "products": pc.products},
+            "speedup": tc / tw, "rel_diff_cos": diff}
+    A = torch.from_numpy(W.laplacian_2d(64, 64.0)).cuda()
+    C, S = torch.empty_like(A), torch.empty_like(A)
+    for t in (0.5, 4.0):
+        p = sc.sincosm_wave_eval(A, t, C, S, ws=ws)
+        tw = _elapsed(torch, lambda: sc.sincosm_wave_eval(A, t, C, S, ws=ws), 3)
+        out[f"laplacian2d_t{t}"] = {"ms": 1e3 * tw, "plan": [p.level, p.s], "products": p.products,
+                                    "tflops_algorithmic": p.products * 2.0 * n ** 3 / tw / 1e12}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -204,7 +240,8 @@ def main():
         import torch
         import paper_2010_00465_amd as sc
         import workloads as W
-        fn = {"batched": bench_batched, "backward": bench_backward, "tiers": bench_tiers}[args.only]
+        fn = {"batched": bench_batched, "backward": bench_backward, "tiers": bench_tiers,
+              "wave": bench_wave}[args.only]
         print(json.dumps({args.only: fn(torch, sc, W)}))
         return
     import torch
@@ -279,6 +316,7 @@ def main():
         extras["batched"] = bench_batched(torch, sc, W)
         extras["backward"] = bench_backward(torch, sc, W)
         extras["tiers"] = bench_tiers(torch, sc, W)
+        extras["wave"] = bench_wave(torch, sc, W)
 
     out = {
         "metric": "cos+sin evals/sec & % MFMA peak at n=4096 FP64; rel err vs FP64 oracle",

@@ -16,8 +16,9 @@ def pytest_configure(config):
 def rel_fro(X, Ref):
     """Relative Frobenius error ||X - Ref||_F / ||Ref||_F (absolute when Ref = 0)."""
     import numpy as np
-    X = np.asarray(X, dtype=np.float64)
-    Ref = np.asarray(Ref, dtype=np.float64)
+    dt = np.complex128 if (np.iscomplexobj(X) or np.iscomplexobj(Ref)) else np.float64
+    X = np.asarray(X, dtype=dt)
+    Ref = np.asarray(Ref, dtype=dt)
     d = float(np.linalg.norm(X - Ref))
     r = float(np.linalg.norm(Ref))
     return d / r if r > 0 else d

@@ -142,6 +142,36 @@ sincosm_status sincosm_wave_eval(int64_t n, int dtype, const void* A, int64_t ld
                                  int acc, int prod, void* ws, size_t ws_bytes,
                                  sincosm_plan* plan_host, void* stream);
 
+/* Block propagator of the wave system (eq:symplectic, Section 1): y'' + A y = 0
+ * written as (y, y')' = M (y, y'), M = [[0, I], [-A, 0]], has
+ *   E = e^{tM} = [[c(t^2 A), s(t, A)], [-A s(t, A), c(t^2 A)]].
+ * Computed as sincosm_wave_eval does, plus one product A s(t, A) whose
+ * epilogue writes all four n x n blocks of E (2n x 2n, row-major, leading
+ * dimension lde >= 2n, type `dtype`). E must not overlap A. Plan, workspace
+ * (sincosm_workspace_size(n, dtype, acc, prod)), dtype/prod combinations and
+ * errors as for sincosm_wave_eval; the wave plan's product count does not
+ * include the extra product. Non-finite input: E filled with NaN,
+ * SINCOSM_E_NONFINITE. */
+sincosm_status sincosm_wave_block_eval(int64_t n, int dtype, const void* A, int64_t lda, double t,
+                                       void* E, int64_t lde, int acc, int prod, void* ws,
+                                       size_t ws_bytes, sincosm_plan* plan_host, void* stream);
+
+/* Unitary propagator of i u' = A u for real A (eq:unitary, Section 1):
+ *   U = e^{-itA} = cos(tA) - i sin(tA),
+ * from the cos/sin method on X = tA (the copy of A is multiplied by t in
+ * float64 as it is read; the plan is that of sincosm_eval for ||tA||_1), so
+ * every product is real and each double-angle step costs two real products.
+ *  U: n x n complex, interleaved (real, imaginary) pairs of `dtype` (complex128
+ *     for F64, complex64 for F32), leading dimension ldu >= n in complex
+ *     elements, aligned to one complex element; must not overlap A.
+ *  t: finite scalar; non-finite t is SINCOSM_E_ARG.
+ * Workspace sincosm_workspace_size(n, dtype, acc, prod); dtype/prod, plan_host
+ * and errors as for sincosm_eval (non-finite tA: U filled with NaN,
+ * SINCOSM_E_NONFINITE). */
+sincosm_status sincosm_expi_eval(int64_t n, int dtype, const void* A, int64_t lda, double t,
+                                 void* U, int64_t ldu, int acc, int prod, void* ws, size_t ws_bytes,
+                                 sincosm_plan* plan_host, void* stream);
+
 /* Batched evaluation of many independent matrices of uneven orders
  * (1 <= n <= 256), packed row-major with leading dimension n at element
  * offsets offset_host[i] (the same offsets for A, C and S). Two calls:

@@ -26,7 +26,8 @@ TUNED_ENTRIES = _autotune.apply_cache()
 
 __all__ = ["sincosm", "sincosm_eval", "sincosm_eval_batched", "sincosm_backward", "sincosm_matmul",
            "plan_host", "plan_device", "workspace_size", "Plan", "SincosmError", "sincosm_batched",
-           "wave_plan_host", "sincosm_wave_eval", "wave"]
+           "wave_plan_host", "sincosm_wave_eval", "wave", "sincosm_wave_block_eval", "wave_block",
+           "sincosm_expi_eval", "expi"]
 
 
 def _dtype_code(t: torch.Tensor) -> int:
@@ -133,6 +134,69 @@ def wave(A: torch.Tensor, t: float, accuracy: str = "double", products: str = "n
     S = torch.empty_like(A)
     sincosm_wave_eval(A, t, C, S, accuracy, products)
     return C, S
+
+
+def sincosm_wave_block_eval(A: torch.Tensor, t: float, E: torch.Tensor, accuracy: str = "double",
+                            products: str = "native", ws: torch.Tensor | None = None,
+                            raise_nonfinite=True) -> Plan:
+    """C-ABI sincosm_wave_block_eval: E (2n x 2n) = e^{tM}, M = [[0, I], [-A, 0]], in place."""
+    _require_cuda(A, E)
+    n = A.shape[0]
+    if E.dtype != A.dtype or E.shape[0] != 2 * n or E.shape[1] != 2 * n:
+        raise ValueError("E must be 2n x 2n of A's dtype")
+    if ws is None:
+        ws = _workspace(workspace_size(n, A.dtype, accuracy, products), A.device)
+    plan = Plan()
+    st = lib.sincosm_wave_block_eval(n, _dtype_code(A), A.data_ptr(), _ld(A), float(t), E.data_ptr(), _ld(E),
+                                     ACC[accuracy], PROD[products], ws.data_ptr(), ws.numel(),
+                                     ctypes.byref(plan), _stream(A))
+    if st == _lib.E_NONFINITE and not raise_nonfinite:
+        return plan
+    check(st, "sincosm_wave_block_eval")
+    return plan
+
+
+def wave_block(A: torch.Tensor, t: float, accuracy: str = "double", products: str = "native"):
+    """e^{tM} for M = [[0, I], [-A, 0]] (2n x 2n), the propagator of (y, y') for y'' + A y = 0."""
+    if A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("square matrix expected")
+    A = A.contiguous()
+    n = A.shape[0]
+    E = torch.empty(2 * n, 2 * n, dtype=A.dtype, device=A.device)
+    sincosm_wave_block_eval(A, t, E, accuracy, products)
+    return E
+
+
+_COMPLEX_OF = {torch.float64: torch.complex128, torch.float32: torch.complex64}
+
+
+def sincosm_expi_eval(A: torch.Tensor, t: float, U: torch.Tensor, accuracy: str = "double",
+                      products: str = "native", ws: torch.Tensor | None = None, raise_nonfinite=True) -> Plan:
+    """C-ABI sincosm_expi_eval: U = e^{-itA} = cos(tA) - i sin(tA) (complex tensor, written in place)."""
+    _require_cuda(A, U)
+    n = A.shape[0]
+    if U.dtype != _COMPLEX_OF.get(A.dtype) or U.dim() != 2 or U.stride(1) != 1:
+        raise ValueError("U must be a row-major complex tensor matching A's precision")
+    if ws is None:
+        ws = _workspace(workspace_size(n, A.dtype, accuracy, products), A.device)
+    plan = Plan()
+    st = lib.sincosm_expi_eval(n, _dtype_code(A), A.data_ptr(), _ld(A), float(t), U.data_ptr(), U.stride(0),
+                               ACC[accuracy], PROD[products], ws.data_ptr(), ws.numel(), ctypes.byref(plan),
+                               _stream(A))
+    if st == _lib.E_NONFINITE and not raise_nonfinite:
+        return plan
+    check(st, "sincosm_expi_eval")
+    return plan
+
+
+def expi(A: torch.Tensor, t: float = 1.0, accuracy: str = "double", products: str = "native"):
+    """e^{-itA} for a real square GPU tensor, as a complex tensor (the unitary propagator of i u' = A u)."""
+    if A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("square matrix expected")
+    A = A.contiguous()
+    U = torch.empty(A.shape, dtype=_COMPLEX_OF[A.dtype], device=A.device)
+    sincosm_expi_eval(A, t, U, accuracy, products)
+    return U
 
 
 def sincosm_matmul(X: torch.Tensor, Y: torch.Tensor, Z: torch.Tensor, products: str = "native",

@@ -177,6 +177,12 @@ sincosm_status launch_norm_copy_plan(int64_t n, int64_t np, const void* A, int64
 sincosm_status launch_transpose_pad(int64_t n, int64_t np, const void* src, int64_t lds, bool src_f64,
                                     void* dst, bool dst_f64, hipStream_t stream);
 sincosm_status launch_fill_nan(int64_t n, void* X, int64_t ld, bool f64, hipStream_t stream);
+sincosm_status launch_fill_nan_rect(int64_t rows, int64_t cols, void* X, int64_t ld, bool f64,
+                                    hipStream_t stream);
+// dst (n x n complex, leading dimension ldd in complex elements, pairs of the
+// real type) = re + i (negate_im ? -im : im), from np x np zero-padded planes.
+sincosm_status launch_interleave(int64_t n, int64_t np, const void* re, const void* im, bool negate_im,
+                                 void* dst, int64_t ldd, bool f64, hipStream_t stream);
 sincosm_status launch_fill_zero(int64_t np, void* X, bool f64, hipStream_t stream);
 sincosm_status launch_convert_pad(int64_t n, int64_t np, const void* src, int64_t lds, bool src_f64,
                                   void* dst, bool dst_f64, hipStream_t stream);

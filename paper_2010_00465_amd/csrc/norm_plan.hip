@@ -174,17 +174,53 @@ sincosm_status launch_fill_zero(int64_t np, void* X, bool f64, hipStream_t strea
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void fill_nan_kernel(int64_t n, T* X, int64_t ld) {
+__global__ __launch_bounds__(256) void fill_nan_kernel(int64_t cols, T* X, int64_t ld) {
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t i = blockIdx.y;
-  if (j < n) X[i * ld + j] = (T)__longlong_as_double(0x7ff8000000000000ll);
+  if (j < cols) X[i * ld + j] = (T)__longlong_as_double(0x7ff8000000000000ll);
+}
+
+sincosm_status launch_fill_nan_rect(int64_t rows, int64_t cols, void* X, int64_t ld, bool f64,
+                                    hipStream_t stream) {
+  if (rows <= 0 || cols <= 0) return SINCOSM_OK;
+  dim3 g((unsigned)((cols + 255) / 256), (unsigned)rows);
+  if (f64) fill_nan_kernel<double><<<g, 256, 0, stream>>>(cols, (double*)X, ld);
+  else fill_nan_kernel<float><<<g, 256, 0, stream>>>(cols, (float*)X, ld);
+  SC_HIP(hipGetLastError());
+  return SINCOSM_OK;
 }
 
 sincosm_status launch_fill_nan(int64_t n, void* X, int64_t ld, bool f64, hipStream_t stream) {
+  return launch_fill_nan_rect(n, n, X, ld, f64, stream);
+}
+
+// dst[i][j] = (re[i][j], sgn * im[i][j]) for i, j < n: interleaved complex
+// (real, imaginary) pairs from two zero-padded planes of the same type.
+template <typename T>
+__global__ __launch_bounds__(256) void interleave_kernel(int64_t n, int64_t np, const T* __restrict__ re,
+                                                        const T* __restrict__ im, T sgn, T* __restrict__ dst,
+                                                        int64_t ldd) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = blockIdx.y;
+  if (j < n) {
+    v2 v;
+    v.x = re[i * np + j];
+    v.y = sgn * im[i * np + j];
+    *(v2*)(dst + 2 * (i * ldd + j)) = v;
+  }
+}
+
+sincosm_status launch_interleave(int64_t n, int64_t np, const void* re, const void* im, bool negate_im,
+                                 void* dst, int64_t ldd, bool f64, hipStream_t stream) {
   if (n <= 0) return SINCOSM_OK;
   dim3 g((unsigned)((n + 255) / 256), (unsigned)n);
-  if (f64) fill_nan_kernel<double><<<g, 256, 0, stream>>>(n, (double*)X, ld);
-  else fill_nan_kernel<float><<<g, 256, 0, stream>>>(n, (float*)X, ld);
+  if (f64)
+    interleave_kernel<double><<<g, 256, 0, stream>>>(n, np, (const double*)re, (const double*)im,
+                                                     negate_im ? -1.0 : 1.0, (double*)dst, ldd);
+  else
+    interleave_kernel<float><<<g, 256, 0, stream>>>(n, np, (const float*)re, (const float*)im,
+                                                    negate_im ? -1.0f : 1.0f, (float*)dst, ldd);
   SC_HIP(hipGetLastError());
   return SINCOSM_OK;
 }

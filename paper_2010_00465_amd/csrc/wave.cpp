@@ -190,6 +190,85 @@ static sincosm_status wave_double_angle(Run& r, const void* Cc, const void* Sc, 
   return gemm(r, m.sq, two(p0, p1, (int)m.np));
 }
 
+// State shared by the wave entry points after validation: modes, workspace
+// layout, the padded B = t^2 A and the plan read back from the device.
+struct WaveCall {
+  Modes m;
+  Layout L;
+  char* base;
+  hipStream_t stream;
+  sincosm_plan plan;
+};
+
+// Validation common to every wave entry point (outputs are checked by the caller).
+static sincosm_status wave_check(int64_t n, int dtype, const void* A, int64_t lda, double t, int acc, int prod,
+                                 Modes& m) {
+  if (n < 0 || n > (1 << 20)) return SINCOSM_E_ARG;
+  if (acc != SINCOSM_ACC_DOUBLE && acc != SINCOSM_ACC_SINGLE) return SINCOSM_E_ARG;
+  if (!isfinite(t)) return SINCOSM_E_ARG;
+  if (!modes_for(n > 0 ? n : 1, dtype, prod, m)) return SINCOSM_E_ARG;
+  if (n > 0 && (!A || lda < n)) return SINCOSM_E_ARG;
+  if (m.poly == Arith::BF16X3 && !bf16x3_available()) return SINCOSM_E_UNSUPPORTED;
+  return SINCOSM_OK;
+}
+
+// Workspace check, B = t^2 A padded copy, ||B||_1 and the wave plan.
+static sincosm_status wave_prologue(int64_t n, const void* A, int64_t lda, double t, int acc, void* ws,
+                                    size_t ws_bytes, void* stream, WaveCall& c) {
+  c.L = layout_for(c.m);
+  if (!ws || ws_bytes < c.L.total || ((uintptr_t)ws & 255u)) return SINCOSM_E_WORKSPACE;
+  c.stream = (hipStream_t)stream;
+  c.base = (char*)ws;
+  const NormScratch ns = norm_scratch(c.base + c.L.norm_off, c.m.np);
+  SC_TRY(launch_norm_copy_plan(n, c.m.np, A, lda, c.m.user_f64, c.base + c.L.ap_off, c.m.poly_f64, acc, ns,
+                               c.stream, 1, t * t));
+  return read_plan(ns.plan, &c.plan, c.stream);
+}
+
+// The wave scheme and the s double-angle steps. With user targets the last
+// launch writes them; otherwise the final pair stays in the ping-pong
+// buffers and *Cf, *Sf point at it.
+static sincosm_status wave_body(WaveCall& c, int64_t n, double t, const Target* userC, const Target* userS,
+                                const void** Cf, const void** Sf) {
+  const Modes& m = c.m;
+  Run r;
+  r.m = &m;
+  r.n = n;
+  r.Ap = c.base + c.L.ap_off;
+  for (int i = 0; i < 9; ++i) r.W[i] = c.base + c.L.w_off[i];
+  r.stream = c.stream;
+  r.launched = 0;
+  void* Q[4];
+  for (int i = 0; i < 4; ++i) Q[i] = c.base + c.L.q_off[i];
+  const int s = c.plan.s;
+  const bool to_user = userC && userS;
+  if (s == 0 && to_user) {
+    r.Cout = *userC;
+    r.Sout = *userS;
+  } else {
+    r.Cout = internal(Q[1], m, m.sq_f64);
+    r.Sout = internal(Q[0], m, m.sq_f64);
+  }
+  const double bs = ldexp(1.0, -2 * s);
+  const double ts = ldexp(t, -s);
+  SC_TRY(run_wave_scheme(r, c.plan.level, bs, ts));
+  const void* Cl = Q[1];
+  const void* Sl = Q[0];
+  for (int i = 0; i < s; ++i) {
+    void* Sc = Q[(i & 1) ? 2 : 0];
+    void* Cc = Q[(i & 1) ? 3 : 1];
+    const bool last = (i == s - 1) && to_user;
+    const Target Sn = last ? *userS : internal(Q[(i & 1) ? 0 : 2], m, m.sq_f64);
+    const Target Cn = last ? *userC : internal(Q[(i & 1) ? 1 : 3], m, m.sq_f64);
+    SC_TRY(wave_double_angle(r, Cc, Sc, Cn, Sn));
+    Cl = Cn.p;
+    Sl = Sn.p;
+  }
+  if (Cf) *Cf = Cl;
+  if (Sf) *Sf = Sl;
+  return SINCOSM_OK;
+}
+
 }  // namespace sc
 
 using namespace sc;
@@ -202,72 +281,80 @@ sincosm_status sincosm_wave_plan_host(double normB, int acc, sincosm_plan* out) 
   return SINCOSM_OK;
 }
 
+static void empty_plan(int acc, sincosm_plan* plan_host) {
+  if (plan_host) { plan_rule_wave(0.0, acc, plan_host); plan_host->level = 0; plan_host->products = 0; }
+}
+
 sincosm_status sincosm_wave_eval(int64_t n, int dtype, const void* A, int64_t lda, double t, void* C,
                                  int64_t ldc, void* S, int64_t lds, int acc, int prod, void* ws,
-                                 size_t ws_bytes, sincosm_plan* plan_host, void* stream_) {
-  if (n < 0 || n > (1 << 20)) return SINCOSM_E_ARG;
-  if (acc != SINCOSM_ACC_DOUBLE && acc != SINCOSM_ACC_SINGLE) return SINCOSM_E_ARG;
-  if (!isfinite(t)) return SINCOSM_E_ARG;
-  Modes m;
-  if (!modes_for(n > 0 ? n : 1, dtype, prod, m)) return SINCOSM_E_ARG;
-  if (n == 0) {
-    if (plan_host) { plan_rule_wave(0.0, acc, plan_host); plan_host->level = 0; plan_host->products = 0; }
-    return SINCOSM_OK;
-  }
-  if (!A || !C || !S) return SINCOSM_E_ARG;
-  if (lda < n || ldc < n || lds < n) return SINCOSM_E_ARG;
+                                 size_t ws_bytes, sincosm_plan* plan_host, void* stream) {
+  WaveCall c;
+  SC_TRY(wave_check(n, dtype, A, lda, t, acc, prod, c.m));
+  if (n == 0) { empty_plan(acc, plan_host); return SINCOSM_OK; }
+  if (!C || !S || ldc < n || lds < n) return SINCOSM_E_ARG;
   const size_t es = dtype == SINCOSM_F64 ? 8 : 4;
   if (overlaps(A, lda, C, ldc, n, es) || overlaps(A, lda, S, lds, n, es) || overlaps(C, ldc, S, lds, n, es))
     return SINCOSM_E_ARG;
-  if (m.poly == Arith::BF16X3 && !bf16x3_available()) return SINCOSM_E_UNSUPPORTED;
-  const Layout L = layout_for(m);
-  if (!ws || ws_bytes < L.total || ((uintptr_t)ws & 255u)) return SINCOSM_E_WORKSPACE;
-  hipStream_t stream = (hipStream_t)stream_;
-  char* base = (char*)ws;
-
-  const NormScratch ns = norm_scratch(base + L.norm_off, m.np);
-  void* Bp = base + L.ap_off;
-  SC_TRY(launch_norm_copy_plan(n, m.np, A, lda, m.user_f64, Bp, m.poly_f64, acc, ns, stream, 1, t * t));
-  sincosm_plan plan;
-  SC_TRY(read_plan(ns.plan, &plan, stream));
-  if (plan_host) *plan_host = plan;
-  if (plan.status != SINCOSM_OK) {
-    SC_TRY(launch_fill_nan(n, C, ldc, m.user_f64, stream));
-    SC_TRY(launch_fill_nan(n, S, lds, m.user_f64, stream));
+  SC_TRY(wave_prologue(n, A, lda, t, acc, ws, ws_bytes, stream, c));
+  if (plan_host) *plan_host = c.plan;
+  if (c.plan.status != SINCOSM_OK) {
+    SC_TRY(launch_fill_nan(n, C, ldc, c.m.user_f64, c.stream));
+    SC_TRY(launch_fill_nan(n, S, lds, c.m.user_f64, c.stream));
     return SINCOSM_E_NONFINITE;
   }
+  const Target userC{C, ldc, (int)n, c.m.user_f64};
+  const Target userS{S, lds, (int)n, c.m.user_f64};
+  return wave_body(c, n, t, &userC, &userS, nullptr, nullptr);
+}
 
-  Run r;
-  r.m = &m;
-  r.n = n;
-  r.Ap = Bp;
-  for (int i = 0; i < 9; ++i) r.W[i] = base + L.w_off[i];
-  r.stream = stream;
-  r.launched = 0;
-  void* Q[4];
-  for (int i = 0; i < 4; ++i) Q[i] = base + L.q_off[i];
-  const Target userC{C, ldc, (int)n, m.user_f64};
-  const Target userS{S, lds, (int)n, m.user_f64};
-  const int s = plan.s;
-  if (s == 0) {
-    r.Cout = userC;
-    r.Sout = userS;
-  } else {
-    r.Cout = internal(Q[1], m, m.sq_f64);
-    r.Sout = internal(Q[0], m, m.sq_f64);
+sincosm_status sincosm_wave_block_eval(int64_t n, int dtype, const void* A, int64_t lda, double t, void* E,
+                                       int64_t lde, int acc, int prod, void* ws, size_t ws_bytes,
+                                       sincosm_plan* plan_host, void* stream) {
+  WaveCall c;
+  SC_TRY(wave_check(n, dtype, A, lda, t, acc, prod, c.m));
+  if (n == 0) { empty_plan(acc, plan_host); return SINCOSM_OK; }
+  if (!E || lde < 2 * n) return SINCOSM_E_ARG;
+  const size_t es = dtype == SINCOSM_F64 ? 8 : 4;
+  {
+    const char* a0 = (const char*)A;
+    const char* a1 = a0 + ((size_t)(n - 1) * lda + n) * es;
+    const char* e0 = (const char*)E;
+    const char* e1 = e0 + ((size_t)(2 * n - 1) * lde + 2 * n) * es;
+    if (a0 < e1 && e0 < a1) return SINCOSM_E_ARG;
   }
-  const double bs = ldexp(1.0, -2 * s);
-  const double ts = ldexp(t, -s);
-  SC_TRY(run_wave_scheme(r, plan.level, bs, ts));
-  for (int i = 0; i < s; ++i) {
-    void* Sc = Q[(i & 1) ? 2 : 0];
-    void* Cc = Q[(i & 1) ? 3 : 1];
-    const bool last = (i == s - 1);
-    const Target Sn = last ? userS : internal(Q[(i & 1) ? 0 : 2], m, m.sq_f64);
-    const Target Cn = last ? userC : internal(Q[(i & 1) ? 1 : 3], m, m.sq_f64);
-    SC_TRY(wave_double_angle(r, Cc, Sc, Cn, Sn));
+  SC_TRY(wave_prologue(n, A, lda, t, acc, ws, ws_bytes, stream, c));
+  if (plan_host) *plan_host = c.plan;
+  if (c.plan.status != SINCOSM_OK) {
+    SC_TRY(launch_fill_nan_rect(2 * n, 2 * n, E, lde, c.m.user_f64, c.stream));
+    return SINCOSM_E_NONFINITE;
   }
-  return SINCOSM_OK;
+  const void* Cf = nullptr;
+  const void* Sf = nullptr;
+  SC_TRY(wave_body(c, n, t, nullptr, nullptr, &Cf, &Sf));
+  // A (unscaled) padded into the ping-pong pair that does not hold the result
+  const Modes& m = c.m;
+  void* Q0 = c.base + c.L.q_off[0];
+  void* Q2 = c.base + c.L.q_off[2];
+  void* Ap = (Sf == Q0) ? Q2 : Q0;
+  SC_TRY(launch_convert_pad(n, m.np, A, lda, m.user_f64, Ap, m.sq_f64, c.stream));
+  // one launch: D = A s; E21 = -D, E11 = E22 = c, E12 = s
+  char* e = (char*)E;
+  const Target E11{e, lde, (int)n, m.user_f64};
+  const Target E12{e + (size_t)n * es, lde, (int)n, m.user_f64};
+  const Target E21{e + (size_t)n * lde * es, lde, (int)n, m.user_f64};
+  const Target E22{e + ((size_t)n * lde + n) * es, lde, (int)n, m.user_f64};
+  Problem p = make_problem((int)n);
+  add_seg(p, Ap, Sf, m.np);
+  add_in(p, Cf, m.np);
+  add_in(p, Sf, m.np);
+  add_out(p, E21, -1.0, 0.0, {});
+  add_out(p, E11, 0.0, 0.0, {1.0, 0.0});
+  add_out(p, E22, 0.0, 0.0, {1.0, 0.0});
+  add_out(p, E12, 0.0, 0.0, {0.0, 1.0});
+  const TimingMark tm = timing_begin(SINCOSM_TIMING_SCHEME, c.stream);
+  const sincosm_status st = launch_gemm(m.sq, m.tile, one(p, (int)m.np), c.stream);
+  timing_end(tm, c.stream);
+  return st;
 }
 
 }  // extern "C"

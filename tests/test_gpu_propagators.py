@@ -1,0 +1,235 @@
+"""GPU parity of the propagators (eq:unitary, eq:symplectic of Section 1) against the oracle.
+
+sincosm_expi_eval: U = e^{-itA} = cos(tA) - i sin(tA) as complex128 / complex64.
+sincosm_wave_block_eval: E = e^{tM}, M = [[0, I], [-A, 0]], 2n x 2n.
+Bars: relative Frobenius error <= 1e-12 against the float64 oracle (the paper's schemes
+with the same plan, and the independent Taylor references) on the double-accuracy float64
+path; plan integers equal the oracle's; 5e-6 (scaled by 2^s / 16) for float32 storage."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import plan as P
+from oracle import propagators as Pr
+from oracle import wave as Wv
+from tests.conftest import rel_fro
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2010_00465_amd as sc
+    return torch, sc
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def run_expi(env, A_np, t, accuracy="double", products="native", dtype=None):
+    torch, sc = env
+    A = torch.from_numpy(np.ascontiguousarray(A_np)).cuda()
+    if dtype is not None:
+        A = A.to(dtype)
+    U = torch.empty(A.shape, dtype=torch.complex128 if A.dtype == torch.float64 else torch.complex64,
+                    device="cuda")
+    plan = sc.sincosm_expi_eval(A, t, U, accuracy, products)
+    torch.cuda.synchronize()
+    return U.cpu().numpy().astype(np.complex128), plan
+
+
+def run_block(env, A_np, t, accuracy="double", products="native", dtype=None):
+    torch, sc = env
+    A = torch.from_numpy(np.ascontiguousarray(A_np)).cuda()
+    if dtype is not None:
+        A = A.to(dtype)
+    n = A.shape[0]
+    E = torch.empty(2 * n, 2 * n, dtype=A.dtype, device="cuda")
+    plan = sc.sincosm_wave_block_eval(A, t, E, accuracy, products)
+    torch.cuda.synchronize()
+    return E.cpu().double().numpy(), plan
+
+
+def expi_plan_ok(plan, A, t, acc="double"):
+    th = float(np.abs(float(t) * A).sum(0).max())
+    got = (plan.level, plan.s, plan.products)
+    return any(got == P.plan(th * f, acc) for f in (1.0, 1 - 1e-12, 1 + 1e-12))
+
+
+def wave_plan_ok(plan, A, t, acc="double"):
+    nb = float(np.abs((t * t) * A).sum(0).max())
+    got = (plan.level, plan.s, plan.products)
+    return any(got == Wv.wave_plan(nb * f, acc) for f in (1.0, 1 - 1e-12, 1 + 1e-12))
+
+
+# ---------------------------------------------------------------------------
+# e^{-itA}
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("family", ["gaussian", "symmetric", "laplacian1d"])
+@pytest.mark.parametrize("n", [33, 257])
+@pytest.mark.parametrize("e", [-6, -1, 1, 5, 9])
+def test_expi_parity(env, family, n, e):
+    say("expi", family, n, e)
+    t = 0.75
+    A = W.family(family, n, 2.0 ** e / t, key=(90, n, e + 20))
+    U, plan = run_expi(env, A, t)
+    assert expi_plan_ok(plan, A, t), plan
+    assert rel_fro(U, Pr.unitary_paper(A, t)) <= 1e-12
+    assert rel_fro(U, Pr.unitary(A, t)) <= 1e-12
+
+
+def test_expi_against_complex_expm(env):
+    import scipy.linalg
+    say("expi expm")
+    A = W.gaussian(80, 7.0, key=(91,))
+    U, _ = run_expi(env, A, 1.3)
+    assert rel_fro(U, scipy.linalg.expm(-1.3j * A)) <= 1e-12
+
+
+def test_expi_larger_n(env):
+    say("expi 1500")
+    A = W.symmetric_gaussian(1500, 40.0, key=(92,))
+    U, plan = run_expi(env, A, 0.5)
+    assert expi_plan_ok(plan, A, 0.5)
+    assert rel_fro(U, Pr.unitary_paper(A, 0.5)) <= 1e-12
+
+
+def test_expi_unitary_n4096(env):
+    """At full size, symmetric A: U U^H = I (scaled residual on the GPU)."""
+    torch, sc = env
+    say("expi 4096 unitarity")
+    n = 4096
+    A = torch.from_numpy(W.symmetric_gaussian(n, 64.0, key=(93, n))).cuda()
+    U = sc.expi(A, 2.0)
+    I = torch.eye(n, dtype=torch.complex128, device="cuda")
+    r = float((U @ U.conj().T - I).norm()) / n ** 0.5
+    assert r <= 8 * n * 2.0 ** -53, r
+
+
+def test_expi_t_zero_and_sign(env):
+    A = W.gaussian(90, 5.0, key=(94,))
+    U0, plan = run_expi(env, A, 0.0)
+    assert (plan.level, plan.s) == (3, 0)
+    assert np.array_equal(U0, np.eye(90))
+    Up, _ = run_expi(env, A, 1.1)
+    Um, _ = run_expi(env, A, -1.1)
+    assert np.array_equal(Um, Up.conj())
+
+
+def test_expi_strided_output(env):
+    torch, sc = env
+    A = torch.from_numpy(W.gaussian(50, 3.0, key=(95,))).cuda()
+    Ub = torch.zeros(60, 70, dtype=torch.complex128, device="cuda")
+    U = Ub[4:54, 9:59]
+    sc.sincosm_expi_eval(A, 0.8, U)
+    torch.cuda.synchronize()
+    assert rel_fro(U.cpu().numpy(), Pr.unitary_paper(A.cpu().numpy(), 0.8)) <= 1e-12
+    rest = Ub.cpu().numpy().copy()
+    rest[4:54, 9:59] = 0
+    assert not rest.any()
+
+
+def test_expi_nonfinite_and_errors(env):
+    torch, sc = env
+    A = torch.zeros(20, 20, dtype=torch.float64, device="cuda")
+    A[2, 5] = float("inf")
+    U = torch.zeros(20, 20, dtype=torch.complex128, device="cuda")
+    plan = sc.sincosm_expi_eval(A, 1.0, U, raise_nonfinite=False)
+    assert plan.status == -4
+    assert torch.isnan(U.real).all() and torch.isnan(U.imag).all()
+    A[2, 5] = 0.0
+    with pytest.raises(sc.SincosmError):
+        sc.sincosm_expi_eval(A, float("nan"), U)
+
+
+@pytest.mark.parametrize("n,e", [(64, 1), (300, 6)])
+def test_expi_float32(env, n, e):
+    import torch
+    say("expi f32", n, e)
+    A32 = W.gaussian(n, 2.0 ** e, key=(96, n)).astype(np.float32)
+    U, plan = run_expi(env, A32, 1.0, accuracy="single", dtype=torch.float32)
+    assert expi_plan_ok(plan, A32.astype(np.float64), 1.0, "single")
+    tol = 5e-6 * max(1, 2 ** plan.s / 16)
+    assert rel_fro(U, Pr.unitary(A32.astype(np.float64), 1.0)) <= tol
+
+
+# ---------------------------------------------------------------------------
+# e^{tM}, M = [[0, I], [-A, 0]]
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("family", ["gaussian", "symmetric", "laplacian1d"])
+@pytest.mark.parametrize("n", [33, 257])
+@pytest.mark.parametrize("e", [-8, -2, 1, 4, 8])
+def test_block_parity(env, family, n, e):
+    say("block", family, n, e)
+    t = 1.3
+    A = W.family(family, n, 2.0 ** e / (t * t), key=(97, n, e + 20))
+    E, plan = run_block(env, A, t)
+    assert wave_plan_ok(plan, A, t), plan
+    assert rel_fro(E, Pr.symplectic_paper(A, t)) <= 1e-12
+    assert rel_fro(E, Pr.symplectic(A, t)) <= 1e-12
+
+
+def test_block_against_expm(env):
+    import scipy.linalg
+    say("block expm")
+    n = 70
+    A = W.gaussian(n, 9.0, key=(98,))
+    t = 0.9
+    E, _ = run_block(env, A, t)
+    M = np.zeros((2 * n, 2 * n))
+    M[:n, n:] = np.eye(n)
+    M[n:, :n] = -A
+    assert rel_fro(E, scipy.linalg.expm(t * M)) <= 1e-12
+
+
+def test_block_semigroup_n4096(env):
+    """At full size: e^{2tM} = (e^{tM})^2 from two independent calls (different plans)."""
+    torch, sc = env
+    say("block 4096 semigroup")
+    n = 4096
+    A = torch.from_numpy(W.laplacian_2d(64, 64.0)).cuda()
+    E1 = sc.wave_block(A, 0.5)
+    E2 = sc.wave_block(A, 1.0)
+    r = float((E1 @ E1 - E2).norm() / (E1.norm() ** 2))
+    assert r <= 8 * 2 * n * 2.0 ** -53, r
+
+
+def test_block_t_zero(env):
+    A = W.gaussian(40, 3.0, key=(99,))
+    E, _ = run_block(env, A, 0.0)
+    assert np.array_equal(E, np.eye(80))
+
+
+def test_block_strided_and_errors(env):
+    torch, sc = env
+    A = torch.from_numpy(W.gaussian(30, 2.0, key=(100,))).cuda()
+    Eb = torch.zeros(70, 75, dtype=torch.float64, device="cuda")
+    E = Eb[5:65, 8:68]
+    sc.sincosm_wave_block_eval(A, 0.7, E)
+    torch.cuda.synchronize()
+    assert rel_fro(E.cpu().numpy(), Pr.symplectic_paper(A.cpu().numpy(), 0.7)) <= 1e-12
+    rest = Eb.cpu().numpy().copy()
+    rest[5:65, 8:68] = 0
+    assert not rest.any()
+    An = A.clone()
+    An[0, 0] = float("nan")
+    plan = sc.sincosm_wave_block_eval(An, 0.7, E, raise_nonfinite=False)
+    assert plan.status == -4 and torch.isnan(E).all()
+    with pytest.raises(sc.SincosmError):
+        sc.sincosm_wave_block_eval(A, float("inf"), E)
+
+
+def test_block_float32(env):
+    import torch
+    say("block f32")
+    A32 = W.gaussian(200, 50.0, key=(101,)).astype(np.float32)
+    E, plan = run_block(env, A32, 1.0, accuracy="single", dtype=torch.float32)
+    tol = 5e-6 * max(1, 2 ** plan.s / 16)
+    assert rel_fro(E, Pr.symplectic(A32.astype(np.float64), 1.0)) <= tol

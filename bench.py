@@ -40,8 +40,8 @@ def parse():
     ap.add_argument("--n", type=int, default=N)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the batched, backward, precision-tier and wave measurements")
-    ap.add_argument("--only", choices=["batched", "backward", "tiers", "wave"],
+                    help="skip the batched, backward, precision-tier, wave and propagator measurements")
+    ap.add_argument("--only", choices=["batched", "backward", "tiers", "wave", "propagators"],
                     help="run and print only one of the secondary measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run sincosm_matmul once at --n: its two pad/convert copy kernels read and "
@@ -226,6 +226,45 @@ def bench_wave(torch, sc, W):
     return out
 
 
+def bench_propagators(torch, sc, W):
+    """n = 4096 float64 propagators against torch.linalg.matrix_exp on the same operator.
+
+    e^{-itA} (eq:unitary): symmetric Gaussian A with ||A||_1 = 64 and the 2-D Laplacian with
+    ||A||_1 = 64, t = 1: sincosm_expi_eval (real products, two per double-angle step) against
+    matrix_exp of the complex128 matrix -itA (a general exponential with complex products).
+    e^{tM} (eq:symplectic): the 2-D Laplacian, t = 1: sincosm_wave_block_eval (n x n products)
+    against matrix_exp of the real 2n x 2n block M. Reported: times, the ratio, and the relative
+    difference of the two results."""
+    n = 4096
+    out = {"workload": "n=4096 float64; library comparison: torch.linalg.matrix_exp on the same operator"}
+    ws = torch.empty(sc.workspace_size(n, torch.float64), dtype=torch.uint8, device="cuda")
+    ops = {"symmetric_gaussian": torch.from_numpy(W.symmetric_gaussian(n, 64.0, key=(6, n))).cuda(),
+           "laplacian2d": torch.from_numpy(W.laplacian_2d(64, 64.0)).cuda()}
+    for name, A in ops.items():
+        U = torch.empty(n, n, dtype=torch.complex128, device="cuda")
+        p = sc.sincosm_expi_eval(A, 1.0, U, ws=ws)
+        t_ours = _elapsed(torch, lambda: sc.sincosm_expi_eval(A, 1.0, U, ws=ws), 3)
+        Z = (-1j) * A.to(torch.complex128)
+        R = torch.linalg.matrix_exp(Z)
+        t_ref = _elapsed(torch, lambda: torch.linalg.matrix_exp(Z), 2)
+        out[f"expi_{name}"] = {"ms": 1e3 * t_ours, "plan": [p.level, p.s], "real_products": p.products,
+                               "matrix_exp_complex128_ms": 1e3 * t_ref, "speedup": t_ref / t_ours,
+                               "rel_diff": float((U - R).norm() / R.norm())}
+    A = ops["laplacian2d"]
+    E = torch.empty(2 * n, 2 * n, dtype=torch.float64, device="cuda")
+    p = sc.sincosm_wave_block_eval(A, 1.0, E, ws=ws)
+    t_ours = _elapsed(torch, lambda: sc.sincosm_wave_block_eval(A, 1.0, E, ws=ws), 3)
+    M = torch.zeros(2 * n, 2 * n, dtype=torch.float64, device="cuda")
+    M[:n, n:] = torch.eye(n, dtype=torch.float64, device="cuda")
+    M[n:, :n] = -A
+    R = torch.linalg.matrix_exp(M)
+    t_ref = _elapsed(torch, lambda: torch.linalg.matrix_exp(M), 2)
+    out["block_laplacian2d"] = {"ms": 1e3 * t_ours, "plan": [p.level, p.s], "products_n": p.products + 1,
+                                "matrix_exp_2n_ms": 1e3 * t_ref, "speedup": t_ref / t_ours,
+                                "rel_diff": float((E - R).norm() / R.norm())}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -241,7 +280,7 @@ def main():
         import paper_2010_00465_amd as sc
         import workloads as W
         fn = {"batched": bench_batched, "backward": bench_backward, "tiers": bench_tiers,
-              "wave": bench_wave}[args.only]
+              "wave": bench_wave, "propagators": bench_propagators}[args.only]
         print(json.dumps({args.only: fn(torch, sc, W)}))
         return
     import torch
@@ -317,6 +356,7 @@ def main():
         extras["backward"] = bench_backward(torch, sc, W)
         extras["tiers"] = bench_tiers(torch, sc, W)
         extras["wave"] = bench_wave(torch, sc, W)
+        extras["propagators"] = bench_propagators(torch, sc, W)
 
     out = {
         "metric": "cos+sin evals/sec & % MFMA peak at n=4096 FP64; rel err vs FP64 oracle",

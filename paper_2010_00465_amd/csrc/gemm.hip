@@ -13,8 +13,9 @@
 //  * 16x16x4 MFMA (f64 or f32); each wave owns a WTM x WTN sub-tile as
 //    FM x FN MFMA blocks held in accumulator registers.
 //  * Operand tiles are staged through LDS, double buffered, one barrier per
-//    BK step; the next tile's global loads are issued before the MFMAs of the
-//    current one so their latency hides behind the matrix core.
+//    BK step placed before the step's last substep of MFMAs; the next tile's
+//    global loads are issued before the MFMAs of the current one so their
+//    latency hides behind the matrix core.
 //  * LDS layouts: A as [m][k] with row pitch BK+1, B as [k][n] with row pitch
 //    BN+16, so the 16-lane groups that feed one MFMA read distinct banks.
 //  * All operands are internal buffers padded with zeros to a multiple of the
@@ -78,6 +79,21 @@ __device__ inline void tile_coords(int np, int BM, int BN, int nprob, int& p, in
   tn = in_group / rows;
 }
 
+// The k loop. Each BK step is KK = BK/4 substeps of FM x FN MFMAs. The
+// operand fragments of a substep are read from LDS one substep ahead (double
+// buffered in registers). The global loads of the next BK step are issued at
+// the start of the current one; at its last substep they are stored to the
+// other LDS buffer, the workgroup synchronises, and the first fragments of the
+// next step are read while the last substep's MFMAs run, so the barrier sits
+// between MFMAs that are already queued. The segment cursor of the global
+// loads (pointers, k offset, operand scales) is uniform state advanced
+// incrementally.
+//
+// LDS hazards (two buffers): the store into buffer (k+1)&1 happens in step k
+// before barrier B_k, after the storing wave passed B_{k-1}; every read of that
+// buffer (step k-1: the prefetch after B_{k-2} and the substep reads before
+// B_{k-1}) completed before its wave reached B_{k-1}. Reads of buffer (k+1)&1
+// in step k+1 start after B_k, when all stores into it are complete.
 template <typename T, int BM, int BN, int BK, int WGM, int WGN, int WPE>
 __global__ __launch_bounds__(WGM * WGN * 64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void gemm_kernel(const GemmLaunch g) {
@@ -89,9 +105,9 @@ void gemm_kernel(const GemmLaunch g) {
   constexpr int FM = WTM / 16, FN = WTN / 16;
   constexpr int LDA = BK + 1, LDB = BN + 16;
   constexpr int VEC = M::VEC;
+  constexpr int KK = BK / 4;
   constexpr int A_LOADS = BM * BK / VEC / NT;
   constexpr int B_LOADS = BK * BN / VEC / NT;
-  // epilogue staging: one band of WTM rows (the rows of one row of waves) at a time
   constexpr int LDE = BN + VEC;
   constexpr int STAGE_ELEMS = 2 * (BM * LDA + BK * LDB);
   constexpr int EPI_ELEMS = WTM * LDE;
@@ -99,7 +115,7 @@ void gemm_kernel(const GemmLaunch g) {
   static_assert(FM >= 1 && FN >= 1 && WTM % 16 == 0 && WTN % 16 == 0, "wave tile");
   static_assert(A_LOADS >= 1 && A_LOADS * VEC * NT == BM * BK, "A staging");
   static_assert(B_LOADS >= 1 && B_LOADS * VEC * NT == BK * BN, "B staging");
-  static_assert(BK % 4 == 0 && BK % VEC == 0 && BN % VEC == 0, "k tiling");
+  static_assert(BK % 8 == 0 && BK % VEC == 0 && BN % VEC == 0, "k tiling (even substep count)");
 
   __shared__ __attribute__((aligned(16))) T smem[SMEM_ELEMS];
   T* const As0 = smem;
@@ -123,8 +139,6 @@ void gemm_kernel(const GemmLaunch g) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[i][j][r] = (T)0;
 
-  // Per-thread staging offsets (elements), fixed for the whole k loop. All
-  // operands are np x np internal buffers with leading dimension np.
   int offA[A_LOADS], offB[B_LOADS], ldsA[A_LOADS], ldsB[B_LOADS];
 #pragma unroll
   for (int i = 0; i < A_LOADS; ++i) {
@@ -141,33 +155,55 @@ void gemm_kernel(const GemmLaunch g) {
     ldsB[i] = r * LDB + c;
   }
 
-  const int nk = np / BK;
-  const int nkt = P.nseg * nk;
-  vec_t ra[A_LOADS], rb[B_LOADS];
+  const int nseg = P.nseg;
+  const int nkt = nseg * (np / BK);
   const int64_t a_tile = (int64_t)tile_m * BM * np;
   const int64_t b_tile = (int64_t)tile_n * BN;
 
-  auto gload = [&](int kt) {
-    const int sidx = kt / nk;
-    const int k0 = (kt - sidx * nk) * BK;
-    const T* L = (const T*)P.seg[sidx].L + a_tile + k0;
-    const T* R = (const T*)P.seg[sidx].R + b_tile + (int64_t)k0 * np;
+  // uniform cursor: the next tile to load
+  int cseg = 0, ck0 = 0;
+  const T* Lc = nullptr;
+  const T* Rc = nullptr;
+  T lsc = (T)1, rsc = (T)1;
+  if (nseg > 0) {
+    Lc = (const T*)P.seg[0].L + a_tile;
+    Rc = (const T*)P.seg[0].R + b_tile;
+    lsc = (T)P.seg[0].lscale;
+    rsc = (T)P.seg[0].rscale;
+  }
+  T pl = (T)1, pr = (T)1;   // scales of the tile held in ra / rb
+  vec_t ra[A_LOADS], rb[B_LOADS];
+
+  auto gload = [&]() {
+    const T* L = Lc + ck0;
+    const T* R = Rc + (int64_t)ck0 * np;
 #pragma unroll
     for (int i = 0; i < A_LOADS; ++i) ra[i] = *(const vec_t*)(L + offA[i]);
 #pragma unroll
     for (int i = 0; i < B_LOADS; ++i) rb[i] = *(const vec_t*)(R + offB[i]);
+    pl = lsc;
+    pr = rsc;
+    ck0 += BK;
+    if (ck0 == np) {
+      ck0 = 0;
+      ++cseg;
+      if (cseg < nseg) {
+        Lc = (const T*)P.seg[cseg].L + a_tile;
+        Rc = (const T*)P.seg[cseg].R + b_tile;
+        lsc = (T)P.seg[cseg].lscale;
+        rsc = (T)P.seg[cseg].rscale;
+      }
+    }
   };
 
-  auto lstore = [&](int buf, int kt) {
-    const Seg& S = P.seg[kt / nk];
+  auto lstore = [&](int buf) {
     T* as = As0 + buf * (BM * LDA);
     T* bs = Bs0 + buf * (BK * LDB);
-    if (S.lscale != 1.0 || S.rscale != 1.0) {
-      const T ls = (T)S.lscale, rs = (T)S.rscale;
+    if (pl != (T)1 || pr != (T)1) {
 #pragma unroll
-      for (int i = 0; i < A_LOADS; ++i) ra[i] = ra[i] * ls;
+      for (int i = 0; i < A_LOADS; ++i) ra[i] = ra[i] * pl;
 #pragma unroll
-      for (int i = 0; i < B_LOADS; ++i) rb[i] = rb[i] * rs;
+      for (int i = 0; i < B_LOADS; ++i) rb[i] = rb[i] * pr;
     }
 #pragma unroll
     for (int i = 0; i < A_LOADS; ++i)
@@ -177,31 +213,42 @@ void gemm_kernel(const GemmLaunch g) {
     for (int i = 0; i < B_LOADS; ++i) *(vec_t*)(bs + ldsB[i]) = rb[i];
   };
 
-  if (nkt > 0) {   // nseg == 0: epilogue-only launch (linear combination of inputs)
-    gload(0);
-    lstore(0, 0);
+  T fa[2][FM], fb[2][FN];
+  auto lread = [&](int buf, int kk, T (&a)[FM], T (&b)[FN]) {
+    const T* as = As0 + buf * (BM * LDA) + (wm * WTM + lr) * LDA + lg + kk * 4;
+    const T* bs = Bs0 + buf * (BK * LDB) + (lg + kk * 4) * LDB + wn * WTN + lr;
+#pragma unroll
+    for (int i = 0; i < FM; ++i) a[i] = as[i * 16 * LDA];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) b[j] = bs[j * 16];
+  };
+
+  if (nkt > 0) {
+    gload();
+    lstore(0);
   }
   __syncthreads();
+  if (nkt > 0) lread(0, 0, fa[0], fb[0]);
 
   for (int kt = 0; kt < nkt; ++kt) {
     const int cur = kt & 1;
-    if (kt + 1 < nkt) gload(kt + 1);
-    const T* as = As0 + cur * (BM * LDA) + (wm * WTM + lr) * LDA + lg;
-    const T* bs = Bs0 + cur * (BK * LDB) + lg * LDB + wn * WTN + lr;
+    const bool more = kt + 1 < nkt;
+    if (more) gload();
 #pragma unroll
-    for (int kk = 0; kk < BK / 4; ++kk) {
-      T a[FM], b[FN];
-#pragma unroll
-      for (int i = 0; i < FM; ++i) a[i] = as[i * 16 * LDA + kk * 4];
-#pragma unroll
-      for (int j = 0; j < FN; ++j) b[j] = bs[kk * 4 * LDB + j * 16];
+    for (int kk = 0; kk < KK; ++kk) {
+      const int f = kk & 1;
+      if (kk + 1 < KK) {
+        lread(cur, kk + 1, fa[f ^ 1], fb[f ^ 1]);
+      } else {
+        if (more) lstore(cur ^ 1);
+        __syncthreads();
+        if (more) lread(cur ^ 1, 0, fa[f ^ 1], fb[f ^ 1]);
+      }
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) acc[i][j] = M::mma(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < FN; ++j) acc[i][j] = M::mma(fa[f][i], fb[f][j], acc[i][j]);
     }
-    if (kt + 1 < nkt) lstore(cur ^ 1, kt + 1);
-    __syncthreads();
   }
 
   epilogue_bands<T, BM, BN, WGM, WGN, M>(P, np, tile_m, tile_n, acc, smem);
@@ -236,6 +283,7 @@ static sincosm_status launch_cfg(const GemmLaunch& g, hipStream_t stream) {
   SC_HIP(hipGetLastError());
   return SINCOSM_OK;
 }
+
 
 // ----------------------------------------------------------------------------
 // Kernel configurations the autotuner chooses among. Each entry: tile rows and

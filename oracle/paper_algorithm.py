@@ -28,17 +28,17 @@ from .reference import norm1
 __all__ = ["sincosm", "plan_for"]
 
 
-def plan_for(A: np.ndarray, accuracy: str = "double"):
-    """(level, s, products) for A."""
-    return _plan.plan(norm1(A), accuracy)
+def plan_for(A: np.ndarray, accuracy: str = "double", extended: bool = False):
+    """(level, s, products) for A (``extended``: the 5-product scheme is a candidate too)."""
+    return _plan.plan(norm1(A), accuracy, extended)
 
 
-def sincosm(A: np.ndarray, accuracy: str = "double", dtype=np.float64, return_plan=False):
+def sincosm(A: np.ndarray, accuracy: str = "double", dtype=np.float64, return_plan=False, extended=False):
     """cos(A), sin(A) by the paper's method in ``dtype`` arithmetic."""
     A = np.asarray(A, dtype=dtype)
     n = A.shape[0]
     I = np.eye(n, dtype=dtype)
-    level, s, products = plan_for(A, accuracy)
+    level, s, products = plan_for(A, accuracy, extended)
     X = A * dtype(2.0) ** (-s)
     C, S = _schemes.evaluate(level, X, dtype=dtype)
     for _ in range(s):

@@ -14,6 +14,11 @@ Readings taken (the paper only shows the resulting staircase in its Figure 1):
   smaller s. s is found by exact halving, never through a floating log2.
 * The 7-product sine bound in double precision is 1.8548 (re-derived from the
   printed coefficients) instead of the printed 1.97.
+* Extended plan (opt-in, not the paper's tables): the 5-product scheme of
+  Algorithm4cA + Algorithm5sA joins the candidates. Its sine bound (T^s_9,
+  derived as for the tables: 1.7401e-1 double, 1.0812 single) exceeds its
+  cosine's, so its combined bound is the printed T^c_8 bound of Tables 1-2:
+  1.1495e-1 (double), 8.5756e-1 (single).
 
 Pins (tests/test_oracle_plan.py): a brute-force enumeration over all
 (level, s) candidates written independently, and the table constants against
@@ -23,15 +28,17 @@ from __future__ import annotations
 
 import math
 
-__all__ = ["THETA", "PRODUCTS", "plan", "scaling_for"]
+__all__ = ["THETA", "THETA_LEVEL5", "PRODUCTS", "plan", "scaling_for"]
 
-PRODUCTS = {3: 3, 4: 4, 6: 6, 7: 7}
+PRODUCTS = {3: 3, 4: 4, 5: 5, 6: 6, 7: 7}
 
 # min(theta^c, theta^s) per scheme; Table 1 (u = 2^-53) and Table 2 (u = 2^-24).
 THETA = {
     "double": {3: 6.5633e-3, 4: 8.0438e-2, 6: 9.8108e-1, 7: 1.8548},
     "single": {3: 1.8709e-1, 4: 7.492e-1, 6: 2.9935, 7: 4.3819},
 }
+# combined bound of the 5-product scheme (extended plan only)
+THETA_LEVEL5 = {"double": 1.1495e-1, "single": 8.5756e-1}
 
 
 def scaling_for(theta: float, limit: float) -> int:
@@ -44,16 +51,20 @@ def scaling_for(theta: float, limit: float) -> int:
     return s
 
 
-def plan(theta: float, accuracy: str = "double"):
+def plan(theta: float, accuracy: str = "double", extended: bool = False):
     """Return (level, s, products) for a matrix of 1-norm ``theta``.
 
+    ``extended`` adds the 5-product scheme to the candidates.
     Raises ValueError for a non-finite or negative norm.
     """
     if not math.isfinite(theta) or theta < 0:
         raise ValueError("norm must be finite and >= 0")
+    bounds = dict(THETA[accuracy])
+    if extended:
+        bounds[5] = THETA_LEVEL5[accuracy]
     best = None
-    for level in (3, 4, 6, 7):
-        s = scaling_for(theta, THETA[accuracy][level])
+    for level in sorted(bounds):
+        s = scaling_for(theta, bounds[level])
         cand = (PRODUCTS[level] + 2 * s, s, level)
         if best is None or cand[:2] < best[:2]:
             best = cand

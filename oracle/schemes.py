@@ -5,6 +5,8 @@ that evaluates an approximation of cos(A) and sin(A) simultaneously:
 
 * k = 3: equations (Algorithm3cA) and (Algorithm3sA): T^c_4 and T^s_5.
 * k = 4: equations (Algorithm4cA) and (Algorithm4sA): T^c_8 and T^s_{7,9}.
+* k = 5: (Algorithm4cA) with the sine raised to order nine by (Algorithm5sA):
+  T^c_8 and T^s_9 (not in Tables 1-2; used only by the extended plan).
 * k = 6: equations (Algorithm6cA) with coefficients (eq:cosm8), and
   (Algorithm6sA) with the rational z_0..z_8: T^c_16 and T^s_{17,25}.
 * k = 7: equations (Algorithm7cA) with (Coefs7cA), and (Algorithm7sA) with
@@ -41,11 +43,11 @@ from fractions import Fraction
 import mpmath
 import numpy as np
 
-__all__ = ["Poly", "coefficients", "float_coefficients", "level3", "level4",
+__all__ = ["Poly", "coefficients", "float_coefficients", "level3", "level4", "level5",
            "level6", "level7", "SCHEMES", "PRODUCTS", "CountingMatrix"]
 
-# Products per scheme (Tables 1 and 2, row Pi_{2m}).
-PRODUCTS = {3: 3, 4: 4, 6: 6, 7: 7}
+# Products per scheme (Tables 1 and 2, row Pi_{2m}; k = 5 from Algorithm5sA).
+PRODUCTS = {3: 3, 4: 4, 5: 5, 6: 6, 7: 7}
 
 
 def coefficients(dps: int = 60):
@@ -246,6 +248,18 @@ def level4(A, I, c=None):
     return Tc, Ts
 
 
+def level5(A, I, c=None):
+    """k = 5: T^c_8 of Algorithm4cA (three products) and T^s_9 of Algorithm5sA, whose own A_8
+    uses 1/7! and 1/9! (one product) before the final product with A."""
+    A2 = A @ A
+    A4 = A2 @ A2
+    A8c = A4 @ (-A2 / 720 + A4 / 40320)
+    Tc = I - A2 / 2 + A4 / 24 + A8c
+    A8s = A4 @ (-A2 / 5040 + A4 / 362880)
+    Ts = A @ (I - A2 / 6 + A4 / 120 + A8s)
+    return Tc, Ts
+
+
 def level6(A, I, c):
     """k = 6: T^c_16 with four products (Algorithm6cA), T^s_{17,25} with two more (Algorithm6sA)."""
     x, z = c["x"], c["z6"]
@@ -275,7 +289,7 @@ def level7(A, I, c):
     return Tc, Ts
 
 
-SCHEMES = {3: level3, 4: level4, 6: level6, 7: level7}
+SCHEMES = {3: level3, 4: level4, 5: level5, 6: level6, 7: level7}
 
 
 def scheme_polynomials(level: int, dps: int = 60):

@@ -101,8 +101,9 @@ def test_plan_tie_rule_caught():
     assert P.plan(t) == (6, 0, 6)
     lv, s, cost = P.plan(t)
     cands = []
-    for level, pi in P.PRODUCTS.items():
-        ss = P.scaling_for(t, P.THETA["double"][level])
+    for level, th in P.THETA["double"].items():
+        pi = P.PRODUCTS[level]
+        ss = P.scaling_for(t, th)
         cands.append((pi + 2 * ss, -ss, level))
     wrong = min(cands)
     assert (lv, s) != (wrong[2], -wrong[1]) or cost != wrong[0]

@@ -54,3 +54,17 @@ def test_float32_single_accuracy():
     Cr, Sr = R.sincosm(A32.astype(np.float64))
     assert rel_fro(C, Cr) <= 5e-5
     assert rel_fro(S, Sr) <= 5e-5
+
+
+@pytest.mark.parametrize("acc,theta,tol", [("double", 0.1, 1e-15), ("double", 0.1149, 1e-15),
+                                           ("single", 0.8, 2e-7)])
+def test_extended_level5_against_mpmath(acc, theta, tol):
+    """The 5-product scheme at the top of its band against mpmath's cosm/sinm at 40 digits."""
+    A = W.gaussian(8, theta, key=(30, int(theta * 1e5)))
+    C, S, plan = PA.sincosm(A, acc, return_plan=True, extended=True)
+    assert plan == (5, 0, 5)
+    with mpmath.workdps(40):
+        M = mpmath.matrix(A.tolist())
+        Cm = np.array(mpmath.cosm(M).tolist(), dtype=float)
+        Sm = np.array(mpmath.sinm(M).tolist(), dtype=float)
+    assert rel_fro(C, Cm) <= tol and rel_fro(S, Sm) <= tol

@@ -15,8 +15,9 @@ from oracle import schemes
 GOLD = os.path.join(os.path.dirname(__file__), "golden", "theta_tables.json")
 
 # (level) -> (cosine exact through x^k, sine exact through x^k) as stated in
-# Section 2.1: T^c_4/T^s_5, T^c_8/T^s_7, T^c_16/T^s_17, T^c_24/T^s through x^21.
-ORDERS = {3: (5, 6), 4: (9, 8), 6: (17, 18), 7: (25, 22)}
+# Section 2.1: T^c_4/T^s_5, T^c_8/T^s_7, T^c_8/T^s_9 (Algorithm5sA), T^c_16/T^s_17,
+# T^c_24/T^s through x^21.
+ORDERS = {3: (5, 6), 4: (9, 8), 5: (9, 10), 6: (17, 18), 7: (25, 22)}
 
 
 def taylor(kind, k):
@@ -36,18 +37,18 @@ def max_rel_mismatch(poly, kind, upto):
     return worst
 
 
-@pytest.mark.parametrize("level", [3, 4, 6, 7])
+@pytest.mark.parametrize("level", [3, 4, 5, 6, 7])
 def test_scheme_matches_taylor(level):
     pc, ps = schemes.scheme_polynomials(level)
     oc, os_ = ORDERS[level]
     # level 7: coefficients printed to 20 digits; cancellation lifts the relative
     # residual of the highest matched orders to a few 1e-16 (absolute < 1e-35)
-    tol = 1e-30 if level in (3, 4, 6) else 1e-15
+    tol = 1e-30 if level in (3, 4, 5, 6) else 1e-15
     assert max_rel_mismatch(pc, "c", oc) <= tol
     assert max_rel_mismatch(ps, "s", os_) <= tol
 
 
-@pytest.mark.parametrize("level", [3, 4, 6, 7])
+@pytest.mark.parametrize("level", [3, 4, 5, 6, 7])
 def test_scheme_differs_at_next_order(level):
     """The first mismatch is exactly where the paper's orders end (x^23 for the k=7 sine)."""
     pc, ps = schemes.scheme_polynomials(level)
@@ -113,3 +114,14 @@ def test_float_scheme_on_scalar_matrix():
             C, S = schemes.evaluate(level, np.array([[x]]))
             assert abs(C[0, 0] - math.cos(x)) <= 8e-16   # truncation <= u plus a few roundings
             assert abs(S[0, 0] - math.sin(x)) <= 8e-16   # truncation <= u plus a few roundings
+
+
+def test_level5_product_count_and_shared_cosine():
+    """The 5-product scheme spends one product more than k = 4 (Algorithm5sA's own A_8) and
+    keeps the k = 4 cosine polynomial exactly."""
+    assert schemes.count_products(5) == 5
+    with mpmath.workdps(60):
+        c4, _ = schemes.scheme_polynomials(4)
+        c5, _ = schemes.scheme_polynomials(5)
+        for k in range(40):
+            assert c4.coeff(k) == c5.coeff(k)

@@ -69,3 +69,17 @@ def test_bound_is_monotone_and_tight():
     b = lambda t: sum(abs(a) * mpmath.mpf(t) ** k for k, a in enumerate(alpha) if k >= k0)
     assert b(th * (1 - 1e-12)) <= theta.U_DOUBLE   # th is rounded to float64
     assert b(th * (1 + 1e-9)) > theta.U_DOUBLE
+
+
+def test_level5_bounds():
+    """Extended plan: the 5-product sine (T^s_9 of Algorithm5sA) bound exceeds the shared T^c_8
+    bound, so the combined bound is the printed T^c_8 value of Tables 1-2 (column 2m = 8)."""
+    g = printed()
+    i8 = g["columns_products"].index(4)
+    for acc, u in (("double", theta.U_DOUBLE), ("single", theta.U_SINGLE)):
+        c5 = theta.theta(5, "c", u)
+        s5 = theta.theta(5, "s", u)
+        assert s5 > c5
+        assert c5 == theta.theta(4, "c", u)
+        assert plan.THETA_LEVEL5[acc] == g[acc]["cos"][i8]
+        assert agree_to_printed_digits(c5, plan.THETA_LEVEL5[acc])

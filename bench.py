@@ -40,8 +40,9 @@ def parse():
     ap.add_argument("--n", type=int, default=N)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the batched, backward, precision-tier, wave and propagator measurements")
-    ap.add_argument("--only", choices=["batched", "backward", "tiers", "wave", "propagators"],
+                    help="skip the batched, backward, precision-tier, wave, propagator and 5-product-scheme "
+                         "measurements")
+    ap.add_argument("--only", choices=["batched", "backward", "tiers", "wave", "propagators", "level5"],
                     help="run and print only one of the secondary measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run sincosm_matmul once at --n: its two pad/convert copy kernels read and "
@@ -226,6 +227,31 @@ def bench_wave(torch, sc, W):
     return out
 
 
+def bench_level5(torch, sc, W):
+    """n = 4096 Gaussian with ||A||_1 = 0.1 (double) and 0.8 (single accuracy), float64: the
+    paper's plan (6 products) against the extended plan with the 5-product scheme; relative
+    difference of the results."""
+    n = 4096
+    out = {"workload": "n=4096 float64 Gaussian; paper plan vs plan with the 5-product scheme"}
+    ws = torch.empty(sc.workspace_size(n, torch.float64), dtype=torch.uint8, device="cuda")
+    for acc, norm in (("double", 0.1), ("single", 0.8)):
+        A = torch.from_numpy(W.gaussian(n, norm, key=(7, n, int(norm * 10)))).cuda()
+        res = {}
+        outs = {}
+        for ext in (False, True):
+            C, S = torch.empty_like(A), torch.empty_like(A)
+            p = sc.sincosm_eval(A, C, S, acc, ws=ws, extended=ext)
+            t = _elapsed(torch, lambda: sc.sincosm_eval(A, C, S, acc, ws=ws, extended=ext), 5)
+            res["extended" if ext else "paper"] = {"ms": 1e3 * t, "plan": [p.level, p.s], "products": p.products}
+            outs[ext] = (C, S)
+        (C0, S0), (C1, S1) = outs[False], outs[True]
+        res["speedup"] = res["paper"]["ms"] / res["extended"]["ms"]
+        res["rel_diff_cos"] = float((C1 - C0).norm() / C0.norm())
+        res["rel_diff_sin"] = float((S1 - S0).norm() / S0.norm())
+        out[f"{acc}_norm_{norm}"] = res
+    return out
+
+
 def bench_propagators(torch, sc, W):
     """n = 4096 float64 propagators against torch.linalg.matrix_exp on the same operator.
 
@@ -280,7 +306,7 @@ def main():
         import paper_2010_00465_amd as sc
         import workloads as W
         fn = {"batched": bench_batched, "backward": bench_backward, "tiers": bench_tiers,
-              "wave": bench_wave, "propagators": bench_propagators}[args.only]
+              "wave": bench_wave, "propagators": bench_propagators, "level5": bench_level5}[args.only]
         print(json.dumps({args.only: fn(torch, sc, W)}))
         return
     import torch
@@ -357,6 +383,7 @@ def main():
         extras["tiers"] = bench_tiers(torch, sc, W)
         extras["wave"] = bench_wave(torch, sc, W)
         extras["propagators"] = bench_propagators(torch, sc, W)
+        extras["level5"] = bench_level5(torch, sc, W)
 
     out = {
         "metric": "cos+sin evals/sec & % MFMA peak at n=4096 FP64; rel err vs FP64 oracle",

@@ -57,6 +57,16 @@ typedef enum { SINCOSM_F64 = 0, SINCOSM_F32 = 1 } sincosm_dtype;
 /* Accuracy target of the plan: Table 1 bounds (u = 2^-53) or Table 2 (u = 2^-24). */
 typedef enum { SINCOSM_ACC_DOUBLE = 0, SINCOSM_ACC_SINGLE = 1 } sincosm_accuracy;
 
+/* Flag OR-ed into `acc` of sincosm_plan_host, sincosm_plan_device, sincosm_eval and
+ * sincosm_expi_eval: the plan also considers the 5-product scheme of Section 2.1
+ * (the 4-product cosine T^c_8 of Algorithm4cA with the order-nine sine T^s_9 of
+ * Algorithm5sA; combined bound = the printed T^c_8 bound, 1.1495e-1 double /
+ * 8.5756e-1 single, since its sine bound is larger). It is chosen only where it
+ * saves a product: ||A||_1 in (8.0438e-2, 1.1495e-1] double, (7.492e-1, 8.5756e-1]
+ * single. Without the flag the plan uses exactly the schemes of Tables 1-2. The
+ * batched, backward and wave entries reject the flag (SINCOSM_E_ARG). */
+enum { SINCOSM_PLAN_EXTENDED = 16 };
+
 /* Arithmetic of the polynomial-phase products (the scheme of step 3):
  *  NATIVE - the storage type (float64 MFMA for F64, float32 MFMA for F32);
  *  F32    - float32 MFMA products and float32 intermediates;
@@ -67,7 +77,8 @@ typedef enum { SINCOSM_ACC_DOUBLE = 0, SINCOSM_ACC_SINGLE = 1 } sincosm_accuracy
 typedef enum { SINCOSM_PROD_NATIVE = 0, SINCOSM_PROD_F32 = 1, SINCOSM_PROD_BF16X3 = 2 } sincosm_prod;
 
 /* The plan chosen for one matrix. level in {3,4,6,7} (= products of the
- * scheme), s = number of double-angle steps, products = level + 2 s, status =
+ * scheme; also 5 with SINCOSM_PLAN_EXTENDED; 2..5 for the wave entries),
+ * s = number of double-angle steps, products = level + 2 s, status =
  * SINCOSM_OK or SINCOSM_E_NONFINITE, norm1 = ||A||_1 as computed on device. */
 typedef struct {
   int32_t level;

@@ -54,21 +54,26 @@ def _require_cuda(*ts):
             raise ValueError("tensors must live on the GPU")
 
 
-def plan_host(norm1: float, accuracy: str = "double") -> Plan:
-    """The library's plan for a given 1-norm (host computation, same rule as the device)."""
+def _acc(accuracy: str, extended: bool = False) -> int:
+    return ACC[accuracy] | (_lib.PLAN_EXTENDED if extended else 0)
+
+
+def plan_host(norm1: float, accuracy: str = "double", extended: bool = False) -> Plan:
+    """The library's plan for a given 1-norm (host computation, same rule as the device).
+    ``extended`` adds the 5-product scheme (Algorithm4cA + Algorithm5sA) to the candidates."""
     p = Plan()
-    check(lib.sincosm_plan_host(float(norm1), ACC[accuracy], ctypes.byref(p)), "sincosm_plan_host")
+    check(lib.sincosm_plan_host(float(norm1), _acc(accuracy, extended), ctypes.byref(p)), "sincosm_plan_host")
     return p
 
 
-def plan_device(A: torch.Tensor, accuracy: str = "double") -> Plan:
+def plan_device(A: torch.Tensor, accuracy: str = "double", extended: bool = False) -> Plan:
     """The plan sincosm_eval would choose for A (1-norm and rule on the device)."""
     _require_cuda(A)
     n = A.shape[0]
     ws = _workspace(lib.sincosm_plan_workspace_size(n), A.device)
     p = Plan()
-    check(lib.sincosm_plan_device(n, _dtype_code(A), A.data_ptr(), _ld(A), ACC[accuracy], ws.data_ptr(),
-                                  ws.numel(), ctypes.byref(p), _stream(A)), "sincosm_plan_device")
+    check(lib.sincosm_plan_device(n, _dtype_code(A), A.data_ptr(), _ld(A), _acc(accuracy, extended),
+                                  ws.data_ptr(), ws.numel(), ctypes.byref(p), _stream(A)), "sincosm_plan_device")
     return p
 
 
@@ -83,8 +88,10 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 
 
 def sincosm_eval(A: torch.Tensor, C: torch.Tensor, S: torch.Tensor, accuracy: str = "double",
-                 products: str = "native", ws: torch.Tensor | None = None, raise_nonfinite=True) -> Plan:
-    """C-ABI sincosm_eval on torch tensors (writes C and S in place). Returns the plan."""
+                 products: str = "native", ws: torch.Tensor | None = None, raise_nonfinite=True,
+                 extended: bool = False) -> Plan:
+    """C-ABI sincosm_eval on torch tensors (writes C and S in place). Returns the plan.
+    ``extended``: the plan may also use the 5-product scheme."""
     _require_cuda(A, C, S)
     n = A.shape[0]
     dt = _dtype_code(A)
@@ -92,7 +99,7 @@ def sincosm_eval(A: torch.Tensor, C: torch.Tensor, S: torch.Tensor, accuracy: st
         ws = _workspace(workspace_size(n, A.dtype, accuracy, products), A.device)
     plan = Plan()
     st = lib.sincosm_eval(n, dt, A.data_ptr(), _ld(A), C.data_ptr(), _ld(C), S.data_ptr(), _ld(S),
-                          ACC[accuracy], PROD[products], ws.data_ptr(), ws.numel(), ctypes.byref(plan),
+                          _acc(accuracy, extended), PROD[products], ws.data_ptr(), ws.numel(), ctypes.byref(plan),
                           _stream(A))
     if st == _lib.E_NONFINITE and not raise_nonfinite:
         return plan
@@ -171,7 +178,8 @@ _COMPLEX_OF = {torch.float64: torch.complex128, torch.float32: torch.complex64}
 
 
 def sincosm_expi_eval(A: torch.Tensor, t: float, U: torch.Tensor, accuracy: str = "double",
-                      products: str = "native", ws: torch.Tensor | None = None, raise_nonfinite=True) -> Plan:
+                      products: str = "native", ws: torch.Tensor | None = None, raise_nonfinite=True,
+                      extended: bool = False) -> Plan:
     """C-ABI sincosm_expi_eval: U = e^{-itA} = cos(tA) - i sin(tA) (complex tensor, written in place)."""
     _require_cuda(A, U)
     n = A.shape[0]
@@ -181,8 +189,8 @@ def sincosm_expi_eval(A: torch.Tensor, t: float, U: torch.Tensor, accuracy: str 
         ws = _workspace(workspace_size(n, A.dtype, accuracy, products), A.device)
     plan = Plan()
     st = lib.sincosm_expi_eval(n, _dtype_code(A), A.data_ptr(), _ld(A), float(t), U.data_ptr(), U.stride(0),
-                               ACC[accuracy], PROD[products], ws.data_ptr(), ws.numel(), ctypes.byref(plan),
-                               _stream(A))
+                               _acc(accuracy, extended), PROD[products], ws.data_ptr(), ws.numel(),
+                               ctypes.byref(plan), _stream(A))
     if st == _lib.E_NONFINITE and not raise_nonfinite:
         return plan
     check(st, "sincosm_expi_eval")

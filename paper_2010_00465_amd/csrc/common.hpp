@@ -39,17 +39,33 @@ __host__ __device__ inline double plan_theta(int acc, int idx) {
   return acc == SINCOSM_ACC_SINGLE ? sgl[idx] : dbl[idx];
 }
 
-// Fills level, s, products, status; norm1 is stored as given.
+// Combined bound of the 5-product scheme (Algorithm4cA cosine, Algorithm5sA
+// sine): its sine bound is the larger, so it is the printed T^c_8 bound of
+// Tables 1-2. Used only when the caller asks for the extended plan.
+__host__ __device__ inline double plan_theta_level5(int acc) {
+  return (acc & 1) == SINCOSM_ACC_SINGLE ? 8.5756e-1 : 1.1495e-1;
+}
+
+// Accuracy argument check: DOUBLE or SINGLE, optionally with the extended-plan flag.
+inline bool acc_valid(int acc, bool allow_extended) {
+  const int base = allow_extended ? (acc & ~(int)SINCOSM_PLAN_EXTENDED) : acc;
+  return base == SINCOSM_ACC_DOUBLE || base == SINCOSM_ACC_SINGLE;
+}
+
+// Fills level, s, products, status; norm1 is stored as given. `acc` may carry
+// SINCOSM_PLAN_EXTENDED (the 5-product scheme joins the candidates).
 __host__ __device__ inline void plan_rule(double norm1, int acc, sincosm_plan* p) {
-  const int levels[4] = {3, 4, 6, 7};
+  const int levels[5] = {3, 4, 6, 7, 5};
+  const int base = acc & 1;
+  const int nlev = (acc & SINCOSM_PLAN_EXTENDED) ? 5 : 4;
   p->norm1 = norm1;
   if (!(norm1 >= 0.0 && norm1 <= 1.7976931348623157e308)) {  // NaN, negative or +Inf
     p->level = 0; p->s = 0; p->products = 0; p->status = SINCOSM_E_NONFINITE;
     return;
   }
   int best_cost = 0x7fffffff, best_s = 0, best_level = 3;
-  for (int i = 0; i < 4; ++i) {
-    const double th = plan_theta(acc, i);
+  for (int i = 0; i < nlev; ++i) {
+    const double th = i < 4 ? plan_theta(base, i) : plan_theta_level5(base);
     int s = 0;
     double t = norm1;
     while (t > th) { t *= 0.5; ++s; }     // exact halving: no log2 rounding

@@ -14,6 +14,12 @@
 //   G1 Y;  G2 Y2 = Y Y -> Y2, W = -Y/6! + Y2/8!, Pc = I - Y/2 + Y2/24, Ps = I - Y/6 + Y2/120
 //   G3 Y4 = Y2 W -> C = Pc + Y4, V = Ps + (6!/7!) Y4
 //   G4 S = (sA) V
+// 5 products (Algorithm4cA, Algorithm5sA; extended plan only):
+//   G1 Y;  G2 Y2 = Y Y -> Y2, W = -Y/6! + Y2/8!, Ws = -Y/7! + Y2/9!, Pc = I - Y/2 + Y2/24,
+//        Ps = I - Y/6 + Y2/120
+//   G3 Y4 = Y2 W  -> C = Pc + Y4
+//   G4 Y4s = Y2 Ws -> V = Ps + Y4s
+//   G5 S = (sA) V
 // 6 products (Algorithm6cA with eq:cosm8, Algorithm6sA):
 //   G1 Y;  G2 Y2 = Y Y -> Y2, W = x1 Y + x2 Y2
 //   G3 Y4 = Y2 W (paper A_8) -> Y4, L = x3 Y2 + Y4, R = x4 I + x5 Y + x6 Y2 + x7 Y4,
@@ -224,6 +230,40 @@ sincosm_status scheme4(Run& r, double sx) {
   return gemm(r, m.poly, one(p, (int)np));
 }
 
+sincosm_status scheme5(Run& r, double sx) {
+  const Modes& m = *r.m;
+  const int64_t np = m.np;
+  const int nv = (int)r.n;
+  const bool pf = m.poly_f64;
+  Problem p = make_problem(nv);
+  add_seg(p, r.Ap, r.Ap, np, sx, sx);
+  add_out(p, internal(r.W[0], m, pf), 1.0, 0.0, {});
+  SC_TRY(gemm(r, m.poly, one(p, (int)np)));
+  p = make_problem(nv);
+  add_seg(p, r.W[0], r.W[0], np);
+  add_in(p, r.W[0], np);
+  add_out(p, internal(r.W[1], m, pf), 1.0, 0.0, {});
+  add_out(p, internal(r.W[2], m, pf), 1.0 / 40320.0, 0.0, {-1.0 / 720.0});
+  add_out(p, internal(r.W[5], m, pf), 1.0 / 362880.0, 0.0, {-1.0 / 5040.0});
+  add_out(p, internal(r.W[3], m, pf), 1.0 / 24.0, 1.0, {-0.5});
+  add_out(p, internal(r.W[4], m, pf), 1.0 / 120.0, 1.0, {-1.0 / 6.0});
+  SC_TRY(gemm(r, m.poly, one(p, (int)np)));
+  p = make_problem(nv);
+  add_seg(p, r.W[1], r.W[2], np);
+  add_in(p, r.W[3], np);
+  add_out(p, r.Cout, 1.0, 0.0, {1.0});
+  SC_TRY(gemm(r, m.poly, one(p, (int)np)));
+  p = make_problem(nv);
+  add_seg(p, r.W[1], r.W[5], np);
+  add_in(p, r.W[4], np);
+  add_out(p, internal(r.W[4], m, pf), 1.0, 0.0, {1.0});
+  SC_TRY(gemm(r, m.poly, one(p, (int)np)));
+  p = make_problem(nv);
+  add_seg(p, r.Ap, r.W[4], np, sx, 1.0);
+  add_out(p, r.Sout, 1.0, 0.0, {});
+  return gemm(r, m.poly, one(p, (int)np));
+}
+
 sincosm_status scheme6(Run& r, double sx) {
   const Modes& m = *r.m;
   const int64_t np = m.np;
@@ -342,6 +382,7 @@ sincosm_status run_scheme(Run& r, int level, double sx) {
   switch (level) {
     case 3: return scheme3(r, sx);
     case 4: return scheme4(r, sx);
+    case 5: return scheme5(r, sx);
     case 6: return scheme6(r, sx);
     default: return scheme7(r, sx);
   }

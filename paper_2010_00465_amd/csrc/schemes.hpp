@@ -59,6 +59,7 @@ Target internal(void* p, const Modes& m, bool f64);
 sincosm_status gemm(Run& r, Arith ar, const GemmLaunch& g, int kind = -1);
 sincosm_status scheme3(Run& r, double sx);
 sincosm_status scheme4(Run& r, double sx);
+sincosm_status scheme5(Run& r, double sx);
 sincosm_status scheme6(Run& r, double sx);
 sincosm_status scheme7(Run& r, double sx);
 sincosm_status run_scheme(Run& r, int level, double sx);

@@ -22,7 +22,7 @@ const char* sincosm_strerror(int status) {
 }
 
 sincosm_status sincosm_plan_host(double norm1, int acc, sincosm_plan* out) {
-  if (!out || (acc != SINCOSM_ACC_DOUBLE && acc != SINCOSM_ACC_SINGLE)) return SINCOSM_E_ARG;
+  if (!out || (!acc_valid(acc, true))) return SINCOSM_E_ARG;
   plan_rule(norm1, acc, out);
   return SINCOSM_OK;
 }
@@ -35,7 +35,7 @@ size_t sincosm_plan_workspace_size(int64_t n) {
 sincosm_status sincosm_plan_device(int64_t n, int dtype, const void* A, int64_t lda, int acc, void* ws,
                                    size_t ws_bytes, sincosm_plan* plan_host, void* stream_) {
   if (n < 0 || !plan_host) return SINCOSM_E_ARG;
-  if (acc != SINCOSM_ACC_DOUBLE && acc != SINCOSM_ACC_SINGLE) return SINCOSM_E_ARG;
+  if (!acc_valid(acc, true)) return SINCOSM_E_ARG;
   if (dtype != SINCOSM_F64 && dtype != SINCOSM_F32) return SINCOSM_E_ARG;
   if (n == 0) { plan_rule(0.0, acc, plan_host); return SINCOSM_OK; }
   if (!A || lda < n) return SINCOSM_E_ARG;
@@ -58,7 +58,7 @@ sincosm_status sincosm_eval(int64_t n, int dtype, const void* A, int64_t lda, vo
                             int64_t lds, int acc, int prod, void* ws, size_t ws_bytes, sincosm_plan* plan_host,
                             void* stream_) {
   if (n < 0 || n > (1 << 20)) return SINCOSM_E_ARG;
-  if (acc != SINCOSM_ACC_DOUBLE && acc != SINCOSM_ACC_SINGLE) return SINCOSM_E_ARG;
+  if (!acc_valid(acc, true)) return SINCOSM_E_ARG;
   Modes m;
   if (!modes_for(n > 0 ? n : 1, dtype, prod, m)) return SINCOSM_E_ARG;
   if (n == 0) {

@@ -105,3 +105,22 @@ def test_wave_host_plan_matches_oracle(lib):
             assert (p.level, p.s, p.products, p.status) == (*Wv.wave_plan(float(x), name), 0), (x, name)
     p = Plan()
     assert lib.sincosm_wave_plan_host(math.nan, 0, ctypes.byref(p)) == 0 and p.status == -4
+
+
+def test_host_plan_extended_matches_oracle(lib):
+    """With SINCOSM_PLAN_EXTENDED the host rule equals the oracle's extended plan; flagged
+    accuracy codes are rejected by the wave plan."""
+    from oracle import plan as P
+    ext = 16
+    xs = list(np.exp2(np.random.default_rng(9).uniform(-30, 40, size=3000)))
+    for acc in ("double", "single"):
+        for th in list(P.THETA[acc].values()) + [P.THETA_LEVEL5[acc]]:
+            for k in range(10):
+                b = math.ldexp(th, k)
+                xs += [b, math.nextafter(b, math.inf), math.nextafter(b, 0.0)]
+    for x in xs:
+        for code, name in ((0, "double"), (1, "single")):
+            p = host_plan(lib, float(x), code | ext)
+            assert (p.level, p.s, p.products) == P.plan(float(x), name, extended=True), (x, name)
+    lib.sincosm_wave_plan_host.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.POINTER(Plan)]
+    assert lib.sincosm_wave_plan_host(1.0, ext, ctypes.byref(Plan())) == -1

@@ -361,3 +361,48 @@ def test_tier_bf16x3_float32_storage(env):
     Cr, Sr = R.sincosm(A32.astype(np.float64))
     tol = 8 * 7 * U_BF * 2 ** plan.s
     assert rel_fro(C, Cr) <= tol and rel_fro(S, Sr) <= tol
+
+
+# ---------------------------------------------------------------------------
+# Extended plan: the 5-product scheme (Algorithm4cA cosine, Algorithm5sA sine)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [33, 257, 1000])
+@pytest.mark.parametrize("acc,norm", [("double", 0.1), ("double", 0.114), ("single", 0.8)])
+def test_extended_level5(env, n, acc, norm):
+    torch, sc = env
+    say("eval level5", n, acc, norm)
+    A = W.gaussian(n, norm, key=(56, n, int(norm * 1000)))
+    At = torch.from_numpy(A).cuda()
+    C = torch.empty_like(At)
+    S = torch.empty_like(At)
+    plan = sc.sincosm_eval(At, C, S, acc, extended=True)
+    torch.cuda.synchronize()
+    assert (plan.level, plan.s, plan.products) == (5, 0, 5)
+    assert sc.plan_device(At, acc).products == 6          # the paper's tables take one more
+    C, S = C.cpu().numpy(), S.cpu().numpy()
+    Cp, Sp = PA.sincosm(A, acc, extended=True)
+    assert rel_fro(C, Cp) <= 1e-12 and rel_fro(S, Sp) <= 1e-12
+    Cr, Sr = R.sincosm(A)
+    tol = 1e-12 if acc == "double" else 5e-6
+    assert rel_fro(C, Cr) <= tol and rel_fro(S, Sr) <= tol
+
+
+def test_extended_level5_tiers_and_expi(env):
+    torch, sc = env
+    A = W.gaussian(300, 0.8, key=(57,))
+    C, S, plan = None, None, None
+    At = torch.from_numpy(A).cuda()
+    C = torch.empty_like(At)
+    S = torch.empty_like(At)
+    plan = sc.sincosm_eval(At, C, S, "single", "bf16x3", extended=True)
+    assert plan.level == 5
+    Cr, Sr = R.sincosm(A)
+    tol = 8 * 5 * U_BF
+    assert rel_fro(C.cpu().numpy(), Cr) <= tol and rel_fro(S.cpu().numpy(), Sr) <= tol
+    U = torch.empty(300, 300, dtype=torch.complex128, device="cuda")
+    p = sc.sincosm_expi_eval(At, 1.0, U, "double", extended=False)
+    assert p.level == 6
+    p = sc.sincosm_expi_eval(At * 0.125, 1.0, U, "double", extended=True)
+    assert p.level == 5
+    Ur = R.sincosm(A * 0.125)
+    assert rel_fro(U.cpu().numpy(), Ur[0] - 1j * Ur[1]) <= 1e-12

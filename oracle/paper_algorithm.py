@@ -28,17 +28,20 @@ from .reference import norm1
 __all__ = ["sincosm", "plan_for"]
 
 
-def plan_for(A: np.ndarray, accuracy: str = "double", extended: bool = False):
-    """(level, s, products) for A (``extended``: the 5-product scheme is a candidate too)."""
-    return _plan.plan(norm1(A), accuracy, extended)
+def plan_for(A: np.ndarray, accuracy: str = "double", extended: bool = False, refined: bool = False):
+    """(level, s, products) for A (``extended``: the 5-product scheme is a candidate too;
+    ``refined``: plan on min(||A||_1, ||A^2||_1^(1/2)))."""
+    theta = _plan.refined_theta(A) if refined else norm1(A)
+    return _plan.plan(theta, accuracy, extended)
 
 
-def sincosm(A: np.ndarray, accuracy: str = "double", dtype=np.float64, return_plan=False, extended=False):
+def sincosm(A: np.ndarray, accuracy: str = "double", dtype=np.float64, return_plan=False, extended=False,
+            refined=False):
     """cos(A), sin(A) by the paper's method in ``dtype`` arithmetic."""
     A = np.asarray(A, dtype=dtype)
     n = A.shape[0]
     I = np.eye(n, dtype=dtype)
-    level, s, products = plan_for(A, accuracy, extended)
+    level, s, products = plan_for(A, accuracy, extended, refined)
     X = A * dtype(2.0) ** (-s)
     C, S = _schemes.evaluate(level, X, dtype=dtype)
     for _ in range(s):

@@ -19,6 +19,14 @@ Readings taken (the paper only shows the resulting staircase in its Figure 1):
   derived as for the tables: 1.7401e-1 double, 1.0812 single) exceeds its
   cosine's, so its combined bound is the printed T^c_8 bound of Tables 1-2:
   1.1495e-1 (double), 8.5756e-1 (single).
+* Refined norm (opt-in, not in the paper): Section 4 tests [[1, lambda],
+  [0, -1]] up to lambda = 1e8, where ||A||_1 is huge but A^2 = I, and notes
+  the overscaling this causes. Every scheme is a polynomial in Y = X^2 (the
+  sine times X), so its truncation error is bounded by the same series in
+  ||Y||^(1/2): the plan may use theta' = min(||A||_1, ||A^2||_1^(1/2)), with A^2
+  the product the schemes form first anyway. The cosine bound then holds as
+  in Tables 1-2; the sine's bound becomes u ||X|| / theta_level relative to X
+  (Al-Mohy and Higham's use of ||A^p||^(1/p), restricted to p = 2).
 
 Pins (tests/test_oracle_plan.py): a brute-force enumeration over all
 (level, s) candidates written independently, and the table constants against
@@ -28,7 +36,7 @@ from __future__ import annotations
 
 import math
 
-__all__ = ["THETA", "THETA_LEVEL5", "PRODUCTS", "plan", "scaling_for"]
+__all__ = ["THETA", "THETA_LEVEL5", "PRODUCTS", "plan", "scaling_for", "refined_theta"]
 
 PRODUCTS = {3: 3, 4: 4, 5: 5, 6: 6, 7: 7}
 
@@ -70,3 +78,16 @@ def plan(theta: float, accuracy: str = "double", extended: bool = False):
             best = cand
     cost, s, level = best
     return level, s, cost
+
+
+def refined_theta(A) -> float:
+    """min(||A||_1, ||A^2||_1^(1/2)) with A^2 formed in float64 (NaN or Inf propagate)."""
+    import numpy as np
+    A = np.asarray(A, dtype=np.float64)
+    t1 = float(np.abs(A).sum(axis=0).max()) if A.size else 0.0
+    if not math.isfinite(t1):
+        return t1
+    t2 = float(np.abs(A @ A).sum(axis=0).max()) if A.size else 0.0
+    if not math.isfinite(t2):
+        return t1
+    return min(t1, math.sqrt(t2))

@@ -68,3 +68,37 @@ def test_extended_level5_against_mpmath(acc, theta, tol):
         Cm = np.array(mpmath.cosm(M).tolist(), dtype=float)
         Sm = np.array(mpmath.sinm(M).tolist(), dtype=float)
     assert rel_fro(C, Cm) <= tol and rel_fro(S, Sm) <= tol
+
+
+@pytest.mark.parametrize("lam", [1e2, 1e4, 1e8])
+def test_refined_norm_removes_overscaling(lam):
+    """Section 4's [[1, lambda], [0, -1]]: A^2 = I, so cos A = cos(1) I and sin A = sin(1) A exactly.
+    The tables' plan scales by about lambda and loses accuracy; the refined plan needs s = 0."""
+    import math
+    A = np.array([[1.0, lam], [0.0, -1.0]])
+    Cx, Sx = math.cos(1.0) * np.eye(2), math.sin(1.0) * A
+    C0, S0, p0 = PA.sincosm(A, return_plan=True)
+    C1, S1, p1 = PA.sincosm(A, return_plan=True, refined=True)
+    assert p1 == (7, 0, 7) and p0[1] >= int(math.log2(lam)) - 1
+    assert rel_fro(C1, Cx) <= 1e-15 and rel_fro(S1, Sx) <= 1e-15
+    if lam >= 1e8:
+        assert max(rel_fro(C0, Cx), rel_fro(S0, Sx)) > 1e-12    # the overscaling the paper notes
+
+
+def test_refined_norm_block_family_and_random():
+    """[[I, B], [0, -I]] squares to I for any B (closed form at any size); on Gaussian matrices the
+    refined plan never takes more products and stays within 1e-12 of the reference."""
+    import math
+    n = 24
+    B = W.gaussian(n // 2, 300.0, key=(31,))
+    A = np.block([[np.eye(n // 2), B], [np.zeros((n // 2, n // 2)), -np.eye(n // 2)]])
+    assert np.array_equal(A @ A, np.eye(n))
+    C, S, p = PA.sincosm(A, return_plan=True, refined=True)
+    assert p == (7, 0, 7)
+    assert rel_fro(C, math.cos(1.0) * np.eye(n)) <= 1e-15 and rel_fro(S, math.sin(1.0) * A) <= 1e-15
+    for e in (-3, 1, 5, 9):
+        A = W.gaussian(40, 2.0 ** e, key=(32, e + 10))
+        C, S, p = PA.sincosm(A, return_plan=True, refined=True)
+        assert p[2] <= P.plan(np.linalg.norm(A, 1))[2]
+        Cr, Sr = R.sincosm(A)
+        assert rel_fro(C, Cr) <= 1e-12 and rel_fro(S, Sr) <= 1e-12

@@ -40,9 +40,10 @@ def parse():
     ap.add_argument("--n", type=int, default=N)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the batched, backward, precision-tier, wave, propagator and 5-product-scheme "
-                         "measurements")
-    ap.add_argument("--only", choices=["batched", "backward", "tiers", "wave", "propagators", "level5"],
+                    help="skip the batched, backward, precision-tier, wave, propagator, 5-product-scheme and "
+                         "refined-norm measurements")
+    ap.add_argument("--only", choices=["batched", "backward", "tiers", "wave", "propagators", "level5",
+                                       "refined"],
                     help="run and print only one of the secondary measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run sincosm_matmul once at --n: its two pad/convert copy kernels read and "
@@ -252,6 +253,33 @@ def bench_level5(torch, sc, W):
     return out
 
 
+def bench_refined(torch, sc, W):
+    """Overscaling (Section 4's [[1, lambda], [0, -1]] family at n = 4096): A = [[I, B], [0, -I]]
+    with B Gaussian, ||B||_1 = 1024, so A^2 = I and cos A = cos(1) I, sin A = sin(1) A exactly.
+    The tables' plan on ||A||_1 against the refined plan on min(||A||_1, ||A^2||_1^(1/2)); errors
+    against the closed forms (computed on the GPU)."""
+    import math
+    n, h = 4096, 2048
+    B = torch.from_numpy(W.gaussian(h, 1024.0, key=(8, n))).cuda()
+    A = torch.zeros(n, n, dtype=torch.float64, device="cuda")
+    A[:h, :h] = torch.eye(h, dtype=torch.float64, device="cuda")
+    A[h:, h:] = -torch.eye(h, dtype=torch.float64, device="cuda")
+    A[:h, h:] = B
+    I = torch.eye(n, dtype=torch.float64, device="cuda")
+    Cx, Sx = math.cos(1.0) * I, math.sin(1.0) * A
+    ws = torch.empty(sc.workspace_size(n, torch.float64), dtype=torch.uint8, device="cuda")
+    out = {"workload": "n=4096 float64 [[I, B], [0, -I]], B Gaussian with ||B||_1 = 1024 (A^2 = I)"}
+    for name, ref in (("paper_plan", False), ("refined_plan", True)):
+        C, S = torch.empty_like(A), torch.empty_like(A)
+        p = sc.sincosm_eval(A, C, S, ws=ws, refined=ref)
+        t = _elapsed(torch, lambda: sc.sincosm_eval(A, C, S, ws=ws, refined=ref), 3)
+        out[name] = {"ms": 1e3 * t, "plan": [p.level, p.s], "products": p.products, "norm_used": p.norm1,
+                     "rel_err_cos": float((C - Cx).norm() / Cx.norm()),
+                     "rel_err_sin": float((S - Sx).norm() / Sx.norm())}
+    out["speedup"] = out["paper_plan"]["ms"] / out["refined_plan"]["ms"]
+    return out
+
+
 def bench_propagators(torch, sc, W):
     """n = 4096 float64 propagators against torch.linalg.matrix_exp on the same operator.
 
@@ -306,7 +334,8 @@ def main():
         import paper_2010_00465_amd as sc
         import workloads as W
         fn = {"batched": bench_batched, "backward": bench_backward, "tiers": bench_tiers,
-              "wave": bench_wave, "propagators": bench_propagators, "level5": bench_level5}[args.only]
+              "wave": bench_wave, "propagators": bench_propagators, "level5": bench_level5,
+              "refined": bench_refined}[args.only]
         print(json.dumps({args.only: fn(torch, sc, W)}))
         return
     import torch
@@ -384,6 +413,7 @@ def main():
         extras["wave"] = bench_wave(torch, sc, W)
         extras["propagators"] = bench_propagators(torch, sc, W)
         extras["level5"] = bench_level5(torch, sc, W)
+        extras["refined"] = bench_refined(torch, sc, W)
 
     out = {
         "metric": "cos+sin evals/sec & % MFMA peak at n=4096 FP64; rel err vs FP64 oracle",

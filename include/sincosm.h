@@ -67,6 +67,19 @@ typedef enum { SINCOSM_ACC_DOUBLE = 0, SINCOSM_ACC_SINGLE = 1 } sincosm_accuracy
  * batched, backward and wave entries reject the flag (SINCOSM_E_ARG). */
 enum { SINCOSM_PLAN_EXTENDED = 16 };
 
+/* Flag OR-ed into `acc` of sincosm_eval only: plan on theta' = min(||A||_1,
+ * ||A^2||_1^(1/2)) instead of ||A||_1 (not in the paper; the remedy for the
+ * overscaling Section 4 observes on [[1, lambda], [0, -1]], whose square is I).
+ * A^2 is the first product every scheme forms anyway: it is computed unscaled
+ * before the plan, its 1-norm taken on the device, and after the plan it is
+ * scaled by 4^-s (exact) and reused, so the product count stays Pi + 2 s. Cost:
+ * one more O(n^2) norm pass and scaling pass. The cosine's truncation bound
+ * holds as for Tables 1-2 (the scheme is a polynomial in A^2); the sine's
+ * becomes u ||X|| / theta_level relative to X = 2^-s A. plan_host->norm1
+ * reports theta'. If A^2 overflows, theta' = ||A||_1 and A^2 is recomputed from
+ * the scaled operands (one extra product). Rejected elsewhere (SINCOSM_E_ARG). */
+enum { SINCOSM_PLAN_REFINED = 32 };
+
 /* Arithmetic of the polynomial-phase products (the scheme of step 3):
  *  NATIVE - the storage type (float64 MFMA for F64, float32 MFMA for F32);
  *  F32    - float32 MFMA products and float32 intermediates;

@@ -54,8 +54,8 @@ def _require_cuda(*ts):
             raise ValueError("tensors must live on the GPU")
 
 
-def _acc(accuracy: str, extended: bool = False) -> int:
-    return ACC[accuracy] | (_lib.PLAN_EXTENDED if extended else 0)
+def _acc(accuracy: str, extended: bool = False, refined: bool = False) -> int:
+    return ACC[accuracy] | (_lib.PLAN_EXTENDED if extended else 0) | (_lib.PLAN_REFINED if refined else 0)
 
 
 def plan_host(norm1: float, accuracy: str = "double", extended: bool = False) -> Plan:
@@ -89,9 +89,10 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 
 def sincosm_eval(A: torch.Tensor, C: torch.Tensor, S: torch.Tensor, accuracy: str = "double",
                  products: str = "native", ws: torch.Tensor | None = None, raise_nonfinite=True,
-                 extended: bool = False) -> Plan:
+                 extended: bool = False, refined: bool = False) -> Plan:
     """C-ABI sincosm_eval on torch tensors (writes C and S in place). Returns the plan.
-    ``extended``: the plan may also use the 5-product scheme."""
+    ``extended``: the plan may also use the 5-product scheme; ``refined``: plan on
+    min(||A||_1, ||A^2||_1^(1/2)) (against overscaling of nonnormal A)."""
     _require_cuda(A, C, S)
     n = A.shape[0]
     dt = _dtype_code(A)
@@ -99,8 +100,8 @@ def sincosm_eval(A: torch.Tensor, C: torch.Tensor, S: torch.Tensor, accuracy: st
         ws = _workspace(workspace_size(n, A.dtype, accuracy, products), A.device)
     plan = Plan()
     st = lib.sincosm_eval(n, dt, A.data_ptr(), _ld(A), C.data_ptr(), _ld(C), S.data_ptr(), _ld(S),
-                          _acc(accuracy, extended), PROD[products], ws.data_ptr(), ws.numel(), ctypes.byref(plan),
-                          _stream(A))
+                          _acc(accuracy, extended, refined), PROD[products], ws.data_ptr(), ws.numel(),
+                          ctypes.byref(plan), _stream(A))
     if st == _lib.E_NONFINITE and not raise_nonfinite:
         return plan
     check(st, "sincosm_eval")

@@ -46,9 +46,9 @@ __host__ __device__ inline double plan_theta_level5(int acc) {
   return (acc & 1) == SINCOSM_ACC_SINGLE ? 8.5756e-1 : 1.1495e-1;
 }
 
-// Accuracy argument check: DOUBLE or SINGLE, optionally with the extended-plan flag.
-inline bool acc_valid(int acc, bool allow_extended) {
-  const int base = allow_extended ? (acc & ~(int)SINCOSM_PLAN_EXTENDED) : acc;
+// Accuracy argument check: DOUBLE or SINGLE, optionally with the plan flags in `allowed`.
+inline bool acc_valid(int acc, int allowed) {
+  const int base = acc & ~allowed;
   return base == SINCOSM_ACC_DOUBLE || base == SINCOSM_ACC_SINGLE;
 }
 
@@ -190,6 +190,12 @@ sincosm_status launch_norm_copy_plan(int64_t n, int64_t np, const void* A, int64
                                      const NormScratch& ns, hipStream_t stream, int mode = 0,
                                      double pre = 1.0);
 // dst (np x np, zero padded) = src^T for an n x n src.
+// 1-norm of the np x np padded Y (its n x n part) into the second max slot, then
+// the refined plan: theta' = min(||A||_1, ||Y||_1^(1/2)) when both are finite
+// (else ||A||_1). plan[0] receives the plan, plan[1].level = 1 when Y is finite
+// and may be reused as the scheme's first product.
+sincosm_status launch_norm_sq_plan(int64_t n, int64_t np, const void* Y, bool y_f64, int acc,
+                                   const NormScratch& ns, hipStream_t stream);
 sincosm_status launch_transpose_pad(int64_t n, int64_t np, const void* src, int64_t lds, bool src_f64,
                                     void* dst, bool dst_f64, hipStream_t stream);
 sincosm_status launch_fill_nan(int64_t n, void* X, int64_t ld, bool f64, hipStream_t stream);

@@ -89,6 +89,42 @@ __global__ void plan_kernel(const unsigned long long* maxbits, int acc, int mode
   *plan = p;
 }
 
+__global__ void plan_sq_kernel(const unsigned long long* maxbits, int acc, sincosm_plan* plan) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double t1 = __longlong_as_double((long long)maxbits[0]);
+  const double t2 = __longlong_as_double((long long)maxbits[1]);
+  const double big = 1.7976931348623157e308;
+  double t = t1;
+  int y_ok = 0;
+  if (t1 >= 0.0 && t1 <= big && t2 >= 0.0 && t2 <= big) {
+    const double r = sqrt(t2);
+    t = r < t1 ? r : t1;
+    y_ok = 1;
+  }
+  sincosm_plan p;
+  plan_rule(t, acc, &p);
+  plan[0] = p;
+  sincosm_plan q;
+  q.level = y_ok; q.s = 0; q.products = 0; q.status = 0; q.norm1 = t2;
+  plan[1] = q;
+}
+
+sincosm_status launch_norm_sq_plan(int64_t n, int64_t np, const void* Y, bool y_f64, int acc,
+                                   const NormScratch& ns, hipStream_t stream) {
+  dim3 g1((unsigned)((np + NORM_COLS - 1) / NORM_COLS), (unsigned)ns.nchunks);
+  if (y_f64)
+    norm_copy_kernel<double, double><<<g1, NORM_COLS, 0, stream>>>(n, np, (const double*)Y, np, 1.0, nullptr,
+                                                                   ns.partial, ns.maxbits + 1);
+  else
+    norm_copy_kernel<float, double><<<g1, NORM_COLS, 0, stream>>>(n, np, (const float*)Y, np, 1.0, nullptr,
+                                                                  ns.partial, ns.maxbits + 1);
+  dim3 g2((unsigned)((np + NORM_COLS - 1) / NORM_COLS));
+  norm_reduce_kernel<<<g2, NORM_COLS, 0, stream>>>(np, ns.nchunks, ns.partial, ns.maxbits + 1);
+  plan_sq_kernel<<<1, 64, 0, stream>>>(ns.maxbits, acc, ns.plan);
+  SC_HIP(hipGetLastError());
+  return SINCOSM_OK;
+}
+
 template <typename TS, typename TD>
 static void launch_norm_t(int64_t n, int64_t np, const void* A, int64_t lda, void* Ap, const NormScratch& ns,
                           int acc, int mode, double pre, hipStream_t stream) {

@@ -20,7 +20,7 @@ sincosm_status sincosm_expi_eval(int64_t n, int dtype, const void* A, int64_t ld
                                  int acc, int prod, void* ws, size_t ws_bytes, sincosm_plan* plan_host,
                                  void* stream_) {
   if (n < 0 || n > (1 << 20)) return SINCOSM_E_ARG;
-  if (!acc_valid(acc, true)) return SINCOSM_E_ARG;
+  if (!acc_valid(acc, SINCOSM_PLAN_EXTENDED)) return SINCOSM_E_ARG;
   if (!isfinite(t)) return SINCOSM_E_ARG;
   Modes m;
   if (!modes_for(n > 0 ? n : 1, dtype, prod, m)) return SINCOSM_E_ARG;

@@ -142,12 +142,13 @@ Layout layout_for(const Modes& m) {
 
 // Pinned host slot for the plan read-back (one per host thread, kept for the
 // life of the process).
-sincosm_status read_plan(const sincosm_plan* dev, sincosm_plan* host, hipStream_t stream) {
+sincosm_status read_plan(const sincosm_plan* dev, sincosm_plan* host, hipStream_t stream, int count) {
   thread_local sincosm_plan* pinned = nullptr;
-  if (!pinned) SC_HIP(hipHostMalloc((void**)&pinned, sizeof(sincosm_plan), hipHostMallocDefault));
-  SC_HIP(hipMemcpyAsync(pinned, dev, sizeof(sincosm_plan), hipMemcpyDeviceToHost, stream));
+  if (count < 1 || count > 2) return SINCOSM_E_ARG;
+  if (!pinned) SC_HIP(hipHostMalloc((void**)&pinned, 2 * sizeof(sincosm_plan), hipHostMallocDefault));
+  SC_HIP(hipMemcpyAsync(pinned, dev, count * sizeof(sincosm_plan), hipMemcpyDeviceToHost, stream));
   SC_HIP(hipStreamSynchronize(stream));
-  *host = *pinned;
+  for (int i = 0; i < count; ++i) host[i] = pinned[i];
   return SINCOSM_OK;
 }
 
@@ -179,16 +180,23 @@ sincosm_status gemm(Run& r, Arith ar, const GemmLaunch& g, int kind) {
   return st;
 }
 
+// G1 of every scheme: Y = (sA)(sA) into W0, unless the caller already placed it there.
+static sincosm_status g1(Run& r, double sx) {
+  if (r.y_ready) return SINCOSM_OK;
+  const Modes& m = *r.m;
+  Problem p = make_problem((int)r.n);
+  add_seg(p, r.Ap, r.Ap, m.np, sx, sx);
+  add_out(p, internal(r.W[0], m, m.poly_f64), 1.0, 0.0, {});
+  return gemm(r, m.poly, one(p, (int)m.np));
+}
+
 sincosm_status scheme3(Run& r, double sx) {
   const Modes& m = *r.m;
   const int64_t np = m.np;
   const int nv = (int)r.n;
   const bool pf = m.poly_f64;
+  SC_TRY(g1(r, sx));
   Problem p = make_problem(nv);
-  add_seg(p, r.Ap, r.Ap, np, sx, sx);
-  add_out(p, internal(r.W[0], m, pf), 1.0, 0.0, {});
-  SC_TRY(gemm(r, m.poly, one(p, (int)np)));
-  p = make_problem(nv);
   add_seg(p, r.W[0], r.W[0], np);
   add_in(p, r.W[0], np);
   add_out(p, r.Cout, 1.0 / 24.0, 1.0, {-0.5});
@@ -205,11 +213,8 @@ sincosm_status scheme4(Run& r, double sx) {
   const int64_t np = m.np;
   const int nv = (int)r.n;
   const bool pf = m.poly_f64;
+  SC_TRY(g1(r, sx));
   Problem p = make_problem(nv);
-  add_seg(p, r.Ap, r.Ap, np, sx, sx);
-  add_out(p, internal(r.W[0], m, pf), 1.0, 0.0, {});
-  SC_TRY(gemm(r, m.poly, one(p, (int)np)));
-  p = make_problem(nv);
   add_seg(p, r.W[0], r.W[0], np);
   add_in(p, r.W[0], np);
   add_out(p, internal(r.W[1], m, pf), 1.0, 0.0, {});
@@ -235,11 +240,8 @@ sincosm_status scheme5(Run& r, double sx) {
   const int64_t np = m.np;
   const int nv = (int)r.n;
   const bool pf = m.poly_f64;
+  SC_TRY(g1(r, sx));
   Problem p = make_problem(nv);
-  add_seg(p, r.Ap, r.Ap, np, sx, sx);
-  add_out(p, internal(r.W[0], m, pf), 1.0, 0.0, {});
-  SC_TRY(gemm(r, m.poly, one(p, (int)np)));
-  p = make_problem(nv);
   add_seg(p, r.W[0], r.W[0], np);
   add_in(p, r.W[0], np);
   add_out(p, internal(r.W[1], m, pf), 1.0, 0.0, {});
@@ -272,12 +274,9 @@ sincosm_status scheme6(Run& r, double sx) {
   const Coeffs& k = coeffs();
   const double* x = k.x;   // x[1..8]
   const double* z = k.z6;  // z[0..8]
-  Problem p = make_problem(nv);
-  add_seg(p, r.Ap, r.Ap, np, sx, sx);
-  add_out(p, internal(r.W[0], m, pf), 1.0, 0.0, {});
-  SC_TRY(gemm(r, m.poly, one(p, (int)np)));
+  SC_TRY(g1(r, sx));
   // G2: Y2 = Y Y -> Y2, W = x1 Y + x2 Y2
-  p = make_problem(nv);
+  Problem p = make_problem(nv);
   add_seg(p, r.W[0], r.W[0], np);
   add_in(p, r.W[0], np);
   add_out(p, internal(r.W[1], m, pf), 1.0, 0.0, {});
@@ -326,12 +325,9 @@ sincosm_status scheme7(Run& r, double sx) {
   const Coeffs& k = coeffs();
   const double(*a)[5] = k.a;  // a[i][j], i = 0..3, j = 1..4
   const double* z = k.z7;     // z[0..11]
-  Problem p = make_problem(nv);
-  add_seg(p, r.Ap, r.Ap, np, sx, sx);
-  add_out(p, internal(r.W[0], m, pf), 1.0, 0.0, {});
-  SC_TRY(gemm(r, m.poly, one(p, (int)np)));
+  SC_TRY(g1(r, sx));
   // G2: Y2 = Y Y
-  p = make_problem(nv);
+  Problem p = make_problem(nv);
   add_seg(p, r.W[0], r.W[0], np);
   add_out(p, internal(r.W[1], m, pf), 1.0, 0.0, {});
   SC_TRY(gemm(r, m.poly, one(p, (int)np)));

@@ -36,6 +36,7 @@ struct Run {
   hipStream_t stream;
   int launched;
   Recorder* rec = nullptr;
+  bool y_ready = false;   // W0 already holds Y = (2^-s A)^2: the schemes skip their first product
 };
 
 // Launch capture used to build the batched path's stage templates from the
@@ -53,7 +54,7 @@ GemmLaunch one(const Problem& p, int np);
 GemmLaunch two(const Problem& p0, const Problem& p1, int np);
 bool modes_for(int64_t n, int dtype, int prod, Modes& m);
 Layout layout_for(const Modes& m);
-sincosm_status read_plan(const sincosm_plan* dev, sincosm_plan* host, hipStream_t stream);
+sincosm_status read_plan(const sincosm_plan* dev, sincosm_plan* host, hipStream_t stream, int count = 1);
 bool overlaps(const void* a, int64_t lda, const void* b, int64_t ldb, int64_t n, size_t es);
 Target internal(void* p, const Modes& m, bool f64);
 sincosm_status gemm(Run& r, Arith ar, const GemmLaunch& g, int kind = -1);

@@ -22,7 +22,7 @@ const char* sincosm_strerror(int status) {
 }
 
 sincosm_status sincosm_plan_host(double norm1, int acc, sincosm_plan* out) {
-  if (!out || (!acc_valid(acc, true))) return SINCOSM_E_ARG;
+  if (!out || (!acc_valid(acc, SINCOSM_PLAN_EXTENDED))) return SINCOSM_E_ARG;
   plan_rule(norm1, acc, out);
   return SINCOSM_OK;
 }
@@ -35,7 +35,7 @@ size_t sincosm_plan_workspace_size(int64_t n) {
 sincosm_status sincosm_plan_device(int64_t n, int dtype, const void* A, int64_t lda, int acc, void* ws,
                                    size_t ws_bytes, sincosm_plan* plan_host, void* stream_) {
   if (n < 0 || !plan_host) return SINCOSM_E_ARG;
-  if (!acc_valid(acc, true)) return SINCOSM_E_ARG;
+  if (!acc_valid(acc, SINCOSM_PLAN_EXTENDED)) return SINCOSM_E_ARG;
   if (dtype != SINCOSM_F64 && dtype != SINCOSM_F32) return SINCOSM_E_ARG;
   if (n == 0) { plan_rule(0.0, acc, plan_host); return SINCOSM_OK; }
   if (!A || lda < n) return SINCOSM_E_ARG;
@@ -58,7 +58,9 @@ sincosm_status sincosm_eval(int64_t n, int dtype, const void* A, int64_t lda, vo
                             int64_t lds, int acc, int prod, void* ws, size_t ws_bytes, sincosm_plan* plan_host,
                             void* stream_) {
   if (n < 0 || n > (1 << 20)) return SINCOSM_E_ARG;
-  if (!acc_valid(acc, true)) return SINCOSM_E_ARG;
+  if (!acc_valid(acc, SINCOSM_PLAN_EXTENDED | SINCOSM_PLAN_REFINED)) return SINCOSM_E_ARG;
+  const bool refined = (acc & SINCOSM_PLAN_REFINED) != 0;
+  acc &= ~(int)SINCOSM_PLAN_REFINED;
   Modes m;
   if (!modes_for(n > 0 ? n : 1, dtype, prod, m)) return SINCOSM_E_ARG;
   if (n == 0) {
@@ -78,16 +80,6 @@ sincosm_status sincosm_eval(int64_t n, int dtype, const void* A, int64_t lda, vo
 
   const NormScratch ns = norm_scratch(base + L.norm_off, m.np);
   void* Ap = base + L.ap_off;
-  SC_TRY(launch_norm_copy_plan(n, m.np, A, lda, m.user_f64, Ap, m.poly_f64, acc, ns, stream));
-  sincosm_plan plan;
-  SC_TRY(read_plan(ns.plan, &plan, stream));
-  if (plan_host) *plan_host = plan;
-  if (plan.status != SINCOSM_OK) {
-    SC_TRY(launch_fill_nan(n, C, ldc, m.user_f64, stream));
-    SC_TRY(launch_fill_nan(n, S, lds, m.user_f64, stream));
-    return SINCOSM_E_NONFINITE;
-  }
-
   Run r;
   r.m = &m;
   r.n = n;
@@ -95,6 +87,36 @@ sincosm_status sincosm_eval(int64_t n, int dtype, const void* A, int64_t lda, vo
   for (int i = 0; i < 9; ++i) r.W[i] = base + L.w_off[i];
   r.stream = stream;
   r.launched = 0;
+  SC_TRY(launch_norm_copy_plan(n, m.np, A, lda, m.user_f64, Ap, m.poly_f64, acc, ns, stream));
+  sincosm_plan plans[2];
+  if (refined) {
+    // the schemes' first product, unscaled: W0 = A A; plan on min(||A||_1, ||A^2||_1^(1/2))
+    Problem p = make_problem((int)n);
+    add_seg(p, Ap, Ap, m.np);
+    add_out(p, internal(r.W[0], m, m.poly_f64), 1.0, 0.0, {});
+    SC_TRY(gemm(r, m.poly, one(p, (int)m.np)));
+    SC_TRY(launch_norm_sq_plan(n, m.np, r.W[0], m.poly_f64, acc, ns, stream));
+    SC_TRY(read_plan(ns.plan, plans, stream, 2));
+  } else {
+    SC_TRY(read_plan(ns.plan, plans, stream));
+  }
+  const sincosm_plan plan = plans[0];
+  if (plan_host) *plan_host = plan;
+  if (plan.status != SINCOSM_OK) {
+    SC_TRY(launch_fill_nan(n, C, ldc, m.user_f64, stream));
+    SC_TRY(launch_fill_nan(n, S, lds, m.user_f64, stream));
+    return SINCOSM_E_NONFINITE;
+  }
+  if (refined && plans[1].level == 1) {
+    // reuse A^2 as Y = 4^-s A^2 (exact scaling, in place, epilogue-only launch)
+    if (plan.s > 0) {
+      Problem p = make_problem((int)n);
+      add_in(p, r.W[0], m.np);
+      add_out(p, internal(r.W[0], m, m.poly_f64), 0.0, 0.0, {ldexp(1.0, -2 * plan.s)});
+      SC_TRY(launch_gemm(m.poly, m.tile, one(p, (int)m.np), stream));
+    }
+    r.y_ready = true;
+  }
   void* Q[4];
   for (int i = 0; i < 4; ++i) Q[i] = base + L.q_off[i];
   const Target userC{C, ldc, (int)n, m.user_f64};

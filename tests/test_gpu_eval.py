@@ -406,3 +406,79 @@ def test_extended_level5_tiers_and_expi(env):
     assert p.level == 5
     Ur = R.sincosm(A * 0.125)
     assert rel_fro(U.cpu().numpy(), Ur[0] - 1j * Ur[1]) <= 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Refined-norm plan (min(||A||_1, ||A^2||_1^(1/2))) against overscaling
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("lam", [1e2, 1e4, 1e8])
+def test_refined_paper_overscaling_matrix(env, lam):
+    """Section 4's [[1, lambda], [0, -1]]: cos A = cos(1) I, sin A = sin(1) A; 7 products, s = 0."""
+    torch, sc = env
+    A = np.array([[1.0, lam], [0.0, -1.0]])
+    At = torch.from_numpy(A).cuda()
+    C, S = torch.empty_like(At), torch.empty_like(At)
+    plan = sc.sincosm_eval(At, C, S, refined=True)
+    assert (plan.level, plan.s, plan.products) == (7, 0, 7)
+    assert rel_fro(C.cpu().numpy(), math.cos(1.0) * np.eye(2)) <= 1e-15
+    assert rel_fro(S.cpu().numpy(), math.sin(1.0) * A) <= 1e-15
+
+
+@pytest.mark.parametrize("n,norm", [(300, 1e3), (1000, 1e6), (4096, 1024.0)])
+def test_refined_block_family(env, n, norm):
+    """[[I, B], [0, -I]] squares to I exactly: closed form at any size, including n = 4096."""
+    torch, sc = env
+    say("refined block", n, norm)
+    h = n // 2
+    B = torch.from_numpy(W.gaussian(h, norm, key=(58, n))).cuda()
+    A = torch.zeros(n, n, dtype=torch.float64, device="cuda")
+    A[:h, :h] = torch.eye(h, dtype=torch.float64, device="cuda")
+    A[h:, h:] = -torch.eye(h, dtype=torch.float64, device="cuda")
+    A[:h, h:] = B
+    C, S = torch.empty_like(A), torch.empty_like(A)
+    plan = sc.sincosm_eval(A, C, S, refined=True)
+    assert (plan.level, plan.s) == (7, 0)
+    I = torch.eye(n, dtype=torch.float64, device="cuda")
+    ec = float((C - math.cos(1.0) * I).norm() / (math.cos(1.0) * n ** 0.5))
+    es = float((S - math.sin(1.0) * A).norm() / (math.sin(1.0) * A.norm()))
+    assert ec <= 1e-15 and es <= 1e-15, (ec, es)
+    # the tables' plan on the same matrix scales by about ||A||_1
+    assert sc.plan_device(A).s >= 9
+
+
+@pytest.mark.parametrize("e", [-3, 1, 5, 9])
+def test_refined_random_matches_oracle(env, e):
+    """Gaussian matrices: plan = the oracle's refined plan; within 1e-12 of both oracles; and
+    bitwise equal to the unrefined call whenever the plans agree (same products, A^2 reused)."""
+    torch, sc = env
+    A = W.gaussian(257, 2.0 ** e, key=(59, e + 10))
+    At = torch.from_numpy(A).cuda()
+    C, S = torch.empty_like(At), torch.empty_like(At)
+    plan = sc.sincosm_eval(At, C, S, refined=True)
+    th = P.refined_theta(A)
+    got = (plan.level, plan.s, plan.products)
+    assert any(got == P.plan(th * f) for f in (1.0, 1 - 1e-12, 1 + 1e-12)), (got, th)
+    C, S = C.cpu().numpy(), S.cpu().numpy()
+    Cp, Sp = PA.sincosm(A, refined=True)
+    assert rel_fro(C, Cp) <= 1e-12 and rel_fro(S, Sp) <= 1e-12
+    Cr, Sr = R.sincosm(A)
+    assert rel_fro(C, Cr) <= 1e-12 and rel_fro(S, Sr) <= 1e-12
+    C0, S0, plan0 = run(env, A)
+    if (plan0.level, plan0.s) == (plan.level, plan.s):
+        assert np.array_equal(C0, C) and np.array_equal(S0, S)
+
+
+def test_refined_tiers_and_flags(env):
+    torch, sc = env
+    A = np.kron(np.eye(50), np.array([[1.0, 1e6], [0.0, -1.0]]))
+    At = torch.from_numpy(A).cuda()
+    C, S = torch.empty_like(At), torch.empty_like(At)
+    plan = sc.sincosm_eval(At, C, S, "single", "f32", refined=True, extended=True)
+    assert plan.s == 0
+    tol = 5e-6
+    assert rel_fro(C.cpu().numpy(), math.cos(1.0) * np.eye(100)) <= tol
+    assert rel_fro(S.cpu().numpy(), math.sin(1.0) * A) <= tol
+    # the flag is for sincosm_eval only
+    U = torch.empty(100, 100, dtype=torch.complex128, device="cuda")
+    st = sc.lib.sincosm_expi_eval(100, 0, At.data_ptr(), 100, 1.0, U.data_ptr(), 100, 32, 0, None, 0, None, None)
+    assert st == -1

@@ -113,12 +113,16 @@ const char* sincosm_strerror(int status);
 
 /* The plan sincosm_eval would use for A (1-norm and rule on the device),
  * read back to *plan_host. ws: sincosm_plan_workspace_size(n) bytes, 256-byte
- * aligned. Returns SINCOSM_OK also for non-finite input (status in the plan). */
+ * aligned. acc may carry SINCOSM_PLAN_EXTENDED (not SINCOSM_PLAN_REFINED, which
+ * needs a product). Returns SINCOSM_OK also for non-finite input (status in
+ * the plan). */
 size_t sincosm_plan_workspace_size(int64_t n);
 sincosm_status sincosm_plan_device(int64_t n, int dtype, const void* A, int64_t lda, int acc,
                                    void* ws, size_t ws_bytes, sincosm_plan* plan_host, void* stream);
 
-/* Bytes of workspace sincosm_eval needs for this n and settings (0 for n <= 0). */
+/* Bytes of workspace sincosm_eval needs for this n and settings (0 for n <= 0);
+ * the same size serves sincosm_wave_eval, sincosm_wave_block_eval and
+ * sincosm_expi_eval. `acc` does not change it. */
 size_t sincosm_workspace_size(int64_t n, int dtype, int acc, int prod);
 
 /* cos(A) and sin(A) of one n x n matrix (Sections 1 and 2.1, Tables 1-2).
@@ -128,7 +132,8 @@ size_t sincosm_workspace_size(int64_t n, int dtype, int acc, int prod);
  *  256-byte aligned.
  *  plan_host: optional host pointer receiving the plan used.
  *  Supported: dtype F64 with prod NATIVE, F32 or BF16X3; dtype F32 with prod
- *  NATIVE (= F32) or BF16X3. acc may be DOUBLE or SINGLE in every case.
+ *  NATIVE (= F32) or BF16X3. acc may be DOUBLE or SINGLE in every case, with
+ *  SINCOSM_PLAN_EXTENDED and/or SINCOSM_PLAN_REFINED OR-ed in.
  *  Returns SINCOSM_E_NONFINITE (after filling C and S with NaN) when A holds
  *  Inf or NaN. */
 sincosm_status sincosm_eval(int64_t n, int dtype, const void* A, int64_t lda,

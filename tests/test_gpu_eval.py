@@ -482,3 +482,37 @@ def test_refined_tiers_and_flags(env):
     U = torch.empty(100, 100, dtype=torch.complex128, device="cuda")
     st = sc.lib.sincosm_expi_eval(100, 0, At.data_ptr(), 100, 1.0, U.data_ptr(), 100, 32, 0, None, 0, None, None)
     assert st == -1
+
+
+def test_refined_edge_cases(env):
+    torch, sc = env
+    # n = 1: A^2 = a^2, theta' = |a|
+    for x in (0.0, -0.3, 40.0):
+        At = torch.tensor([[x]], dtype=torch.float64, device="cuda")
+        C, S = torch.empty_like(At), torch.empty_like(At)
+        plan = sc.sincosm_eval(At, C, S, refined=True)
+        assert abs(plan.norm1 - abs(x)) <= 1e-15 * max(1.0, abs(x))
+        assert abs(float(C) - math.cos(x)) <= 1e-15 * 16 * max(1, abs(x))
+        assert abs(float(S) - math.sin(x)) <= 1e-15 * 16 * max(1, abs(x))
+    # zero matrix: exact identity / zero
+    Z = torch.zeros(40, 40, dtype=torch.float64, device="cuda")
+    C, S = torch.empty_like(Z), torch.empty_like(Z)
+    plan = sc.sincosm_eval(Z, C, S, refined=True)
+    assert (plan.level, plan.s) == (3, 0)
+    assert torch.equal(C, torch.eye(40, dtype=torch.float64, device="cuda")) and not S.any()
+    # non-finite input: status and NaN outputs, as without the flag
+    Z[3, 7] = float("nan")
+    plan = sc.sincosm_eval(Z, C, S, refined=True, raise_nonfinite=False)
+    assert plan.status == -4 and torch.isnan(C).all() and torch.isnan(S).all()
+    # A^2 overflows while A is finite: plan on ||A||_1, A^2 recomputed from the scaled operands
+    A = torch.full((8, 8), 1e160, dtype=torch.float64, device="cuda")
+    C, S = torch.empty_like(A), torch.empty_like(A)
+    p0 = sc.sincosm_eval(A.clone(), C.clone(), S.clone())
+    plan = sc.sincosm_eval(A, C, S, refined=True)
+    assert (plan.level, plan.s) == (p0.level, p0.s)
+    C0, S0 = torch.empty_like(A), torch.empty_like(A)
+    sc.sincosm_eval(A, C0, S0)
+    # (about 530 double-angle steps: the values are not meaningful, but both calls run the
+    # same launches, so they agree bit for bit, NaN and Inf included)
+    same = lambda X, Y: torch.equal(torch.nan_to_num(X), torch.nan_to_num(Y))
+    assert same(C, C0) and same(S, S0)

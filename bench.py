@@ -139,13 +139,32 @@ def bench_batched(torch, sc, W):
     loop()
     t_loop = _elapsed(torch, loop, 1)
     loop_flops = float(sum(p.products * 2.0 * int(n) ** 3 for p, n in zip(pl[:k], ns[:k])))
+    # the same call captured in a HIP graph and replayed
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        w.run(A, C, S, plans)
+    g.replay()
+    t_graph = _elapsed(torch, g.replay, 3)
+    # float32 storage with the single-accuracy plans, same orders and norms
+    A32 = A.to(torch.float32)
+    C32, S32 = torch.empty_like(A32), torch.empty_like(A32)
+    plans32 = torch.zeros_like(plans)
+    w32 = sc.BatchedWorkspace(ns, offs, torch.float32, A.device, accuracy="single")
+    w32.run(A32, C32, S32, plans32)
+    pl32 = sc.plans_from_bytes(plans32)
+    flops32 = float(sum(p.products * 2.0 * int(n) ** 3 for p, n in zip(pl32, ns)))
+    t32 = _elapsed(torch, lambda: w32.run(A32, C32, S32, plans32), 3)
     return {"workload": "20000 float64 Gaussian matrices, n uniform on {8,...,256}, ||A||_1 = 2^U(-6,8), "
                         "double-accuracy plans, one sincosm_eval_batched call",
             "ms_per_batch": 1e3 * t, "evals_per_s": len(ns) / t, "tflops_algorithmic": flops / t / 1e12,
             "mean_products": float(np.mean([p.products for p in pl])),
+            "graph_replay_ms": 1e3 * t_graph,
             "loop_of_sincosm_eval": {"matrices": k, "evals_per_s": k / t_loop,
                                      "tflops_algorithmic": loop_flops / t_loop / 1e12},
-            "speedup_vs_loop": (len(ns) / t) / (k / t_loop)}
+            "speedup_vs_loop": (len(ns) / t) / (k / t_loop),
+            "float32_single": {"ms_per_batch": 1e3 * t32, "evals_per_s": len(ns) / t32,
+                               "tflops_algorithmic": flops32 / t32 / 1e12,
+                               "mean_products": float(np.mean([p.products for p in pl32]))}}
 
 
 def bench_backward(torch, sc, W):

@@ -178,3 +178,30 @@ def test_batched_config_full(env):
         Cr, Sr = R.sincosm(Am)
         assert rel_fro(Cc[o:o + n * n].reshape(n, n), Cr) <= 1e-12
         assert rel_fro(Sc[o:o + n * n].reshape(n, n), Sr) <= 1e-12
+
+
+def test_batched_config_full_float32(env):
+    """The 20,000-matrix batch in float32 storage with single-accuracy plans: sampled oracle
+    parity (oracle on the float32 values promoted to float64) at the single-accuracy bar."""
+    torch, sc = env
+    ns, offs, packed, norms = W.batched_gaussian(20000, key=(3,), dtype=np.float32)
+    A = torch.from_numpy(packed).cuda()
+    C = torch.empty_like(A)
+    S = torch.empty_like(A)
+    plans = torch.zeros(len(ns) * sc.PLAN_BYTES, dtype=torch.uint8, device="cuda")
+    sc.sincosm_eval_batched(ns, offs, A, C, S, accuracy="single", plans=plans)
+    torch.cuda.synchronize()
+    pl = sc.plans_from_bytes(plans)
+    assert all(p.status == 0 for p in pl)
+    idx = np.random.default_rng(87).choice(len(ns), size=40, replace=False)
+    idx = np.concatenate([idx, [int(np.argmax(ns)), int(np.argmax(norms))]])
+    Cc = C.double().cpu().numpy()
+    Sc = S.double().cpu().numpy()
+    for i in idx:
+        n, o = int(ns[i]), int(offs[i])
+        Am = packed[o:o + n * n].reshape(n, n).astype(np.float64)
+        assert plan_ok(pl[i], Am, "single")
+        Cr, Sr = R.sincosm(Am)
+        tol = 5e-6 * max(1, 2 ** pl[i].s / 16)
+        assert rel_fro(Cc[o:o + n * n].reshape(n, n), Cr) <= tol
+        assert rel_fro(Sc[o:o + n * n].reshape(n, n), Sr) <= tol

@@ -14,15 +14,21 @@ integer arithmetic (j k mod 2 (n + 1)) before the multiplication by pi, and
 lambda_k uses the 4 sin^2 form, so no entry loses accuracy to cancellation or
 to large arguments.
 
+The 2-D 5-point Laplacian on an m x m grid, L = I (x) T + T (x) I (n = m^2),
+has the eigenvectors v_i (x) v_j with eigenvalues lambda_i + lambda_j, so a
+row (a, b) of f(c L) is sum_i v_i(a) v_i (x) [sum_j f(c (lambda_i + lambda_j))
+v_j(b) v_j], O(m^3) per row.
+
 Pins (tests/test_oracle_closed_forms.py): eigenpairs against numpy's eigh and
 T V = V Lambda; rows of cos/sin against the Taylor reference; the wave and
-unitary rows against their oracles.
+unitary rows against their oracles; 2-D rows against the Taylor reference.
 """
 from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["laplacian_1d_eig", "function_rows", "sincos_rows", "wave_rows", "unitary_rows"]
+__all__ = ["laplacian_1d_eig", "function_rows", "sincos_rows", "wave_rows", "unitary_rows",
+           "laplacian_2d_rows"]
 
 
 def laplacian_1d_eig(n: int, c: float = 1.0):
@@ -64,3 +70,15 @@ def unitary_rows(n: int, c: float, t: float, rows):
     rows = np.asarray(rows, dtype=np.int64)
     Vr = V[rows]
     return ((Vr * np.cos(t * lam)) @ V.T) - 1j * ((Vr * np.sin(t * lam)) @ V.T)
+
+
+def laplacian_2d_rows(m: int, c: float, rows, f) -> np.ndarray:
+    """Rows (flattened grid index a m + b) of f(c (I (x) T + T (x) I)) for an m x m grid."""
+    lam, V = laplacian_1d_eig(m)
+    F = f(float(c) * (lam[:, None] + lam[None, :]))          # F[i, j] = f(c (lam_i + lam_j))
+    out = np.empty((len(rows), m * m), dtype=np.result_type(F, V))
+    for k, r in enumerate(rows):
+        a, b = divmod(int(r), m)
+        Wb = (F * V[b, :][None, :]) @ V.T                     # [i, b'] = sum_j F_ij v_j(b) v_j(b')
+        out[k] = ((V * V[a, :][None, :]) @ Wb).ravel()        # [a', b'] = sum_i v_i(a) v_i(a') Wb[i, b']
+    return out

@@ -3,9 +3,13 @@ family A = c tridiag(-1, 2, -1), whose matrix functions have the closed form
 V f(c Lambda) V^T (oracle/closed_forms.py): sampled rows of every output are compared with
 the exact values, in the launch configuration the product kernels use at that order.
 
+The precision tiers are checked the same way on the 2-D Laplacian of a 90 x 90 grid
+(n = 8100), whose eigenvectors are Kronecker products of the 1-D ones.
+
 Bars: relative Frobenius error over the sampled rows <= 1e-12 for the float64 double-accuracy
 paths (the float64 CPU oracle itself stays at 4e-13 on this family up to ||A||_1 = 2^10);
-<= 5e-6 for float32 storage with the single-accuracy plan."""
+<= 5e-6 for float32 storage with the single-accuracy plan; the tier bounds stated at
+test_tiers_laplacian_2d_n8100."""
 import sys
 
 import numpy as np
@@ -160,3 +164,35 @@ def test_wave_block_n4096(env, eig):
     assert rel_fro(Eh[rows, n:], Sr) <= 1e-12
     assert rel_fro(Eh[n + rows, :n], -ASr) <= 1e-12
     assert rel_fro(Eh[n + rows, n:], Cr) <= 1e-12
+
+
+U32 = 2.0 ** -24
+U_BF = 2.0 ** -18
+
+
+@pytest.mark.parametrize("acc,prod", [("double", "native"), ("single", "native"), ("single", "f32"),
+                                      ("single", "bf16x3")])
+def test_tiers_laplacian_2d_n8100(env, acc, prod):
+    """Precision tiers on the 2-D Laplacian of a 90 x 90 grid (n = 8100), ||A||_1 = 64, float64
+    storage, against the closed form (sampled rows). Bounds: 1e-12 for the float64 double path;
+    5e-6 for float64 with the single table; the FP32-product tier 16 Pi u_32 2^s and the BF16x3
+    tier 8 Pi 2^-18 2^s (each scheme product rounds to float32 / carries the split error, and the
+    s float64 double-angle steps amplify an error by about 2 each)."""
+    torch, sc = env
+    m = 90
+    say("tiers 8100", acc, prod)
+    A = torch.from_numpy(W.laplacian_2d(m, 64.0)).cuda()
+    C, S = torch.empty_like(A), torch.empty_like(A)
+    plan = sc.sincosm_eval(A, C, S, acc, prod)
+    c = 64.0 / 8.0
+    rows = sample_rows(m * m, 6)
+    Cr = CF.laplacian_2d_rows(m, c, rows, np.cos)
+    Sr = CF.laplacian_2d_rows(m, c, rows, np.sin)
+    ec = rel_fro(C[rows].cpu().numpy(), Cr)
+    es = rel_fro(S[rows].cpu().numpy(), Sr)
+    pi = plan.level
+    tol = {("double", "native"): 1e-12, ("single", "native"): 5e-6,
+           ("single", "f32"): 16 * pi * U32 * 2 ** plan.s,
+           ("single", "bf16x3"): 8 * pi * U_BF * 2 ** plan.s}[(acc, prod)]
+    print(f"n=8100 {acc}/{prod} plan=({plan.level},{plan.s}) rows rel err cos {ec:.2e} sin {es:.2e} tol {tol:.1e}")
+    assert ec <= tol and es <= tol

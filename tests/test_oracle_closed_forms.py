@@ -51,3 +51,16 @@ def test_large_argument_reduction():
     idx = [0, 1999, 3999]
     G = V[:, idx].T @ V[:, idx]
     assert np.abs(G - np.eye(3)).max() <= 1e-13
+
+
+@pytest.mark.parametrize("target", [4.0, 64.0])
+def test_laplacian_2d_rows_against_reference(target):
+    m = 9
+    A = W.laplacian_2d(m, target)
+    c = target / 8.0
+    L = W.laplacian_2d(m, 8.0)
+    assert np.array_equal(A, c * L)
+    rows = [0, 13, 40, 80]
+    C, S = R.sincosm(A)
+    assert rel_fro(CF.laplacian_2d_rows(m, c, rows, np.cos), C[rows]) <= 1e-12 * max(1.0, target / 8)
+    assert rel_fro(CF.laplacian_2d_rows(m, c, rows, np.sin), S[rows]) <= 1e-12 * max(1.0, target / 8)

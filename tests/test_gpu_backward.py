@@ -62,7 +62,8 @@ def test_backward_one_sided(env, which):
     assert rel_fro(gA, ref) <= 1e-10
 
 
-@pytest.mark.parametrize("n,norm", [(256, 0.5), (256, 8.0), (1024, 0.5), (1024, 8.0), (1024, 128.0)])
+@pytest.mark.parametrize("n,norm", [(256, 0.5), (256, 8.0), (256, 128.0), (1024, 0.5), (1024, 8.0), (1024, 128.0),
+                                    (2048, 0.5), (2048, 8.0), (2048, 128.0)])
 def test_backward_config_sizes(env, n, norm):
     print("[case] backward config", n, norm, flush=True)
     A = W.gaussian(n, norm, key=(4, n, int(norm * 2)))

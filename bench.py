@@ -78,24 +78,35 @@ def cpu_baseline(mats):
     return time.perf_counter() - t0, threads, out
 
 
+KERNEL_SOURCES = ("gemm.hip", "epilogue.hpp")
+
+
+def kernel_sources_sha256():
+    """sha256 over the product kernel's sources (gemm.hip, then epilogue.hpp)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2010_00465_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def measured_traffic():
     """HBM bytes per double-angle launch from the committed counter summary,
-    or None when the product kernel's source changed since it was taken."""
-    import hashlib
+    or None when the product kernel's sources changed since it was taken."""
     prof = os.path.join(ROOT, "profiles", "gemm_f64_n4096.md")
-    src = os.path.join(ROOT, "paper_2010_00465_amd", "csrc", "gemm.hip")
     try:
         text = open(prof).read()
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        sha = kernel_sources_sha256()
     except OSError:
         return None
     vals = {}
     for line in text.splitlines():
         if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch (double-angle step)",
-                                                   "gemm_source_sha256"):
+                                                   "kernel_sources_sha256"):
             k, v = line.split(":", 1)
             vals[k] = v.strip()
-    if vals.get("gemm_source_sha256") != sha:
+    if vals.get("kernel_sources_sha256") != sha:
         return None
     try:
         return float(vals["traffic_bytes_per_launch (double-angle step)"])

@@ -4,8 +4,12 @@ wave grid, occupancy) per arithmetic and padded matrix order.
 For each arithmetic and each probe order n it times every configuration the
 library offers whose tile divides the padded order (C-ABI
 ``sincosm_tune_num_configs`` / ``sincosm_tune_config_info``), by forcing it
-with ``sincosm_tune_set`` and timing ``sincosm_matmul`` with HIP events. The
-fastest configuration per probe is written to a JSON cache with the range of
+with ``sincosm_tune_set`` and timing ``sincosm_matmul`` with HIP events. A
+second pass tunes the launches that carry two products (the double-angle
+steps; also used by the reverse pass): it forces each configuration for that
+class only (``SINCOSM_TUNE_MULTI``) and times the double-angle launches of a
+``sincosm_eval`` call with the library's launch timing. The fastest
+configuration per probe and class is written to a JSON cache with the range of
 padded orders it covers (midpoints between probes). ``apply_cache`` installs a
 cache in the library; the package calls it at import for the cache shipped
 next to this file (``tune_gfx950.json``) or the file named by
@@ -26,6 +30,7 @@ from ._lib import lib
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(HERE, "tune_gfx950.json")
 ARITH = {"f64": 0, "f32": 1}
+MULTI = 16          # SINCOSM_TUNE_MULTI: the table of launches with two products' worth of work
 PROBES = (256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096, 6144, 8192)
 
 
@@ -52,11 +57,13 @@ def apply_cache(path: str | None = None) -> int:
     with open(path) as f:
         data = json.load(f)
     count = 0
-    for arith, entries in data.get("entries", {}).items():
-        if arith not in ARITH:
+    for key, entries in data.get("entries", {}).items():
+        arith, _, cls = key.partition("_")
+        if arith not in ARITH or cls not in ("", "multi"):
             continue
+        code = ARITH[arith] | (MULTI if cls == "multi" else 0)
         for e in entries:
-            if lib.sincosm_tune_set(ARITH[arith], int(e["np_lo"]), int(e["np_hi"]), int(e["idx"])) == 0:
+            if lib.sincosm_tune_set(code, int(e["np_lo"]), int(e["np_hi"]), int(e["idx"])) == 0:
                 count += 1
     return count
 
@@ -79,6 +86,36 @@ def time_config(torch, sc, arith: str, n: int, idx: int, reps: int) -> float:
     torch.cuda.synchronize()
     lib.sincosm_tune_set(ARITH[arith], np_, np_, -1)
     return e0.elapsed_time(e1) / reps
+
+
+def time_config_multi(torch, sc, arith: str, n: int, idx: int, reps: int) -> float:
+    """Average duration (ms) of the double-angle launches of sincosm_eval at order n with
+    configuration idx forced for the two-product class only (||A||_1 = 16: 4 steps)."""
+    np_ = padded(n)
+    dt = torch.float64 if arith == "f64" else torch.float32
+    g = torch.Generator(device="cuda").manual_seed(n)
+    A = torch.randn(n, n, dtype=dt, device="cuda", generator=g)
+    A *= 16.0 / float(A.abs().sum(0).max())
+    C, S = torch.empty_like(A), torch.empty_like(A)
+    ws = torch.empty(sc.workspace_size(n, dt), dtype=torch.uint8, device="cuda")
+    lib.sincosm_tune_set(ARITH[arith] | MULTI, np_, np_, idx)
+    sc.sincosm_eval(A, C, S, ws=ws)
+    torch.cuda.synchronize()
+    lib.sincosm_timing_enable(1)
+    for _ in range(reps):
+        sc.sincosm_eval(A, C, S, ws=ws)
+    torch.cuda.synchronize()
+    ms, cnt = ctypes.c_double(), ctypes.c_int64()
+    lib.sincosm_timing_read(1, ctypes.byref(ms), ctypes.byref(cnt))
+    lib.sincosm_timing_enable(0)
+    lib.sincosm_tune_set(ARITH[arith] | MULTI, np_, np_, -1)
+    return ms.value / max(cnt.value, 1)
+
+
+def _ranges(nps, k):
+    lo = 1 if k == 0 else (nps[k - 1] + nps[k]) // 2 + 1
+    hi = 1 << 30 if k == len(nps) - 1 else (nps[k] + nps[k + 1]) // 2
+    return lo, hi
 
 
 def tune(ariths=("f64", "f32"), probes=PROBES, reps=5, log=print):
@@ -108,6 +145,28 @@ def tune(ariths=("f64", "f32"), probes=PROBES, reps=5, log=print):
                 f"({flops / (best[1] * 1e-3) / 1e12:.1f} TFLOP/s incl. padding copies)")
         result["entries"][arith] = entries
         result["timings"][arith] = timings
+        # two-product launches, with the single-product table just measured installed
+        for e in entries:
+            lib.sincosm_tune_set(ARITH[arith], int(e["np_lo"]), int(e["np_hi"]), int(e["idx"]))
+        entries_m, timings_m = [], {}
+        for k, np_ in enumerate(nps):
+            best = None
+            timings_m[str(np_)] = {}
+            for c in configs(arith):
+                if np_ % c["bm"] or np_ % c["bn"]:
+                    continue
+                ms = time_config_multi(torch, sc, arith, np_, c["idx"], reps)
+                timings_m[str(np_)][str(c["idx"])] = ms
+                if best is None or ms < best[1]:
+                    best = (c["idx"], ms)
+            lo, hi = _ranges(nps, k)
+            flops = 4.0 * np_ ** 3
+            entries_m.append({"np_lo": lo, "np_hi": hi, "idx": best[0], "probe_np": np_, "ms": best[1],
+                              "tflops": flops / (best[1] * 1e-3) / 1e12})
+            log(f"{arith} two-product launches np={np_}: best config {best[0]} {best[1]:.3f} ms "
+                f"({flops / (best[1] * 1e-3) / 1e12:.1f} TFLOP/s)")
+        result["entries"][arith + "_multi"] = entries_m
+        result["timings"][arith + "_multi"] = timings_m
     return result
 
 

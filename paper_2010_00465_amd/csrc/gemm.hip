@@ -320,15 +320,20 @@ static const KernelCfg* cfg_table(Arith ar, int& count) {
   return nullptr;
 }
 
-// Tuning table: for (arith, padded order in [lo, hi]) use configuration idx.
-struct TuneEntry { int ar; int64_t lo, hi; int idx; };
+// Tuning table: for (arith, launch class, padded order in [lo, hi]) use
+// configuration idx. Class 0: launches with one product's worth of k-work per
+// output tile set (one problem, one segment); class 1: heavier launches (two
+// problems or several k-segments: the double-angle steps, the reverse pass),
+// which fall back to class 0 entries when none of their own matches.
+struct TuneEntry { int ar; int cls; int64_t lo, hi; int idx; };
 static std::mutex tune_mu;
 static std::vector<TuneEntry> tune_table;
 
-static int tuned_cfg(Arith ar, int64_t np) {
+static int tuned_cfg(Arith ar, int cls, int64_t np) {
   std::lock_guard<std::mutex> g(tune_mu);
-  for (auto it = tune_table.rbegin(); it != tune_table.rend(); ++it)
-    if (it->ar == (int)ar && np >= it->lo && np <= it->hi) return it->idx;
+  for (int c = cls; c >= 0; --c)
+    for (auto it = tune_table.rbegin(); it != tune_table.rend(); ++it)
+      if (it->ar == (int)ar && it->cls == c && np >= it->lo && np <= it->hi) return it->idx;
   return -1;
 }
 
@@ -338,7 +343,9 @@ sincosm_status launch_gemm(Arith ar, int tile, const GemmLaunch& g, hipStream_t 
   int count = 0;
   const KernelCfg* t = cfg_table(ar, count);
   if (!t) return SINCOSM_E_UNSUPPORTED;
-  int idx = tuned_cfg(ar, g.np);
+  int units = 0;
+  for (int p = 0; p < g.nprob; ++p) units += g.prob[p].nseg;
+  int idx = tuned_cfg(ar, units >= 2 ? 1 : 0, g.np);
   if (idx < 0 || idx >= count || g.np % t[idx].bm != 0 || g.np % t[idx].bn != 0) idx = tile;
   return t[idx].fn(g, stream);
 }
@@ -349,13 +356,13 @@ extern "C" {
 
 int sincosm_tune_num_configs(int arith) {
   int count = 0;
-  sc::cfg_table((sc::Arith)arith, count);
+  sc::cfg_table((sc::Arith)(arith & ~(int)SINCOSM_TUNE_MULTI), count);
   return count;
 }
 
 sincosm_status sincosm_tune_config_info(int arith, int idx, int32_t* info) {
   int count = 0;
-  const sc::KernelCfg* t = sc::cfg_table((sc::Arith)arith, count);
+  const sc::KernelCfg* t = sc::cfg_table((sc::Arith)(arith & ~(int)SINCOSM_TUNE_MULTI), count);
   if (!t || !info || idx < 0 || idx >= count) return SINCOSM_E_ARG;
   info[0] = t[idx].bm; info[1] = t[idx].bn; info[2] = t[idx].bk;
   info[3] = t[idx].wgm; info[4] = t[idx].wgn; info[5] = t[idx].wpe;
@@ -363,19 +370,21 @@ sincosm_status sincosm_tune_config_info(int arith, int idx, int32_t* info) {
 }
 
 sincosm_status sincosm_tune_set(int arith, int64_t np_lo, int64_t np_hi, int idx) {
+  const int cls = (arith & SINCOSM_TUNE_MULTI) ? 1 : 0;
+  const int ar = arith & ~(int)SINCOSM_TUNE_MULTI;
   int count = 0;
-  sc::cfg_table((sc::Arith)arith, count);
+  sc::cfg_table((sc::Arith)ar, count);
   if (count == 0 || np_lo > np_hi) return SINCOSM_E_ARG;
   std::lock_guard<std::mutex> g(sc::tune_mu);
-  if (idx < 0) {   // clear entries of this arithmetic overlapping the range
+  if (idx < 0) {   // clear entries of this arithmetic and class overlapping the range
     std::vector<sc::TuneEntry> keep;
     for (auto& e : sc::tune_table)
-      if (!(e.ar == arith && e.hi >= np_lo && e.lo <= np_hi)) keep.push_back(e);
+      if (!(e.ar == ar && e.cls == cls && e.hi >= np_lo && e.lo <= np_hi)) keep.push_back(e);
     sc::tune_table.swap(keep);
     return SINCOSM_OK;
   }
   if (idx >= count) return SINCOSM_E_ARG;
-  sc::tune_table.push_back(sc::TuneEntry{arith, np_lo, np_hi, idx});
+  sc::tune_table.push_back(sc::TuneEntry{ar, cls, np_lo, np_hi, idx});
   return SINCOSM_OK;
 }
 

@@ -47,7 +47,9 @@ def test_shipped_cache_is_consistent(lib):
     path = autotune.DEFAULT_CACHE
     assert os.path.exists(path)
     data = json.load(open(path))
-    for arith, entries in data["entries"].items():
+    for key, entries in data["entries"].items():
+        arith, _, cls = key.partition("_")
+        assert cls in ("", "multi"), key
         n = lib.sincosm_tune_num_configs(autotune.ARITH[arith])
         prev_hi = 0
         for e in entries:
@@ -56,6 +58,15 @@ def test_shipped_cache_is_consistent(lib):
             prev_hi = e["np_hi"]
             info = data["configs"][arith][e["idx"]]
             assert e["probe_np"] % info["bm"] == 0 and e["probe_np"] % info["bn"] == 0
+
+
+def test_multi_class_flag(lib):
+    """SINCOSM_TUNE_MULTI addresses a second table; the configuration list is the same."""
+    from paper_2010_00465_amd import autotune
+    assert lib.sincosm_tune_num_configs(autotune.MULTI) == lib.sincosm_tune_num_configs(0)
+    assert lib.sincosm_tune_set(autotune.MULTI, 1 << 40, 1 << 41, 1) == 0
+    assert lib.sincosm_tune_set(autotune.MULTI, 1 << 40, 1 << 41, -1) == 0
+    assert lib.sincosm_tune_set(autotune.MULTI | 9, 1, 10, 0) == -1
 
 
 def test_padding_rule_matches_library(lib):

@@ -1,5 +1,7 @@
 // C ABI of the forward path: validation, workspace layout, plan read-back,
 // then the scheme's launch sequence (schemes.cpp) and the s double-angle steps.
+// With the refined-norm flag the schemes' first product A^2 is formed before
+// the plan (its 1-norm refines theta) and reused after scaling by 4^-s.
 #include <math.h>
 #include <string.h>
 

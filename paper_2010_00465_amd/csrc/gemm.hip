@@ -240,9 +240,11 @@ void gemm_kernel(const GemmLaunch g) {
       if (kk + 1 < KK) {
         lread(cur, kk + 1, fa[f ^ 1], fb[f ^ 1]);
       } else {
-        if (more) lstore(cur ^ 1);
+        // unconditional: on the last step these move stale values that are never
+        // used, and the fragment registers keep one assignment around the loop
+        lstore(cur ^ 1);
         __syncthreads();
-        if (more) lread(cur ^ 1, 0, fa[f ^ 1], fb[f ^ 1]);
+        lread(cur ^ 1, 0, fa[f ^ 1], fb[f ^ 1]);
       }
 #pragma unroll
       for (int i = 0; i < FM; ++i)

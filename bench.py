@@ -394,10 +394,13 @@ def main():
     _lib.lib.sincosm_timing_enable(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    marks = [t0]
     for _ in range(args.steps):
         step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+        torch.cuda.synchronize()     # each call already waits for its plan; this closes the step
+        marks.append(time.perf_counter())
+    elapsed = marks[-1] - t0
+    step_ms = np.diff(np.asarray(marks)) * 1e3
     tot = {}
     for kind in (0, 1):
         ms, cnt = ctypes.c_double(), ctypes.c_int64()
@@ -417,6 +420,18 @@ def main():
     sq_avg_s = (sq_ms / sq_cnt) / 1e3 if sq_cnt else float("nan")
     sq_tflops = sq_flops / sq_avg_s / 1e12 if sq_cnt else None
     sch_ms, sch_cnt = tot[0]
+
+    # plan read-back alone (1-norm, plan kernel, 24-byte copy and stream sync), outside the timed region
+    pw = torch.empty(sc.lib.sincosm_plan_workspace_size(n), dtype=torch.uint8, device=dev)
+    plan_ms = []
+    for _ in range(10):
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        p_ = sc.Plan()
+        _lib.check(sc.lib.sincosm_plan_device(n, 0, A[1].data_ptr(), n, 0, pw.data_ptr(), pw.numel(),
+                                              ctypes.byref(p_), torch.cuda.current_stream(dev).cuda_stream),
+                   "sincosm_plan_device")
+        plan_ms.append((time.perf_counter() - tp) * 1e3)
 
     rel = None
     cpu = None
@@ -462,6 +477,9 @@ def main():
                                f"||A||_1 = 2^e for e in {list(ANCHORS)} (double-accuracy plan)",
                    "n": n, "anchors_log2_norm1": list(ANCHORS), "products": products,
                    "plans": [[p.level, p.s] for p in plans], "evals_per_step": len(ANCHORS)},
+        "step_ms_median": float(np.median(step_ms)),
+        "step_ms_iqr": float(np.percentile(step_ms, 75) - np.percentile(step_ms, 25)),
+        "plan_readback_ms_median": float(np.median(plan_ms)),
         "tflops_algorithmic": tflops,
         "pct_fp64_mfma_peak": 100.0 * tflops / FP64_MFMA_PEAK_TFLOPS,
         "roofline": {"bound": "mfma", "kernel": "double-angle product launch (FP64 MFMA product kernel, "

@@ -161,7 +161,7 @@ bool overlaps(const void* a, int64_t lda, const void* b, int64_t ldb, int64_t n,
 }
 
 // ----------------------------------------------------------------------------
-// Scheme launch sequences. Return the product count actually launched.
+// Scheme launch sequences. Each launch adds its product count to r.launched.
 // ----------------------------------------------------------------------------
 
 Target internal(void* p, const Modes& m, bool f64) { return Target{p, m.np, (int)m.np, f64}; }

@@ -40,10 +40,10 @@ def parse():
     ap.add_argument("--n", type=int, default=N)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the batched, backward, precision-tier, wave, propagator, 5-product-scheme and "
-                         "refined-norm measurements")
+                    help="skip the secondary measurements (batched, backward, tiers, wave, propagators, "
+                         "5-product scheme, refined norm, other orders)")
     ap.add_argument("--only", choices=["batched", "backward", "tiers", "wave", "propagators", "level5",
-                                       "refined"],
+                                       "refined", "sizes"],
                     help="run and print only one of the secondary measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run sincosm_matmul once at --n: its two pad/convert copy kernels read and "
@@ -283,6 +283,31 @@ def bench_level5(torch, sc, W):
     return out
 
 
+def bench_sizes(torch, sc, W):
+    """The anchor matrices (Gaussian, ||A||_1 = 2^e, e in {-4, 0, 4, 10}) at n = 1024 and 8192,
+    float64 with the double-accuracy plans and float32 storage with the single-accuracy plans:
+    evaluations/s and algorithmic TFLOP/s over the four anchors."""
+    out = {"workload": "four Gaussian anchor matrices per order and storage type"}
+    for n in (1024, 8192):
+        for dt, acc in ((torch.float64, "double"), (torch.float32, "single")):
+            mats = [torch.from_numpy(W.gaussian(n, 2.0 ** e, key=(2, n, 0, e + 10))).cuda().to(dt) for e in ANCHORS]
+            outs = [(torch.empty_like(m), torch.empty_like(m)) for m in mats]
+            ws = torch.empty(sc.workspace_size(n, dt, acc), dtype=torch.uint8, device="cuda")
+            plans = [sc.sincosm_eval(m, c, s_, acc, ws=ws) for m, (c, s_) in zip(mats, outs)]
+
+            def run():
+                for m, (c, s_) in zip(mats, outs):
+                    sc.sincosm_eval(m, c, s_, acc, ws=ws)
+
+            t = _elapsed(torch, run, 2)
+            flops = sum(p.products for p in plans) * 2.0 * n ** 3
+            key = f"n{n}_{'f64' if dt == torch.float64 else 'f32'}_{acc}"
+            out[key] = {"evals_per_s": len(mats) / t, "tflops_algorithmic": flops / t / 1e12,
+                        "products": [p.products for p in plans]}
+            del mats, outs, ws
+    return out
+
+
 def bench_refined(torch, sc, W):
     """Overscaling (Section 4's [[1, lambda], [0, -1]] family at n = 4096): A = [[I, B], [0, -I]]
     with B Gaussian, ||B||_1 = 1024, so A^2 = I and cos A = cos(1) I, sin A = sin(1) A exactly.
@@ -365,7 +390,7 @@ def main():
         import workloads as W
         fn = {"batched": bench_batched, "backward": bench_backward, "tiers": bench_tiers,
               "wave": bench_wave, "propagators": bench_propagators, "level5": bench_level5,
-              "refined": bench_refined}[args.only]
+              "refined": bench_refined, "sizes": bench_sizes}[args.only]
         print(json.dumps({args.only: fn(torch, sc, W)}))
         return
     import torch
@@ -459,6 +484,7 @@ def main():
         extras["propagators"] = bench_propagators(torch, sc, W)
         extras["level5"] = bench_level5(torch, sc, W)
         extras["refined"] = bench_refined(torch, sc, W)
+        extras["sizes"] = bench_sizes(torch, sc, W)
 
     out = {
         "metric": "cos+sin evals/sec & % MFMA peak at n=4096 FP64; rel err vs FP64 oracle",

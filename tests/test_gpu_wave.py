@@ -264,3 +264,33 @@ def test_tier_bf16x3_products(env, n, e):
     Cr, Sr = Wv.reference(A, 1.0)
     tol = 8 * 5 * U_BF * 2 ** plan.s
     assert rel_fro(C, Cr) <= tol and rel_fro(S, Sr) <= tol
+
+
+def test_strided_views(env):
+    """Inputs and outputs as views with leading dimension > n; memory outside stays untouched."""
+    torch, sc = env
+    g = W.rng(72)
+    big = torch.from_numpy(g.standard_normal((80, 90)) * 0.05).cuda()
+    A = big[5:65, 10:70]
+    Cb = torch.zeros(70, 75, dtype=torch.float64, device="cuda")
+    Sb = torch.zeros(70, 75, dtype=torch.float64, device="cuda")
+    C = Cb[2:62, 3:63]
+    S = Sb[4:64, 10:70]
+    sc.sincosm_wave_eval(A, 1.4, C, S)
+    torch.cuda.synchronize()
+    Cp, Sp = Wv.paper_wave(A.cpu().numpy(), 1.4)
+    assert rel_fro(C.cpu().numpy(), Cp) <= 1e-12 and rel_fro(S.cpu().numpy(), Sp) <= 1e-12
+    rc, rs = Cb.cpu().numpy().copy(), Sb.cpu().numpy().copy()
+    rc[2:62, 3:63] = 0
+    rs[4:64, 10:70] = 0
+    assert not rc.any() and not rs.any()
+
+
+def test_block_n1(env):
+    """n = 1: e^{tM} for M = [[0, 1], [-a, 0]] against the oracle's block (closed forms there)."""
+    from oracle import propagators as Pr
+    torch, sc = env
+    for a in (0.0, 2.5, -3.0):
+        A = torch.tensor([[a]], dtype=torch.float64, device="cuda")
+        E = sc.wave_block(A, 0.9).cpu().numpy()
+        assert rel_fro(E, Pr.symplectic(np.array([[a]]), 0.9)) <= 1e-14

@@ -12,10 +12,11 @@
 // Design for gfx950:
 //  * 16x16x4 MFMA (f64 or f32); each wave owns a WTM x WTN sub-tile as
 //    FM x FN MFMA blocks held in accumulator registers.
-//  * Operand tiles are staged through LDS, double buffered, one barrier per
-//    BK step placed before the step's last substep of MFMAs; the next tile's
-//    global loads are issued before the MFMAs of the current one so their
-//    latency hides behind the matrix core.
+//  * Operand tiles go through LDS, double buffered, one barrier per BK step in
+//    the step's last substep of MFMAs; the global loads of the next tile are
+//    issued before the MFMAs of the current one so their latency hides behind
+//    the matrix core. In float64 they can be loaded straight into LDS
+//    (global_load_lds), with no register round trip or LDS store instructions.
 //  * LDS layouts: A as [m][k] with row pitch BK+1, B as [k][n] with row pitch
 //    BN+16, so the 16-lane groups that feed one MFMA read distinct banks.
 //  * All operands are internal buffers padded with zeros to a multiple of the
@@ -81,29 +82,42 @@ __device__ inline void tile_coords(int np, int BM, int BN, int nprob, int& p, in
 
 // The k loop. Each BK step is KK = BK/4 substeps of FM x FN MFMAs. The
 // operand fragments of a substep are read from LDS one substep ahead (double
-// buffered in registers). The global loads of the next BK step are issued at
-// the start of the current one; at its last substep they are stored to the
-// other LDS buffer, the workgroup synchronises, and the first fragments of the
-// next step are read while the last substep's MFMAs run, so the barrier sits
-// between MFMAs that are already queued. The segment cursor of the global
-// loads (pointers, k offset, operand scales) is uniform state advanced
-// incrementally.
+// buffered in registers). The loads of the next BK step are issued at the
+// start of the current one; the workgroup synchronises in the step's last
+// substep, and the first fragments of the next step are read while that
+// substep's MFMAs run, so the barrier sits between MFMAs that are already
+// queued. The segment cursor of the loads (pointers, k offset, operand scales)
+// is uniform state advanced incrementally.
 //
-// LDS hazards (two buffers): the store into buffer (k+1)&1 happens in step k
-// before barrier B_k, after the storing wave passed B_{k-1}; every read of that
-// buffer (step k-1: the prefetch after B_{k-2} and the substep reads before
-// B_{k-1}) completed before its wave reached B_{k-1}. Reads of buffer (k+1)&1
-// in step k+1 start after B_k, when all stores into it are complete.
-template <typename T, int BM, int BN, int BK, int WGM, int WGN, int WPE>
+// Two ways to fill the LDS buffers:
+//  * staged (DL = 0): global loads into registers; in the last substep they
+//    are stored (scaled) into the other buffer, padded so that the fragment
+//    reads hit distinct banks.
+//  * direct (DL = 1, 2): global_load_lds_dwordx4 writes the tile straight into
+//    the other buffer, 16 bytes per lane, with no register round trip and no
+//    LDS store instructions; the permutation that avoids bank conflicts is
+//    chosen through the source addresses, and a launch with operand scales
+//    (DL = 2) applies them to the fragments after the LDS reads.
+//
+// LDS hazards (two buffers, barrier B_k in step k): the store or load into
+// buffer (k+1)&1 happens after the wave passed B_{k-1} (staged: in step k's
+// last substep; direct: at the start of step k). Every read of that buffer
+// belongs to step k-1 (the prefetch after B_{k-2} and the substep reads before
+// B_{k-1}), and the barrier waits for the wave's outstanding LDS reads, so
+// they completed before any wave passed B_{k-1}. Before B_k each wave waits
+// for its own stores or direct loads (vmcnt for the latter); the reads of
+// buffer (k+1)&1 in step k+1 start after B_k.
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int WPE, int DL>
 __global__ __launch_bounds__(WGM * WGN * 64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void gemm_kernel(const GemmLaunch g) {
   using M = Mma<T>;
   using acc_t = typename M::acc_t;
   using vec_t = typename M::vec_t;
-  constexpr int NT = WGM * WGN * 64;
+  constexpr int NW = WGM * WGN;
+  constexpr int NT = NW * 64;
   constexpr int WTM = BM / WGM, WTN = BN / WGN;
   constexpr int FM = WTM / 16, FN = WTN / 16;
-  constexpr int LDA = BK + 1, LDB = BN + 16;
+  constexpr int LDA = DL ? BK : BK + 1, LDB = DL ? BN : BN + 16;
   constexpr int VEC = M::VEC;
   constexpr int KK = BK / 4;
   constexpr int A_LOADS = BM * BK / VEC / NT;
@@ -116,6 +130,10 @@ void gemm_kernel(const GemmLaunch g) {
   static_assert(A_LOADS >= 1 && A_LOADS * VEC * NT == BM * BK, "A staging");
   static_assert(B_LOADS >= 1 && B_LOADS * VEC * NT == BK * BN, "B staging");
   static_assert(BK % 8 == 0 && BK % VEC == 0 && BN % VEC == 0, "k tiling (even substep count)");
+  // direct loads: one wave instruction fills 1 KiB of LDS (64 lanes x 16 bytes),
+  // 8 rows of an A tile of depth 16 or one 128-wide row of a B tile
+  static_assert(!DL || (sizeof(T) == 8 && BK == 16 && BN == 128 && A_LOADS * NW * 8 == BM && B_LOADS * NW == BK),
+                "direct loads: float64, k depth 16, 128-wide tiles");
 
   __shared__ __attribute__((aligned(16))) T smem[SMEM_ELEMS];
   T* const As0 = smem;
@@ -139,118 +157,231 @@ void gemm_kernel(const GemmLaunch g) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[i][j][r] = (T)0;
 
+  // Global offsets of this thread's loads and their LDS places. Staged loads
+  // go through registers into padded rows. A direct load writes lane l's 16
+  // bytes to byte 16 l of the wave's 1 KiB chunk, so the lane picks the source
+  // that belongs there: in an A chunk (rows 8c..8c+7, 16 values each), slot
+  // (row, pair q) holds pair q ^ (row & 7) of that row; in a B chunk (k row c),
+  // slot pair q holds column pair q ^ 8 (c & 1). The fragment reads undo the
+  // permutation, and the 16 lanes x 4 rows of one read hit every bank twice.
   int offA[A_LOADS], offB[B_LOADS], ldsA[A_LOADS], ldsB[B_LOADS];
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
 #pragma unroll
   for (int i = 0; i < A_LOADS; ++i) {
-    const int e = (i * NT + tid) * VEC;
-    const int r = e / BK, c = e - r * BK;
-    offA[i] = r * np + c;
-    ldsA[i] = r * LDA + c;
+    if (DL) {
+      const int c = i * NW + wave_u;
+      const int row = c * 8 + (lane >> 3);
+      offA[i] = row * np + 2 * ((lane & 7) ^ (lane >> 3));
+      ldsA[i] = c * 128;
+    } else {
+      const int e = (i * NT + tid) * VEC;
+      const int r = e / BK, c = e - r * BK;
+      offA[i] = r * np + c;
+      ldsA[i] = r * LDA + c;
+    }
   }
 #pragma unroll
   for (int i = 0; i < B_LOADS; ++i) {
-    const int e = (i * NT + tid) * VEC;
-    const int r = e / BN, c = e - r * BN;
-    offB[i] = r * np + c;
-    ldsB[i] = r * LDB + c;
+    if (DL) {
+      const int c = i * NW + wave_u;
+      offB[i] = c * np + 2 * (lane ^ ((c & 1) << 3));
+      ldsB[i] = c * BN;
+    } else {
+      const int e = (i * NT + tid) * VEC;
+      const int r = e / BN, c = e - r * BN;
+      offB[i] = r * np + c;
+      ldsB[i] = r * LDB + c;
+    }
   }
 
   const int nseg = P.nseg;
-  const int nkt = nseg * (np / BK);
+  const int nks = np / BK;
+  const int nkt = nseg * nks;
   const int64_t a_tile = (int64_t)tile_m * BM * np;
   const int64_t b_tile = (int64_t)tile_n * BN;
 
+  // The launch's segments are read once; the cursors switch between them with
+  // selects, so the k loop issues no scalar memory loads (they share a wait
+  // counter with the LDS reads and would make the loop wait for those).
+  static_assert(MAX_SEG == 3, "segment table");
+  const T* segL[MAX_SEG];
+  const T* segR[MAX_SEG];
+  T segl[MAX_SEG], segr[MAX_SEG];
+#pragma unroll
+  for (int s = 0; s < MAX_SEG; ++s) {
+    const int si = s < nseg ? s : 0;
+    segL[s] = (const T*)P.seg[si].L + a_tile;
+    segR[s] = (const T*)P.seg[si].R + b_tile;
+    segl[s] = (T)P.seg[si].lscale;
+    segr[s] = (T)P.seg[si].rscale;
+  }
+  auto pick = [](auto a0, auto a1, auto a2, int s) { return s == 0 ? a0 : (s == 1 ? a1 : a2); };
+
   // uniform cursor: the next tile to load
   int cseg = 0, ck0 = 0;
-  const T* Lc = nullptr;
-  const T* Rc = nullptr;
-  T lsc = (T)1, rsc = (T)1;
-  if (nseg > 0) {
-    Lc = (const T*)P.seg[0].L + a_tile;
-    Rc = (const T*)P.seg[0].R + b_tile;
-    lsc = (T)P.seg[0].lscale;
-    rsc = (T)P.seg[0].rscale;
-  }
-  T pl = (T)1, pr = (T)1;   // scales of the tile held in ra / rb
-  vec_t ra[A_LOADS], rb[B_LOADS];
-
-  auto gload = [&]() {
-    const T* L = Lc + ck0;
-    const T* R = Rc + (int64_t)ck0 * np;
-#pragma unroll
-    for (int i = 0; i < A_LOADS; ++i) ra[i] = *(const vec_t*)(L + offA[i]);
-#pragma unroll
-    for (int i = 0; i < B_LOADS; ++i) rb[i] = *(const vec_t*)(R + offB[i]);
-    pl = lsc;
-    pr = rsc;
+  const T* Lc = segL[0];
+  const T* Rc = segR[0];
+  T lsc = segl[0], rsc = segr[0];
+  auto advance = [&]() {
     ck0 += BK;
     if (ck0 == np) {
       ck0 = 0;
       ++cseg;
-      if (cseg < nseg) {
-        Lc = (const T*)P.seg[cseg].L + a_tile;
-        Rc = (const T*)P.seg[cseg].R + b_tile;
-        lsc = (T)P.seg[cseg].lscale;
-        rsc = (T)P.seg[cseg].rscale;
-      }
+      const int s = cseg < nseg ? cseg : nseg - 1;
+      Lc = pick(segL[0], segL[1], segL[2], s);
+      Rc = pick(segR[0], segR[1], segR[2], s);
+      lsc = pick(segl[0], segl[1], segl[2], s);
+      rsc = pick(segr[0], segr[1], segr[2], s);
     }
   };
 
+  // staged: global -> registers (gload), registers -> LDS buffer with the
+  // operand scales applied (lstore)
+  T pl = (T)1, pr = (T)1;   // scales of the tile held in ra / rb
+  vec_t ra[DL ? 1 : A_LOADS], rb[DL ? 1 : B_LOADS];
+  auto gload = [&]() {
+    const T* L = Lc + ck0;
+    const T* R = Rc + (int64_t)ck0 * np;
+#pragma unroll
+    for (int i = 0; i < (DL ? 0 : A_LOADS); ++i) ra[i] = *(const vec_t*)(L + offA[i]);
+#pragma unroll
+    for (int i = 0; i < (DL ? 0 : B_LOADS); ++i) rb[i] = *(const vec_t*)(R + offB[i]);
+    pl = lsc;
+    pr = rsc;
+    advance();
+  };
   auto lstore = [&](int buf) {
     T* as = As0 + buf * (BM * LDA);
     T* bs = Bs0 + buf * (BK * LDB);
     if (pl != (T)1 || pr != (T)1) {
 #pragma unroll
-      for (int i = 0; i < A_LOADS; ++i) ra[i] = ra[i] * pl;
+      for (int i = 0; i < (DL ? 0 : A_LOADS); ++i) ra[i] = ra[i] * pl;
 #pragma unroll
-      for (int i = 0; i < B_LOADS; ++i) rb[i] = rb[i] * pr;
+      for (int i = 0; i < (DL ? 0 : B_LOADS); ++i) rb[i] = rb[i] * pr;
     }
 #pragma unroll
-    for (int i = 0; i < A_LOADS; ++i)
+    for (int i = 0; i < (DL ? 0 : A_LOADS); ++i)
 #pragma unroll
       for (int q = 0; q < VEC; ++q) as[ldsA[i] + q] = ra[i][q];
 #pragma unroll
-    for (int i = 0; i < B_LOADS; ++i) *(vec_t*)(bs + ldsB[i]) = rb[i];
+    for (int i = 0; i < (DL ? 0 : B_LOADS); ++i) *(vec_t*)(bs + ldsB[i]) = rb[i];
+  };
+  // direct: global -> LDS buffer; the wave's loads complete (vmcnt) before the
+  // barrier that publishes them
+  auto dload = [&](int buf) {
+    typedef __attribute__((address_space(3))) void lds_void;
+    typedef __attribute__((address_space(1))) void glb_void;
+    const T* L = Lc + ck0;
+    const T* R = Rc + (int64_t)ck0 * np;
+    T* as = As0 + buf * (BM * LDA);
+    T* bs = Bs0 + buf * (BK * LDB);
+#pragma unroll
+    for (int i = 0; i < (DL ? A_LOADS : 0); ++i)
+      __builtin_amdgcn_global_load_lds((glb_void*)(L + offA[i]), (lds_void*)(as + ldsA[i]), 16, 0, 0);
+#pragma unroll
+    for (int i = 0; i < (DL ? B_LOADS : 0); ++i)
+      __builtin_amdgcn_global_load_lds((glb_void*)(R + offB[i]), (lds_void*)(bs + ldsB[i]), 16, 0, 0);
+    advance();
+  };
+  auto dwait = [&]() {
+    if (DL) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   };
 
+  // Direct loads: the lane's read offsets for each substep (A) and each
+  // fragment column (B) follow from the permutation above; pair 2 kk + lg / 2
+  // of row r sits at pair (2 kk ^ (r & 6)) + (lg / 2 ^ (r & 1)).
+  int rdA[DL ? KK : 1], rdB[DL ? FN : 1];
+  if (DL) {
+    const int xa = lr & 7;
+#pragma unroll
+    for (int kk = 0; kk < (DL ? KK : 0); ++kk)
+      rdA[kk] = (wm * WTM + lr) * LDA + 2 * (((2 * kk) ^ (xa & 6)) + ((lg >> 1) ^ (xa & 1))) + (lg & 1);
+#pragma unroll
+    for (int j = 0; j < (DL ? FN : 0); ++j)
+      rdB[j] = lg * LDB + 2 * (((wn * WTN + j * 16 + lr) >> 1) ^ ((lg & 1) << 3)) + (lr & 1);
+  }
+  // Fragment reads. With direct loads of a launch that has operand scales
+  // (DL = 2) the scales of the k step the fragments belong to are applied
+  // here: the same products as when staging.
   T fa[2][FM], fb[2][FN];
-  auto lread = [&](int buf, int kk, T (&a)[FM], T (&b)[FN]) {
-    const T* as = As0 + buf * (BM * LDA) + (wm * WTM + lr) * LDA + lg + kk * 4;
-    const T* bs = Bs0 + buf * (BK * LDB) + (lg + kk * 4) * LDB + wn * WTN + lr;
+  auto lread = [&](int buf, int kk, T sa, T sb, T (&a)[FM], T (&b)[FN]) {
+    if (DL) {
+      const T* as = As0 + buf * (BM * LDA) + rdA[DL ? kk : 0];
+      const T* bs = Bs0 + buf * (BK * LDB) + kk * 4 * LDB;
 #pragma unroll
-    for (int i = 0; i < FM; ++i) a[i] = as[i * 16 * LDA];
+      for (int i = 0; i < FM; ++i) a[i] = as[i * 16 * LDA];
 #pragma unroll
-    for (int j = 0; j < FN; ++j) b[j] = bs[j * 16];
+      for (int j = 0; j < FN; ++j) b[j] = bs[rdB[DL ? j : 0]];
+      if (DL == 2) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i) a[i] *= sa;
+#pragma unroll
+        for (int j = 0; j < FN; ++j) b[j] *= sb;
+      }
+    } else {
+      (void)sa;
+      (void)sb;
+      const T* as = As0 + buf * (BM * LDA) + (wm * WTM + lr) * LDA + lg + kk * 4;
+      const T* bs = Bs0 + buf * (BK * LDB) + (lg + kk * 4) * LDB + wn * WTN + lr;
+#pragma unroll
+      for (int i = 0; i < FM; ++i) a[i] = as[i * 16 * LDA];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) b[j] = bs[j * 16];
+    }
+  };
+  // scales of the step whose first fragments are read next (DL = 2)
+  int rseg = 0, rk = 0;
+  auto next_scales = [&](T& sa, T& sb) {
+    if (++rk == nks) {
+      rk = 0;
+      ++rseg;
+    }
+    const int s = rseg < nseg ? rseg : nseg - 1;
+    sa = pick(segl[0], segl[1], segl[2], s);
+    sb = pick(segr[0], segr[1], segr[2], s);
   };
 
   if (nkt > 0) {
-    gload();
-    lstore(0);
+    if (DL) {
+      dload(0);
+    } else {
+      gload();
+      lstore(0);
+    }
   }
+  dwait();
   __syncthreads();
-  if (nkt > 0) lread(0, 0, fa[0], fb[0]);
+  T sa_c = segl[0], sb_c = segr[0];   // operand scales of step kt (DL = 2)
+  if (nkt > 0) lread(0, 0, sa_c, sb_c, fa[0], fb[0]);
 
   for (int kt = 0; kt < nkt; ++kt) {
     const int cur = kt & 1;
-    const bool more = kt + 1 < nkt;
-    if (more) gload();
+    T sa_n = (T)1, sb_n = (T)1;   // of step kt + 1
+    if (DL == 2) next_scales(sa_n, sb_n);
+    if (kt + 1 < nkt) {
+      if (DL) dload(cur ^ 1);
+      else gload();
+    }
 #pragma unroll
     for (int kk = 0; kk < KK; ++kk) {
       const int f = kk & 1;
       if (kk + 1 < KK) {
-        lread(cur, kk + 1, fa[f ^ 1], fb[f ^ 1]);
+        lread(cur, kk + 1, sa_c, sb_c, fa[f ^ 1], fb[f ^ 1]);
       } else {
         // unconditional: on the last step these move stale values that are never
         // used, and the fragment registers keep one assignment around the loop
         lstore(cur ^ 1);
+        dwait();
         __syncthreads();
-        lread(cur ^ 1, 0, fa[f ^ 1], fb[f ^ 1]);
+        lread(cur ^ 1, 0, sa_n, sb_n, fa[f ^ 1], fb[f ^ 1]);
       }
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = M::mma(fa[f][i], fb[f][j], acc[i][j]);
     }
+    sa_c = sa_n;
+    sb_c = sb_n;
   }
 
   epilogue_bands<T, BM, BN, WGM, WGN, M>(P, np, tile_m, tile_n, acc, smem);
@@ -277,11 +408,23 @@ int choose_tile(Arith ar, int64_t n) {
   return 2;
 }
 
-template <typename T, int BM, int BN, int BK, int WGM, int WGN, int WPE>
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int WPE, int DL>
 static sincosm_status launch_cfg(const GemmLaunch& g, hipStream_t stream) {
   const int tiles = (g.np / BM) * (g.np / BN) * g.nprob;
   if (tiles <= 0) return SINCOSM_OK;
-  gemm_kernel<T, BM, BN, BK, WGM, WGN, WPE><<<tiles, WGM * WGN * 64, 0, stream>>>(g);
+  bool scaled = false;
+  for (int p = 0; p < g.nprob; ++p)
+    for (int s = 0; s < g.prob[p].nseg; ++s)
+      scaled |= g.prob[p].seg[s].lscale != 1.0 || g.prob[p].seg[s].rscale != 1.0;
+  if constexpr (DL != 0) {
+    if (scaled)
+      gemm_kernel<T, BM, BN, BK, WGM, WGN, WPE, 2><<<tiles, WGM * WGN * 64, 0, stream>>>(g);
+    else
+      gemm_kernel<T, BM, BN, BK, WGM, WGN, WPE, 1><<<tiles, WGM * WGN * 64, 0, stream>>>(g);
+  } else {
+    (void)scaled;
+    gemm_kernel<T, BM, BN, BK, WGM, WGN, WPE, 0><<<tiles, WGM * WGN * 64, 0, stream>>>(g);
+  }
   SC_HIP(hipGetLastError());
   return SINCOSM_OK;
 }
@@ -289,30 +432,31 @@ static sincosm_status launch_cfg(const GemmLaunch& g, hipStream_t stream) {
 
 // ----------------------------------------------------------------------------
 // Kernel configurations the autotuner chooses among. Each entry: tile rows and
-// columns, k depth, wave grid, waves per SIMD. Entries 0, 1, 2 are the
-// defaults for the three padding granularities 128, 64 and 32.
+// columns, k depth, wave grid, waves per SIMD, direct loads into LDS. Entries
+// 0, 1, 2 are the defaults for the three padding granularities 128, 64 and 32.
 // ----------------------------------------------------------------------------
 typedef sincosm_status (*LaunchFn)(const GemmLaunch&, hipStream_t);
 struct KernelCfg {
-  int bm, bn, bk, wgm, wgn, wpe;
+  int bm, bn, bk, wgm, wgn, wpe, dl;
   LaunchFn fn;
 };
 
-#define SC_CFG(T, BM, BN, BK, WGM, WGN, WPE) \
-  { BM, BN, BK, WGM, WGN, WPE, &launch_cfg<T, BM, BN, BK, WGM, WGN, WPE> }
+#define SC_CFG(T, BM, BN, BK, WGM, WGN, WPE, DL) \
+  { BM, BN, BK, WGM, WGN, WPE, DL, &launch_cfg<T, BM, BN, BK, WGM, WGN, WPE, DL> }
 
 static const KernelCfg kF64[] = {
-    SC_CFG(double, 128, 128, 16, 2, 2, 2), SC_CFG(double, 64, 64, 16, 2, 2, 2),
-    SC_CFG(double, 32, 32, 16, 2, 2, 2),   SC_CFG(double, 128, 128, 32, 2, 2, 1),
-    SC_CFG(double, 256, 128, 16, 4, 2, 2), SC_CFG(double, 128, 128, 16, 2, 4, 2),
-    SC_CFG(double, 128, 64, 16, 2, 2, 2),  SC_CFG(double, 64, 128, 16, 2, 2, 2),
-    SC_CFG(double, 128, 128, 8, 2, 2, 2),
+    SC_CFG(double, 128, 128, 16, 2, 2, 2, 0), SC_CFG(double, 64, 64, 16, 2, 2, 2, 0),
+    SC_CFG(double, 32, 32, 16, 2, 2, 2, 0),   SC_CFG(double, 128, 128, 32, 2, 2, 1, 0),
+    SC_CFG(double, 256, 128, 16, 4, 2, 2, 0), SC_CFG(double, 128, 128, 16, 2, 4, 2, 0),
+    SC_CFG(double, 128, 64, 16, 2, 2, 2, 0),  SC_CFG(double, 64, 128, 16, 2, 2, 2, 0),
+    SC_CFG(double, 128, 128, 8, 2, 2, 2, 0),  SC_CFG(double, 256, 128, 16, 4, 2, 2, 1),
+    SC_CFG(double, 128, 128, 16, 2, 2, 2, 1), SC_CFG(double, 128, 128, 16, 2, 4, 2, 1),
 };
 static const KernelCfg kF32[] = {
-    SC_CFG(float, 128, 128, 16, 2, 2, 2), SC_CFG(float, 64, 64, 16, 2, 2, 2),
-    SC_CFG(float, 32, 32, 32, 2, 2, 2),   SC_CFG(float, 128, 128, 32, 2, 2, 2),
-    SC_CFG(float, 256, 128, 16, 4, 2, 2), SC_CFG(float, 128, 128, 16, 2, 4, 2),
-    SC_CFG(float, 64, 64, 32, 2, 2, 2),
+    SC_CFG(float, 128, 128, 16, 2, 2, 2, 0), SC_CFG(float, 64, 64, 16, 2, 2, 2, 0),
+    SC_CFG(float, 32, 32, 32, 2, 2, 2, 0),   SC_CFG(float, 128, 128, 32, 2, 2, 2, 0),
+    SC_CFG(float, 256, 128, 16, 4, 2, 2, 0), SC_CFG(float, 128, 128, 16, 2, 4, 2, 0),
+    SC_CFG(float, 64, 64, 32, 2, 2, 2, 0),
 };
 
 static const KernelCfg* cfg_table(Arith ar, int& count) {
@@ -367,7 +511,7 @@ sincosm_status sincosm_tune_config_info(int arith, int idx, int32_t* info) {
   const sc::KernelCfg* t = sc::cfg_table((sc::Arith)(arith & ~(int)SINCOSM_TUNE_MULTI), count);
   if (!t || !info || idx < 0 || idx >= count) return SINCOSM_E_ARG;
   info[0] = t[idx].bm; info[1] = t[idx].bn; info[2] = t[idx].bk;
-  info[3] = t[idx].wgm; info[4] = t[idx].wgn; info[5] = t[idx].wpe;
+  info[3] = t[idx].wgm; info[4] = t[idx].wgn; info[5] = t[idx].wpe; info[6] = t[idx].dl;
   return SINCOSM_OK;
 }
 

@@ -26,7 +26,7 @@ def env():
 
 def configs(lib, arith):
     out = []
-    info = (ctypes.c_int32 * 6)()
+    info = (ctypes.c_int32 * 7)()
     for i in range(lib.sincosm_tune_num_configs(arith)):
         lib.sincosm_tune_config_info(arith, i, info)
         out.append((i, info[0], info[1]))

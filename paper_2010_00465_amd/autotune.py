@@ -13,7 +13,8 @@ configuration per probe and class is written to a JSON cache with the range of
 padded orders it covers (midpoints between probes). ``apply_cache`` installs a
 cache in the library; the package calls it at import for the cache shipped
 next to this file (``tune_gfx950.json``) or the file named by
-``SINCOSM_TUNE_CACHE``.
+``SINCOSM_TUNE_CACHE``. Entries of an arithmetic whose recorded configuration
+table differs from the library's are skipped.
 
 Usage on the GPU:  python -m paper_2010_00465_amd.autotune --out paper_2010_00465_amd/tune_gfx950.json
 """
@@ -61,6 +62,8 @@ def apply_cache(path: str | None = None) -> int:
         arith, _, cls = key.partition("_")
         if arith not in ARITH or cls not in ("", "multi"):
             continue
+        if data.get("configs", {}).get(arith) != configs(arith):
+            continue   # tuned against another configuration table: its indices mean other kernels
         code = ARITH[arith] | (MULTI if cls == "multi" else 0)
         for e in entries:
             if lib.sincosm_tune_set(code, int(e["np_lo"]), int(e["np_hi"]), int(e["idx"])) == 0:

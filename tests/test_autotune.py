@@ -61,6 +61,31 @@ def test_shipped_cache_is_consistent(lib):
             assert e["probe_np"] % info["bm"] == 0 and e["probe_np"] % info["bn"] == 0
 
 
+def test_shipped_cache_matches_table_and_applies(lib):
+    from paper_2010_00465_amd import autotune
+    data = json.load(open(autotune.DEFAULT_CACHE))
+    for arith in autotune.ARITH:
+        assert data["configs"][arith] == autotune.configs(arith)
+    expected = sum(len(v) for v in data["entries"].values())
+    assert autotune.apply_cache() == expected
+
+
+def test_cache_of_another_table_is_skipped(lib, tmp_path):
+    from paper_2010_00465_amd import autotune
+    data = json.load(open(autotune.DEFAULT_CACHE))
+    data["configs"]["f64"] = data["configs"]["f64"][:-1]        # a table with one entry less
+    p = tmp_path / "cache.json"
+    p.write_text(json.dumps(data))
+    try:
+        applied = autotune.apply_cache(str(p))
+        assert applied == sum(len(v) for k, v in data["entries"].items() if not k.startswith("f64"))
+    finally:
+        for arith in autotune.ARITH.values():
+            for code in (arith, arith | autotune.MULTI):
+                lib.sincosm_tune_set(code, 1, 1 << 30, -1)
+        autotune.apply_cache()
+
+
 def test_multi_class_flag(lib):
     """SINCOSM_TUNE_MULTI addresses a second table; the configuration list is the same."""
     from paper_2010_00465_amd import autotune

@@ -15,8 +15,8 @@
 //  * Operand tiles go through LDS, double buffered, one barrier per BK step in
 //    the step's last substep of MFMAs; the global loads of the next tile are
 //    issued before the MFMAs of the current one so their latency hides behind
-//    the matrix core. In float64 they can be loaded straight into LDS
-//    (global_load_lds), with no register round trip or LDS store instructions.
+//    the matrix core. They can be loaded straight into LDS (global_load_lds),
+//    with no register round trip or LDS store instructions.
 //  * LDS layouts: A as [m][k] with row pitch BK+1, B as [k][n] with row pitch
 //    BN+16, so the 16-lane groups that feed one MFMA read distinct banks.
 //  * All operands are internal buffers padded with zeros to a multiple of the
@@ -130,10 +130,18 @@ void gemm_kernel(const GemmLaunch g) {
   static_assert(A_LOADS >= 1 && A_LOADS * VEC * NT == BM * BK, "A staging");
   static_assert(B_LOADS >= 1 && B_LOADS * VEC * NT == BK * BN, "B staging");
   static_assert(BK % 8 == 0 && BK % VEC == 0 && BN % VEC == 0, "k tiling (even substep count)");
-  // direct loads: one wave instruction fills 1 KiB of LDS (64 lanes x 16 bytes),
-  // 8 rows of an A tile of depth 16 or one 128-wide row of a B tile
-  static_assert(!DL || (sizeof(T) == 8 && BK == 16 && BN == 128 && A_LOADS * NW * 8 == BM && B_LOADS * NW == BK),
-                "direct loads: float64, k depth 16, 128-wide tiles");
+  // Direct loads: one wave instruction fills a 1 KiB chunk of LDS (64 lanes x
+  // one 16-byte slot of VEC values). An A row (BK values) has QA slots and a
+  // chunk holds RA rows; a B row (BN values) has QB slots and a chunk holds RB
+  // rows. Rows of A repeat their bank offsets every PA rows (256 bytes: 64
+  // banks of 4 bytes); the 16 columns of one B fragment span 1 / GB of the
+  // banks.
+  constexpr int QA = BK / VEC, QB = BN / VEC;
+  constexpr int RA = 64 / QA, RB = 64 / QB;
+  constexpr int PA = 256 / (BK * (int)sizeof(T)), GB = 256 / (16 * (int)sizeof(T));
+  static_assert(!DL || (BK * sizeof(T) >= 64 && BK * sizeof(T) <= 128 && PA * QA == 16 &&
+                        QB <= 64 && 64 % QB == 0 && A_LOADS * NW * RA == BM && B_LOADS * NW * RB == BK),
+                "direct loads: 64- or 128-byte A rows, B rows that divide 1 KiB");
 
   __shared__ __attribute__((aligned(16))) T smem[SMEM_ELEMS];
   T* const As0 = smem;
@@ -159,20 +167,20 @@ void gemm_kernel(const GemmLaunch g) {
 
   // Global offsets of this thread's loads and their LDS places. Staged loads
   // go through registers into padded rows. A direct load writes lane l's 16
-  // bytes to byte 16 l of the wave's 1 KiB chunk, so the lane picks the source
-  // that belongs there: in an A chunk (rows 8c..8c+7, 16 values each), slot
-  // (row, pair q) holds pair q ^ (row & 7) of that row; in a B chunk (k row c),
-  // slot pair q holds column pair q ^ 8 (c & 1). The fragment reads undo the
-  // permutation, and the 16 lanes x 4 rows of one read hit every bank twice.
+  // bytes to slot l of the wave's 1 KiB chunk, so the lane picks the source
+  // that belongs there: slot q of A row r holds slot q ^ ((r / PA) % QA) of
+  // that row, slot q of B row k holds column slot q ^ (sizeof(T) (k % GB)).
+  // The fragment reads undo the permutation; the 16 lanes x 4 k of one read
+  // then spread evenly over the 64 banks.
   int offA[A_LOADS], offB[B_LOADS], ldsA[A_LOADS], ldsB[B_LOADS];
   const int wave_u = __builtin_amdgcn_readfirstlane(wave);
 #pragma unroll
   for (int i = 0; i < A_LOADS; ++i) {
     if (DL) {
       const int c = i * NW + wave_u;
-      const int row = c * 8 + (lane >> 3);
-      offA[i] = row * np + 2 * ((lane & 7) ^ (lane >> 3));
-      ldsA[i] = c * 128;
+      const int row = c * RA + lane / QA;
+      offA[i] = row * np + VEC * ((lane % QA) ^ ((row / PA) % QA));
+      ldsA[i] = c * 64 * VEC;
     } else {
       const int e = (i * NT + tid) * VEC;
       const int r = e / BK, c = e - r * BK;
@@ -184,8 +192,9 @@ void gemm_kernel(const GemmLaunch g) {
   for (int i = 0; i < B_LOADS; ++i) {
     if (DL) {
       const int c = i * NW + wave_u;
-      offB[i] = c * np + 2 * (lane ^ ((c & 1) << 3));
-      ldsB[i] = c * BN;
+      const int k = c * RB + lane / QB;
+      offB[i] = k * np + VEC * ((lane % QB) ^ ((int)sizeof(T) * (k % GB)));
+      ldsB[i] = c * 64 * VEC;
     } else {
       const int e = (i * NT + tid) * VEC;
       const int r = e / BN, c = e - r * BN;
@@ -288,17 +297,22 @@ void gemm_kernel(const GemmLaunch g) {
   };
 
   // Direct loads: the lane's read offsets for each substep (A) and each
-  // fragment column (B) follow from the permutation above; pair 2 kk + lg / 2
-  // of row r sits at pair (2 kk ^ (r & 6)) + (lg / 2 ^ (r & 1)).
+  // fragment column (B) under the permutation above. The A rows of a lane
+  // differ by multiples of 16 = PA QA, so they share the permutation; its k
+  // in substep kk is 4 kk + lg, and k % GB = lg % GB for B.
   int rdA[DL ? KK : 1], rdB[DL ? FN : 1];
   if (DL) {
-    const int xa = lr & 7;
+    const int ra = wm * WTM + lr;
 #pragma unroll
-    for (int kk = 0; kk < (DL ? KK : 0); ++kk)
-      rdA[kk] = (wm * WTM + lr) * LDA + 2 * (((2 * kk) ^ (xa & 6)) + ((lg >> 1) ^ (xa & 1))) + (lg & 1);
+    for (int kk = 0; kk < (DL ? KK : 0); ++kk) {
+      const int k = kk * 4 + lg;
+      rdA[kk] = ra * LDA + VEC * ((k / VEC) ^ ((ra / PA) % QA)) + k % VEC;
+    }
 #pragma unroll
-    for (int j = 0; j < (DL ? FN : 0); ++j)
-      rdB[j] = lg * LDB + 2 * (((wn * WTN + j * 16 + lr) >> 1) ^ ((lg & 1) << 3)) + (lr & 1);
+    for (int j = 0; j < (DL ? FN : 0); ++j) {
+      const int col = wn * WTN + j * 16 + lr;
+      rdB[j] = lg * LDB + VEC * ((col / VEC) ^ ((int)sizeof(T) * (lg % GB))) + col % VEC;
+    }
   }
   // Fragment reads. With direct loads of a launch that has operand scales
   // (DL = 2) the scales of the k step the fragments belong to are applied
@@ -456,7 +470,8 @@ static const KernelCfg kF32[] = {
     SC_CFG(float, 128, 128, 16, 2, 2, 2, 0), SC_CFG(float, 64, 64, 16, 2, 2, 2, 0),
     SC_CFG(float, 32, 32, 32, 2, 2, 2, 0),   SC_CFG(float, 128, 128, 32, 2, 2, 2, 0),
     SC_CFG(float, 256, 128, 16, 4, 2, 2, 0), SC_CFG(float, 128, 128, 16, 2, 4, 2, 0),
-    SC_CFG(float, 64, 64, 32, 2, 2, 2, 0),
+    SC_CFG(float, 64, 64, 32, 2, 2, 2, 0),   SC_CFG(float, 128, 128, 32, 2, 2, 2, 1),
+    SC_CFG(float, 256, 128, 16, 4, 2, 2, 1), SC_CFG(float, 128, 128, 16, 2, 2, 2, 1),
 };
 
 static const KernelCfg* cfg_table(Arith ar, int& count) {

@@ -275,8 +275,9 @@ sincosm_status sincosm_timing_read(int kind, double* total_ms, int64_t* count);
 /* Autotuning of the product kernel. `arith` is 0 for float64 products, 1 for
  * float32 products. Each arithmetic offers a list of kernel configurations
  * (tile rows, tile columns, k depth, wave rows, wave columns, waves per SIMD,
- * 1 if operand tiles are loaded straight into LDS -> info[0..6]; info must
- * hold 7 entries); entries 0, 1 and 2 are the defaults for padding
+ * 1 if operand tiles are loaded straight into LDS, number of k groups that
+ * split the k steps of a tile -> info[0..7]; info must hold 8 entries);
+ * entries 0, 1 and 2 are the defaults for padding
  * granularities 128, 64 and 32. sincosm_tune_set makes launches of that
  * arithmetic whose padded order lies in [np_lo, np_hi] use configuration idx
  * (later entries win; idx = -1 removes the overlapping entries); a

@@ -43,10 +43,10 @@ def padded(n: int) -> int:
 def configs(arith: str):
     out = []
     for i in range(lib.sincosm_tune_num_configs(ARITH[arith])):
-        info = (ctypes.c_int32 * 7)()
+        info = (ctypes.c_int32 * 8)()
         lib.sincosm_tune_config_info(ARITH[arith], i, info)
         out.append({"idx": i, "bm": info[0], "bn": info[1], "bk": info[2], "wgm": info[3], "wgn": info[4],
-                    "wpe": info[5], "direct": info[6]})
+                    "wpe": info[5], "direct": info[6], "kgroups": info[7]})
     return out
 
 

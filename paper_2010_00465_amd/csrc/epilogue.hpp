@@ -26,13 +26,17 @@ struct VecOf<float> {
   static constexpr int N = 4;
 };
 
-// smem must hold at least (BM / WGM) * (BN + VEC) elements of T.
-template <typename T, int BM, int BN, int WGM, int WGN, typename M, typename AccT, int FM, int FN>
+// smem must hold at least (BM / WGM) * (BN + VEC) elements of T. The waves
+// 0 .. WGM WGN - 1 own the accumulators; NTHR threads (a multiple of 64, at
+// least the owners') share the reading and writing, and all of them call this.
+template <typename T, int BM, int BN, int WGM, int WGN, typename M, typename AccT, int FM, int FN,
+          int NTHR = WGM * WGN * 64>
 __device__ inline void epilogue_bands(const Problem& P, int np, int tile_m, int tile_n, AccT (&acc)[FM][FN],
                                       T* smem) {
   using vec_t = typename VecOf<T>::t;
   constexpr int VEC = VecOf<T>::N;
-  constexpr int NT = WGM * WGN * 64;
+  constexpr int NT = NTHR;
+  static_assert(NT % 64 == 0 && NT >= WGM * WGN * 64, "epilogue threads");
   constexpr int WTM = BM / WGM, WTN = BN / WGN;
   constexpr int LDE = BN + VEC;
   const int tid = threadIdx.x;

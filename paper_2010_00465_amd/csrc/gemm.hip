@@ -107,14 +107,14 @@ __device__ inline void tile_coords(int np, int BM, int BN, int nprob, int& p, in
 // they completed before any wave passed B_{k-1}. Before B_k each wave waits
 // for its own stores or direct loads (vmcnt for the latter); the reads of
 // buffer (k+1)&1 in step k+1 start after B_k.
-template <typename T, int BM, int BN, int BK, int WGM, int WGN, int WPE, int DL>
-__global__ __launch_bounds__(WGM * WGN * 64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int WPE, int DL, int KS>
+__global__ __launch_bounds__(WGM * WGN * KS * 64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void gemm_kernel(const GemmLaunch g) {
   using M = Mma<T>;
   using acc_t = typename M::acc_t;
   using vec_t = typename M::vec_t;
-  constexpr int NW = WGM * WGN;
-  constexpr int NT = NW * 64;
+  constexpr int NW = WGM * WGN;   // waves of one k group
+  constexpr int NT = NW * 64;     // threads of one k group
   constexpr int WTM = BM / WGM, WTN = BN / WGN;
   constexpr int FM = WTM / 16, FN = WTN / 16;
   constexpr int LDA = DL ? BK : BK + 1, LDB = DL ? BN : BN + 16;
@@ -123,9 +123,12 @@ void gemm_kernel(const GemmLaunch g) {
   constexpr int A_LOADS = BM * BK / VEC / NT;
   constexpr int B_LOADS = BK * BN / VEC / NT;
   constexpr int LDE = BN + VEC;
-  constexpr int STAGE_ELEMS = 2 * (BM * LDA + BK * LDB);
+  constexpr int GROUP_ELEMS = 2 * (BM * LDA + BK * LDB);   // the two LDS buffers of a k group
+  constexpr int STAGE_ELEMS = KS * GROUP_ELEMS;
+  constexpr int RED_ELEMS = KS > 1 ? BM * BN : 0;
   constexpr int EPI_ELEMS = WTM * LDE;
-  constexpr int SMEM_ELEMS = STAGE_ELEMS > EPI_ELEMS ? STAGE_ELEMS : EPI_ELEMS;
+  constexpr int SMEM_ELEMS = STAGE_ELEMS > EPI_ELEMS ? (STAGE_ELEMS > RED_ELEMS ? STAGE_ELEMS : RED_ELEMS)
+                                                     : (EPI_ELEMS > RED_ELEMS ? EPI_ELEMS : RED_ELEMS);
   static_assert(FM >= 1 && FN >= 1 && WTM % 16 == 0 && WTN % 16 == 0, "wave tile");
   static_assert(A_LOADS >= 1 && A_LOADS * VEC * NT == BM * BK, "A staging");
   static_assert(B_LOADS >= 1 && B_LOADS * VEC * NT == BK * BN, "B staging");
@@ -143,19 +146,28 @@ void gemm_kernel(const GemmLaunch g) {
                         QB <= 64 && 64 % QB == 0 && A_LOADS * NW * RA == BM && B_LOADS * NW * RB == BK),
                 "direct loads: 64- or 128-byte A rows, B rows that divide 1 KiB");
 
+  static_assert(KS == 1 || KS == 2, "one or two k groups");
+
+  // k groups (KS = 2): the waves split into two groups of WGM x WGN waves that
+  // take alternate k steps of the same output tile, each with its own LDS
+  // buffers; at the end the second group's accumulators are added to the
+  // first's through LDS (a fixed order, so results are deterministic).
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int grp = KS > 1 ? __builtin_amdgcn_readfirstlane(wave / NW) : 0;
+  const int wl = wave - grp * NW;   // wave within its group
+  const int tidg = tid - grp * NT;  // thread within its group
+  const int wm = wl / WGN, wn = wl % WGN;
+  const int lr = lane & 15, lg = lane >> 4;
+
   __shared__ __attribute__((aligned(16))) T smem[SMEM_ELEMS];
-  T* const As0 = smem;
-  T* const Bs0 = smem + 2 * BM * LDA;
+  T* const As0 = smem + grp * GROUP_ELEMS;
+  T* const Bs0 = As0 + 2 * BM * LDA;
 
   const int np = g.np;
   int p, tile_m, tile_n;
   tile_coords(np, BM, BN, g.nprob, p, tile_m, tile_n);
   const Problem& P = g.prob[p];
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave / WGN, wn = wave % WGN;
-  const int lr = lane & 15, lg = lane >> 4;
 
   acc_t acc[FM][FN];
 #pragma unroll
@@ -173,7 +185,7 @@ void gemm_kernel(const GemmLaunch g) {
   // The fragment reads undo the permutation; the 16 lanes x 4 k of one read
   // then spread evenly over the 64 banks.
   int offA[A_LOADS], offB[B_LOADS], ldsA[A_LOADS], ldsB[B_LOADS];
-  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+  const int wave_u = __builtin_amdgcn_readfirstlane(wl);
 #pragma unroll
   for (int i = 0; i < A_LOADS; ++i) {
     if (DL) {
@@ -182,7 +194,7 @@ void gemm_kernel(const GemmLaunch g) {
       offA[i] = row * np + VEC * ((lane % QA) ^ ((row / PA) % QA));
       ldsA[i] = c * 64 * VEC;
     } else {
-      const int e = (i * NT + tid) * VEC;
+      const int e = (i * NT + tidg) * VEC;
       const int r = e / BK, c = e - r * BK;
       offA[i] = r * np + c;
       ldsA[i] = r * LDA + c;
@@ -196,7 +208,7 @@ void gemm_kernel(const GemmLaunch g) {
       offB[i] = k * np + VEC * ((lane % QB) ^ ((int)sizeof(T) * (k % GB)));
       ldsB[i] = c * 64 * VEC;
     } else {
-      const int e = (i * NT + tid) * VEC;
+      const int e = (i * NT + tidg) * VEC;
       const int r = e / BN, c = e - r * BN;
       offB[i] = r * np + c;
       ldsB[i] = r * LDB + c;
@@ -243,6 +255,12 @@ void gemm_kernel(const GemmLaunch g) {
       rsc = pick(segr[0], segr[1], segr[2], s);
     }
   };
+  // a k group loads every KS-th step, starting at its own index
+  auto advance_group = [&]() {
+#pragma unroll
+    for (int q = 0; q < KS; ++q) advance();
+  };
+  for (int q = 0; q < grp; ++q) advance();
 
   // staged: global -> registers (gload), registers -> LDS buffer with the
   // operand scales applied (lstore)
@@ -257,7 +275,7 @@ void gemm_kernel(const GemmLaunch g) {
     for (int i = 0; i < (DL ? 0 : B_LOADS); ++i) rb[i] = *(const vec_t*)(R + offB[i]);
     pl = lsc;
     pr = rsc;
-    advance();
+    advance_group();
   };
   auto lstore = [&](int buf) {
     T* as = As0 + buf * (BM * LDA);
@@ -290,7 +308,7 @@ void gemm_kernel(const GemmLaunch g) {
 #pragma unroll
     for (int i = 0; i < (DL ? B_LOADS : 0); ++i)
       __builtin_amdgcn_global_load_lds((glb_void*)(R + offB[i]), (lds_void*)(bs + ldsB[i]), 16, 0, 0);
-    advance();
+    advance_group();
   };
   auto dwait = [&]() {
     if (DL) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -343,12 +361,16 @@ void gemm_kernel(const GemmLaunch g) {
       for (int j = 0; j < FN; ++j) b[j] = bs[j * 16];
     }
   };
-  // scales of the step whose first fragments are read next (DL = 2)
-  int rseg = 0, rk = 0;
+  // scales of the step whose first fragments are read next (DL = 2): the
+  // group's steps are KS apart, and its first one lies in segment 0
+  int rseg = 0, rk = grp;
   auto next_scales = [&](T& sa, T& sb) {
-    if (++rk == nks) {
-      rk = 0;
-      ++rseg;
+#pragma unroll
+    for (int q = 0; q < KS; ++q) {
+      if (++rk == nks) {
+        rk = 0;
+        ++rseg;
+      }
     }
     const int s = rseg < nseg ? rseg : nseg - 1;
     sa = pick(segl[0], segl[1], segl[2], s);
@@ -365,14 +387,17 @@ void gemm_kernel(const GemmLaunch g) {
   }
   dwait();
   __syncthreads();
-  T sa_c = segl[0], sb_c = segr[0];   // operand scales of step kt (DL = 2)
+  T sa_c = segl[0], sb_c = segr[0];   // operand scales of the current step (DL = 2)
   if (nkt > 0) lread(0, 0, sa_c, sb_c, fa[0], fb[0]);
 
-  for (int kt = 0; kt < nkt; ++kt) {
-    const int cur = kt & 1;
-    T sa_n = (T)1, sb_n = (T)1;   // of step kt + 1
+  // Each group takes nkt / KS steps: the padded order is a multiple of BK KS
+  // (checked at launch), so nkt is too and both groups meet every barrier.
+  const int nit = nkt / KS;
+  for (int it = 0; it < nit; ++it) {
+    const int cur = it & 1;
+    T sa_n = (T)1, sb_n = (T)1;   // of the group's next step
     if (DL == 2) next_scales(sa_n, sb_n);
-    if (kt + 1 < nkt) {
+    if (it + 1 < nit) {
       if (DL) dload(cur ^ 1);
       else gload();
     }
@@ -398,7 +423,34 @@ void gemm_kernel(const GemmLaunch g) {
     sb_c = sb_n;
   }
 
-  epilogue_bands<T, BM, BN, WGM, WGN, M>(P, np, tile_m, tile_n, acc, smem);
+  if constexpr (KS > 1) {
+    // second group's accumulators -> LDS (element-major, so a wave's 64 lanes
+    // write consecutive slots), then added to the first group's
+    constexpr int NACC = FM * FN * 4;
+    static_assert(NACC * NT == BM * BN && RED_ELEMS <= SMEM_ELEMS, "reduction buffer");
+    __syncthreads();   // every wave is done with the stage buffers
+    if (grp == 1) {
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) smem[((i * FN + j) * 4 + r) * NT + tidg] = acc[i][j][r];
+    }
+    __syncthreads();
+    if (grp == 0) {
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[i][j][r] += smem[((i * FN + j) * 4 + r) * NT + tidg];
+    }
+    __syncthreads();   // the epilogue reuses the buffer
+  }
+  // the epilogue's band owners are the first group's waves (the second
+  // group's wave rows lie beyond WGM); all KS x NT threads write the outputs
+  epilogue_bands<T, BM, BN, WGM, WGN, M, acc_t, FM, FN, KS * NT>(P, np, tile_m, tile_n, acc, smem);
 }
 
 // ----------------------------------------------------------------------------
@@ -422,22 +474,23 @@ int choose_tile(Arith ar, int64_t n) {
   return 2;
 }
 
-template <typename T, int BM, int BN, int BK, int WGM, int WGN, int WPE, int DL>
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int WPE, int DL, int KS>
 static sincosm_status launch_cfg(const GemmLaunch& g, hipStream_t stream) {
   const int tiles = (g.np / BM) * (g.np / BN) * g.nprob;
   if (tiles <= 0) return SINCOSM_OK;
+  if ((g.np / BK) % KS != 0) return SINCOSM_E_ARG;   // k groups need a step count divisible by KS
   bool scaled = false;
   for (int p = 0; p < g.nprob; ++p)
     for (int s = 0; s < g.prob[p].nseg; ++s)
       scaled |= g.prob[p].seg[s].lscale != 1.0 || g.prob[p].seg[s].rscale != 1.0;
   if constexpr (DL != 0) {
     if (scaled)
-      gemm_kernel<T, BM, BN, BK, WGM, WGN, WPE, 2><<<tiles, WGM * WGN * 64, 0, stream>>>(g);
+      gemm_kernel<T, BM, BN, BK, WGM, WGN, WPE, 2, KS><<<tiles, WGM * WGN * KS * 64, 0, stream>>>(g);
     else
-      gemm_kernel<T, BM, BN, BK, WGM, WGN, WPE, 1><<<tiles, WGM * WGN * 64, 0, stream>>>(g);
+      gemm_kernel<T, BM, BN, BK, WGM, WGN, WPE, 1, KS><<<tiles, WGM * WGN * KS * 64, 0, stream>>>(g);
   } else {
     (void)scaled;
-    gemm_kernel<T, BM, BN, BK, WGM, WGN, WPE, 0><<<tiles, WGM * WGN * 64, 0, stream>>>(g);
+    gemm_kernel<T, BM, BN, BK, WGM, WGN, WPE, 0, KS><<<tiles, WGM * WGN * KS * 64, 0, stream>>>(g);
   }
   SC_HIP(hipGetLastError());
   return SINCOSM_OK;
@@ -446,17 +499,20 @@ static sincosm_status launch_cfg(const GemmLaunch& g, hipStream_t stream) {
 
 // ----------------------------------------------------------------------------
 // Kernel configurations the autotuner chooses among. Each entry: tile rows and
-// columns, k depth, wave grid, waves per SIMD, direct loads into LDS. Entries
-// 0, 1, 2 are the defaults for the three padding granularities 128, 64 and 32.
+// columns, k depth, wave grid, waves per SIMD, direct loads into LDS, k groups.
+// Entries 0, 1, 2 are the defaults for the three padding granularities 128, 64
+// and 32.
 // ----------------------------------------------------------------------------
 typedef sincosm_status (*LaunchFn)(const GemmLaunch&, hipStream_t);
 struct KernelCfg {
-  int bm, bn, bk, wgm, wgn, wpe, dl;
+  int bm, bn, bk, wgm, wgn, wpe, dl, ks;
   LaunchFn fn;
 };
 
 #define SC_CFG(T, BM, BN, BK, WGM, WGN, WPE, DL) \
-  { BM, BN, BK, WGM, WGN, WPE, DL, &launch_cfg<T, BM, BN, BK, WGM, WGN, WPE, DL> }
+  { BM, BN, BK, WGM, WGN, WPE, DL, 1, &launch_cfg<T, BM, BN, BK, WGM, WGN, WPE, DL, 1> }
+#define SC_CFG_KS(T, BM, BN, BK, WGM, WGN, WPE, DL, KS) \
+  { BM, BN, BK, WGM, WGN, WPE, DL, KS, &launch_cfg<T, BM, BN, BK, WGM, WGN, WPE, DL, KS> }
 
 static const KernelCfg kF64[] = {
     SC_CFG(double, 128, 128, 16, 2, 2, 2, 0), SC_CFG(double, 64, 64, 16, 2, 2, 2, 0),
@@ -465,6 +521,10 @@ static const KernelCfg kF64[] = {
     SC_CFG(double, 128, 64, 16, 2, 2, 2, 0),  SC_CFG(double, 64, 128, 16, 2, 2, 2, 0),
     SC_CFG(double, 128, 128, 8, 2, 2, 2, 0),  SC_CFG(double, 256, 128, 16, 4, 2, 2, 1),
     SC_CFG(double, 128, 128, 16, 2, 2, 2, 1), SC_CFG(double, 128, 128, 16, 2, 4, 2, 1),
+    SC_CFG(double, 64, 64, 16, 2, 2, 2, 1),   SC_CFG(double, 128, 64, 16, 2, 2, 2, 1),
+    SC_CFG(double, 64, 128, 16, 2, 2, 2, 1),
+    SC_CFG_KS(double, 64, 64, 16, 2, 2, 2, 1, 2), SC_CFG_KS(double, 128, 64, 16, 2, 2, 2, 1, 2),
+    SC_CFG_KS(double, 64, 64, 16, 2, 2, 2, 0, 2),
 };
 static const KernelCfg kF32[] = {
     SC_CFG(float, 128, 128, 16, 2, 2, 2, 0), SC_CFG(float, 64, 64, 16, 2, 2, 2, 0),
@@ -472,6 +532,8 @@ static const KernelCfg kF32[] = {
     SC_CFG(float, 256, 128, 16, 4, 2, 2, 0), SC_CFG(float, 128, 128, 16, 2, 4, 2, 0),
     SC_CFG(float, 64, 64, 32, 2, 2, 2, 0),   SC_CFG(float, 128, 128, 32, 2, 2, 2, 1),
     SC_CFG(float, 256, 128, 16, 4, 2, 2, 1), SC_CFG(float, 128, 128, 16, 2, 2, 2, 1),
+    SC_CFG(float, 64, 64, 32, 2, 2, 2, 1),
+    SC_CFG_KS(float, 64, 64, 32, 2, 2, 2, 1, 2), SC_CFG_KS(float, 64, 64, 16, 2, 2, 2, 1, 2),
 };
 
 static const KernelCfg* cfg_table(Arith ar, int& count) {
@@ -527,6 +589,7 @@ sincosm_status sincosm_tune_config_info(int arith, int idx, int32_t* info) {
   if (!t || !info || idx < 0 || idx >= count) return SINCOSM_E_ARG;
   info[0] = t[idx].bm; info[1] = t[idx].bn; info[2] = t[idx].bk;
   info[3] = t[idx].wgm; info[4] = t[idx].wgn; info[5] = t[idx].wpe; info[6] = t[idx].dl;
+  info[7] = t[idx].ks;
   return SINCOSM_OK;
 }
 

@@ -19,12 +19,12 @@ def test_config_table(lib):
     for arith in (0, 1):
         n = lib.sincosm_tune_num_configs(arith)
         assert n >= 3
-        info = (ctypes.c_int32 * 7)()
+        info = (ctypes.c_int32 * 8)()
         for i in range(n):
             assert lib.sincosm_tune_config_info(arith, i, info) == 0
-            bm, bn, bk, wgm, wgn, wpe, direct = list(info)
+            bm, bn, bk, wgm, wgn, wpe, direct, kgroups = list(info)
             assert bm % (16 * wgm) == 0 and bn % (16 * wgn) == 0 and bk % 4 == 0 and wpe >= 1
-            assert direct in (0, 1)
+            assert direct in (0, 1) and kgroups in (1, 2)
         # the three defaults are the square tiles of the padding granularities
         sizes = []
         for i in range(3):

@@ -106,7 +106,9 @@ __device__ inline void tile_coords(int np, int BM, int BN, int nprob, int& p, in
 // B_{k-1}), and the barrier waits for the wave's outstanding LDS reads, so
 // they completed before any wave passed B_{k-1}. Before B_k each wave waits
 // for its own stores or direct loads (vmcnt for the latter); the reads of
-// buffer (k+1)&1 in step k+1 start after B_k.
+// buffer (k+1)&1 in step k+1 start after B_k. With two k groups this holds
+// for each group's own pair of buffers, k counting that group's steps; the
+// groups take equally many steps and share the barriers.
 template <typename T, int BM, int BN, int BK, int WGM, int WGN, int WPE, int DL, int KS>
 __global__ __launch_bounds__(WGM * WGN * KS * 64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void gemm_kernel(const GemmLaunch g) {

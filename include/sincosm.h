@@ -283,12 +283,13 @@ sincosm_status sincosm_timing_read(int kind, double* total_ms, int64_t* count);
  * (later entries win; idx = -1 removes the overlapping entries); a
  * configuration whose tile does not divide the padded order is ignored for it.
  * With SINCOSM_TUNE_MULTI OR-ed into `arith`, sincosm_tune_set addresses the
- * table used by launches that carry more than one product's worth of k-work
- * (two problems or several k-segments: the double-angle steps and the reverse
- * pass); those launches use the plain table where their own has no entry.
- * Host-side state shared by all devices, thread-safe; results do not depend
- * on it beyond rounding order. */
-enum { SINCOSM_TUNE_MULTI = 16 };
+ * table used by launches of several problems with equal k-work (the
+ * double-angle steps); with SINCOSM_TUNE_UNEVEN, the table of the remaining
+ * launches: problems of unequal k-work or one problem with several k-segments
+ * (the reverse pass). Both flags together are an error. Such launches use the
+ * plain table where their own has no entry. Host-side state shared by all
+ * devices, thread-safe; results do not depend on it beyond rounding order. */
+enum { SINCOSM_TUNE_MULTI = 16, SINCOSM_TUNE_UNEVEN = 32 };
 int sincosm_tune_num_configs(int arith);
 sincosm_status sincosm_tune_config_info(int arith, int idx, int32_t* info);
 sincosm_status sincosm_tune_set(int arith, int64_t np_lo, int64_t np_hi, int idx);

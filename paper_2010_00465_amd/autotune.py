@@ -5,10 +5,13 @@ For each arithmetic and each probe order n it times every configuration the
 library offers whose tile divides the padded order (C-ABI
 ``sincosm_tune_num_configs`` / ``sincosm_tune_config_info``), by forcing it
 with ``sincosm_tune_set`` and timing ``sincosm_matmul`` with HIP events. A
-second pass tunes the launches that carry two products (the double-angle
-steps; also used by the reverse pass): it forces each configuration for that
-class only (``SINCOSM_TUNE_MULTI``) and times the double-angle launches of a
-``sincosm_eval`` call with the library's launch timing. The fastest
+second pass tunes the launches of several equal problems (the double-angle
+steps): it forces each configuration for that class only
+(``SINCOSM_TUNE_MULTI``) and times the double-angle launches of a
+``sincosm_eval`` call with the library's launch timing. A third pass (float64)
+tunes the launches of unequal problems or several k-segments, which only the
+reverse pass makes (``SINCOSM_TUNE_UNEVEN``): it times whole
+``sincosm_backward`` calls with each configuration forced for that class. The fastest
 configuration per probe and class is written to a JSON cache with the range of
 padded orders it covers (midpoints between probes). ``apply_cache`` installs a
 cache in the library; the package calls it at import for the cache shipped
@@ -31,7 +34,10 @@ from ._lib import lib
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(HERE, "tune_gfx950.json")
 ARITH = {"f64": 0, "f32": 1}
-MULTI = 16          # SINCOSM_TUNE_MULTI: the table of launches with two products' worth of work
+MULTI = 16          # SINCOSM_TUNE_MULTI: the table of launches of several equal problems
+UNEVEN = 32         # SINCOSM_TUNE_UNEVEN: launches of unequal problems or several k-segments
+CLASS_FLAG = {"": 0, "multi": MULTI, "uneven": UNEVEN}
+UNEVEN_PROBES = (256, 512, 1024, 2048, 4096)
 PROBES = (256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096, 6144, 8192)
 
 
@@ -60,11 +66,11 @@ def apply_cache(path: str | None = None) -> int:
     count = 0
     for key, entries in data.get("entries", {}).items():
         arith, _, cls = key.partition("_")
-        if arith not in ARITH or cls not in ("", "multi"):
+        if arith not in ARITH or cls not in CLASS_FLAG:
             continue
         if data.get("configs", {}).get(arith) != configs(arith):
             continue   # tuned against another configuration table: its indices mean other kernels
-        code = ARITH[arith] | (MULTI if cls == "multi" else 0)
+        code = ARITH[arith] | CLASS_FLAG[cls]
         for e in entries:
             if lib.sincosm_tune_set(code, int(e["np_lo"]), int(e["np_hi"]), int(e["idx"])) == 0:
                 count += 1
@@ -113,6 +119,31 @@ def time_config_multi(torch, sc, arith: str, n: int, idx: int, reps: int) -> flo
     lib.sincosm_timing_enable(0)
     lib.sincosm_tune_set(ARITH[arith] | MULTI, np_, np_, -1)
     return ms.value / max(cnt.value, 1)
+
+
+def time_config_uneven(torch, sc, n: int, idx: int, reps: int) -> float:
+    """Average duration (ms) of a whole float64 sincosm_backward call at order n (Gaussian,
+    ||A||_1 = 128: plan level 7, s = 7) with configuration idx forced for the uneven class."""
+    np_ = padded(n)
+    g = torch.Generator(device="cuda").manual_seed(n)
+    A = torch.randn(n, n, dtype=torch.float64, device="cuda", generator=g)
+    A *= 128.0 / float(A.abs().sum(0).max())
+    Gc = torch.randn(n, n, dtype=torch.float64, device="cuda", generator=g)
+    Gs = torch.randn(n, n, dtype=torch.float64, device="cuda", generator=g)
+    gA = torch.empty_like(A)
+    lib.sincosm_tune_set(ARITH["f64"] | UNEVEN, np_, np_, idx)
+    s = sc.plan_device(A).s
+    ws = torch.empty(lib.sincosm_backward_workspace_size(n, 0, 0, s), dtype=torch.uint8, device="cuda")
+    sc.sincosm_backward(A, Gc, Gs, gA, s=s, ws=ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        sc.sincosm_backward(A, Gc, Gs, gA, s=s, ws=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    lib.sincosm_tune_set(ARITH["f64"] | UNEVEN, np_, np_, -1)
+    return e0.elapsed_time(e1) / reps
 
 
 def _ranges(nps, k):
@@ -170,6 +201,28 @@ def tune(ariths=("f64", "f32"), probes=PROBES, reps=5, log=print):
                 f"({flops / (best[1] * 1e-3) / 1e12:.1f} TFLOP/s)")
         result["entries"][arith + "_multi"] = entries_m
         result["timings"][arith + "_multi"] = timings_m
+        if arith != "f64":
+            continue
+        # launches of the reverse pass, with both tables above installed
+        for e in entries_m:
+            lib.sincosm_tune_set(ARITH[arith] | MULTI, int(e["np_lo"]), int(e["np_hi"]), int(e["idx"]))
+        nps_u = sorted({padded(n) for n in UNEVEN_PROBES})
+        entries_u, timings_u = [], {}
+        for k, np_ in enumerate(nps_u):
+            best = None
+            timings_u[str(np_)] = {}
+            for c in configs(arith):
+                if np_ % c["bm"] or np_ % c["bn"]:
+                    continue
+                ms = time_config_uneven(torch, sc, np_, c["idx"], max(1, reps // 2))
+                timings_u[str(np_)][str(c["idx"])] = ms
+                if best is None or ms < best[1]:
+                    best = (c["idx"], ms)
+            lo, hi = _ranges(nps_u, k)
+            entries_u.append({"np_lo": lo, "np_hi": hi, "idx": best[0], "probe_np": np_, "ms": best[1]})
+            log(f"{arith} reverse-pass launches np={np_}: best config {best[0]}, whole backward {best[1]:.3f} ms")
+        result["entries"][arith + "_uneven"] = entries_u
+        result["timings"][arith + "_uneven"] = timings_u
     return result
 
 

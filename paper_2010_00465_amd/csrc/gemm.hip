@@ -546,19 +546,31 @@ static const KernelCfg* cfg_table(Arith ar, int& count) {
 }
 
 // Tuning table: for (arith, launch class, padded order in [lo, hi]) use
-// configuration idx. Class 0: launches with one product's worth of k-work per
-// output tile set (one problem, one segment); class 1: heavier launches (two
-// problems or several k-segments: the double-angle steps, the reverse pass),
-// which fall back to class 0 entries when none of their own matches.
+// configuration idx. Launch classes:
+//   0  one problem with at most one k-segment (a plain product);
+//   1  several problems with equal k-work (the double-angle steps);
+//   2  the rest: problems of unequal k-work, or one problem with several
+//      k-segments (the reverse pass). A tile that is a good choice for two
+//      equal problems can leave CUs idle here, so this class is tuned on its
+//      own and falls back to the single-product entries.
+// Classes 1 and 2 use class 0 entries when none of their own matches.
 struct TuneEntry { int ar; int cls; int64_t lo, hi; int idx; };
 static std::mutex tune_mu;
 static std::vector<TuneEntry> tune_table;
 
+static int launch_class(const GemmLaunch& g) {
+  if (g.nprob <= 1) return g.prob[0].nseg <= 1 ? 0 : 2;
+  for (int p = 1; p < g.nprob; ++p)
+    if (g.prob[p].nseg != g.prob[0].nseg) return 2;
+  return 1;
+}
+
 static int tuned_cfg(Arith ar, int cls, int64_t np) {
   std::lock_guard<std::mutex> g(tune_mu);
-  for (int c = cls; c >= 0; --c)
+  const int order[2] = {cls, 0};
+  for (int k = 0; k < (cls == 0 ? 1 : 2); ++k)
     for (auto it = tune_table.rbegin(); it != tune_table.rend(); ++it)
-      if (it->ar == (int)ar && it->cls == c && np >= it->lo && np <= it->hi) return it->idx;
+      if (it->ar == (int)ar && it->cls == order[k] && np >= it->lo && np <= it->hi) return it->idx;
   return -1;
 }
 
@@ -568,9 +580,7 @@ sincosm_status launch_gemm(Arith ar, int tile, const GemmLaunch& g, hipStream_t 
   int count = 0;
   const KernelCfg* t = cfg_table(ar, count);
   if (!t) return SINCOSM_E_UNSUPPORTED;
-  int units = 0;
-  for (int p = 0; p < g.nprob; ++p) units += g.prob[p].nseg;
-  int idx = tuned_cfg(ar, units >= 2 ? 1 : 0, g.np);
+  int idx = tuned_cfg(ar, launch_class(g), g.np);
   if (idx < 0 || idx >= count || g.np % t[idx].bm != 0 || g.np % t[idx].bn != 0) idx = tile;
   return t[idx].fn(g, stream);
 }
@@ -581,13 +591,14 @@ extern "C" {
 
 int sincosm_tune_num_configs(int arith) {
   int count = 0;
-  sc::cfg_table((sc::Arith)(arith & ~(int)SINCOSM_TUNE_MULTI), count);
+  sc::cfg_table((sc::Arith)(arith & ~(int)(SINCOSM_TUNE_MULTI | SINCOSM_TUNE_UNEVEN)), count);
   return count;
 }
 
 sincosm_status sincosm_tune_config_info(int arith, int idx, int32_t* info) {
   int count = 0;
-  const sc::KernelCfg* t = sc::cfg_table((sc::Arith)(arith & ~(int)SINCOSM_TUNE_MULTI), count);
+  const sc::KernelCfg* t =
+      sc::cfg_table((sc::Arith)(arith & ~(int)(SINCOSM_TUNE_MULTI | SINCOSM_TUNE_UNEVEN)), count);
   if (!t || !info || idx < 0 || idx >= count) return SINCOSM_E_ARG;
   info[0] = t[idx].bm; info[1] = t[idx].bn; info[2] = t[idx].bk;
   info[3] = t[idx].wgm; info[4] = t[idx].wgn; info[5] = t[idx].wpe; info[6] = t[idx].dl;
@@ -596,8 +607,9 @@ sincosm_status sincosm_tune_config_info(int arith, int idx, int32_t* info) {
 }
 
 sincosm_status sincosm_tune_set(int arith, int64_t np_lo, int64_t np_hi, int idx) {
-  const int cls = (arith & SINCOSM_TUNE_MULTI) ? 1 : 0;
-  const int ar = arith & ~(int)SINCOSM_TUNE_MULTI;
+  if ((arith & SINCOSM_TUNE_MULTI) && (arith & SINCOSM_TUNE_UNEVEN)) return SINCOSM_E_ARG;
+  const int cls = (arith & SINCOSM_TUNE_UNEVEN) ? 2 : (arith & SINCOSM_TUNE_MULTI) ? 1 : 0;
+  const int ar = arith & ~(int)(SINCOSM_TUNE_MULTI | SINCOSM_TUNE_UNEVEN);
   int count = 0;
   sc::cfg_table((sc::Arith)ar, count);
   if (count == 0 || np_lo > np_hi) return SINCOSM_E_ARG;

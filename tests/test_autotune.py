@@ -50,7 +50,7 @@ def test_shipped_cache_is_consistent(lib):
     data = json.load(open(path))
     for key, entries in data["entries"].items():
         arith, _, cls = key.partition("_")
-        assert cls in ("", "multi"), key
+        assert cls in ("", "multi", "uneven"), key
         n = lib.sincosm_tune_num_configs(autotune.ARITH[arith])
         prev_hi = 0
         for e in entries:
@@ -93,6 +93,20 @@ def test_multi_class_flag(lib):
     assert lib.sincosm_tune_set(autotune.MULTI, 1 << 40, 1 << 41, 1) == 0
     assert lib.sincosm_tune_set(autotune.MULTI, 1 << 40, 1 << 41, -1) == 0
     assert lib.sincosm_tune_set(autotune.MULTI | 9, 1, 10, 0) == -1
+
+
+def test_uneven_class_flag(lib):
+    """SINCOSM_TUNE_UNEVEN addresses a third table (float64 reverse-pass launches); both
+    class flags together are rejected."""
+    from paper_2010_00465_amd import autotune
+    assert lib.sincosm_tune_num_configs(autotune.UNEVEN) == lib.sincosm_tune_num_configs(0)
+    info = (ctypes.c_int32 * 8)()
+    assert lib.sincosm_tune_config_info(autotune.UNEVEN, 0, info) == 0
+    assert lib.sincosm_tune_set(autotune.UNEVEN, 1 << 40, 1 << 41, 1) == 0
+    assert lib.sincosm_tune_set(autotune.UNEVEN, 1 << 40, 1 << 41, -1) == 0
+    assert lib.sincosm_tune_set(autotune.UNEVEN | autotune.MULTI, 1 << 40, 1 << 41, 1) == -1
+    data = json.load(open(autotune.DEFAULT_CACHE))
+    assert "f64_uneven" in data["entries"] and "f32_uneven" not in data["entries"]
 
 
 def test_padding_rule_matches_library(lib):

@@ -581,7 +581,9 @@ sincosm_status launch_gemm(Arith ar, int tile, const GemmLaunch& g, hipStream_t 
   const KernelCfg* t = cfg_table(ar, count);
   if (!t) return SINCOSM_E_UNSUPPORTED;
   int idx = tuned_cfg(ar, launch_class(g), g.np);
-  if (idx < 0 || idx >= count || g.np % t[idx].bm != 0 || g.np % t[idx].bn != 0) idx = tile;
+  if (idx < 0 || idx >= count || g.np % t[idx].bm != 0 || g.np % t[idx].bn != 0 ||
+      (g.np / t[idx].bk) % t[idx].ks != 0)
+    idx = tile;
   return t[idx].fn(g, stream);
 }
 

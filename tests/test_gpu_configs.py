@@ -62,8 +62,8 @@ def test_every_config_matmul(env, arith, dt):
 
 def force(lib, arith, n, idx):
     """Make every launch of this arithmetic at padded order n use configuration idx
-    (both launch classes); idx = -1 removes the forcing."""
-    for code in (arith, arith | 16):
+    (all three launch classes); idx = -1 removes the forcing."""
+    for code in (arith, arith | 16, arith | 32):
         assert lib.sincosm_tune_set(code, n, n, idx) == 0
 
 

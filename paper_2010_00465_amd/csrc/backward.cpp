@@ -12,8 +12,12 @@
 // launch by giving it several k-segments.
 //
 // Double-angle step C' = I - 2 S S, S' = 2 S C (Section 1), adjoint:
-//   Sbar = -2 C'bar S^T - 2 S^T C'bar + 2 S'bar C^T     (one launch, 3 segments)
-//   Cbar =  2 S^T S'bar                                   (second problem)
+//   Sbar = -2 C'bar S^T - 2 S^T C'bar + 2 S'bar C^T
+//   Cbar =  2 S^T S'bar
+// as one launch of three problems with 2, 1 and 1 k-segments (the first two
+// terms of Sbar; Cbar; the last term of Sbar into a scratch matrix), so that
+// no tile carries more than twice the work of another, then an epilogue-only
+// launch adds the scratch matrix into Sbar.
 // The scaled argument X = 2^-s A enters the first and last scheme products:
 //   Abar = 2^-s Sbar0 V^T + 4^-s (Ybar A^T + A^T Ybar)    (one launch, 3 segments)
 // Forward product count Pi + 2s; reverse 2 Pi + 4s, plus the recomputed
@@ -263,19 +267,26 @@ sincosm_status rev7(Rev& v) {
 }
 
 // Adjoint of one double-angle step from (Cbar', Sbar') to (Cbar, Sbar), with
-// (SB, CB) the step's inputs computed on B = A^T.
+// (SB, CB) the step's inputs computed on B = A^T; tmp is scratch.
 sincosm_status rev_double_angle(Run& r, const Modes& m, const void* SB, const void* CB, const void* Cbn,
-                                const void* Sbn, void* Cb, void* Sb) {
+                                const void* Sbn, void* Cb, void* Sb, void* tmp) {
   const int64_t np = m.np;
   Problem p0 = make_problem((int)r.n);
   add_seg(p0, Cbn, SB, np, -2.0, 1.0);
   add_seg(p0, SB, Cbn, np, -2.0, 1.0);
-  add_seg(p0, Sbn, CB, np, 2.0, 1.0);
   add_out(p0, internal(Sb, m, true), 1.0, 0.0, {});
   Problem p1 = make_problem((int)r.n);
   add_seg(p1, SB, Sbn, np, 2.0, 1.0);
   add_out(p1, internal(Cb, m, true), 1.0, 0.0, {});
-  return gemm(r, Arith::F64, two(p0, p1, (int)np), SINCOSM_TIMING_BACKWARD);
+  Problem p2 = make_problem((int)r.n);
+  add_seg(p2, Sbn, CB, np, 2.0, 1.0);
+  add_out(p2, internal(tmp, m, true), 1.0, 0.0, {});
+  SC_TRY(gemm(r, Arith::F64, three(p0, p1, p2, (int)np), SINCOSM_TIMING_BACKWARD));
+  Problem sum = make_problem((int)r.n);   // Sbar += tmp, element by element
+  add_in(sum, Sb, np);
+  add_in(sum, tmp, np);
+  add_out(sum, internal(Sb, m, true), 0.0, 0.0, {1.0, 1.0});
+  return gemm(r, Arith::F64, one(sum, (int)np), SINCOSM_TIMING_BACKWARD);
 }
 
 }  // namespace
@@ -368,7 +379,7 @@ sincosm_status sincosm_backward(int64_t n, int dtype, const void* A, int64_t lda
   for (int i = s - 1; i >= 0; --i) {
     const int nxt = cur ^ 1;
     SC_TRY(rev_double_angle(r, m, chainS(i), chainC(i), cot[2 * cur], cot[2 * cur + 1], cot[2 * nxt],
-                            cot[2 * nxt + 1]));
+                            cot[2 * nxt + 1], Rb[0]));   // the scheme adjoint's buffers are free here
     cur = nxt;
   }
 

@@ -121,7 +121,7 @@ __host__ __device__ inline void plan_rule_wave(double normB, int acc, sincosm_pl
 constexpr int MAX_SEG = 3;
 constexpr int MAX_IN = 6;
 constexpr int MAX_OUT = 6;
-constexpr int MAX_PROB = 2;
+constexpr int MAX_PROB = 3;
 
 struct Seg {
   const void* L;

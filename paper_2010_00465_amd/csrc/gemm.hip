@@ -22,8 +22,8 @@
 //  * All operands are internal buffers padded with zeros to a multiple of the
 //    tile, so the main loop has no bounds checks; only outputs carry a limit.
 //  * Block index -> tile: consecutive launch indices go to different XCDs, so
-//    the index is first remapped to give each XCD a contiguous range of tiles,
-//    then walked in groups of 8 tile rows to keep operand panels in L2.
+//    the index is first remapped to give each XCD a contiguous range of each
+//    problem's tiles, then walked in groups of 8 tile rows.
 #include "common.hpp"
 #include "epilogue.hpp"
 
@@ -63,14 +63,23 @@ struct Mma<float> {
   __device__ static inline int row_in_block(int lg, int r) { return 4 * lg + r; }
 };
 
-// Map a launch index to (problem, tile row, tile column).
+// Map a launch index to (problem, tile row, tile column). Consecutive launch
+// indices go to different XCDs (index mod 8). When a problem's tile count is a
+// multiple of 8, XCD x owns the x-th eighth of the tiles of every problem, and
+// its successive workgroups alternate between the problems, so problems of
+// unequal k-work are spread evenly over the XCDs.
 __device__ inline void tile_coords(int np, int BM, int BN, int nprob, int& p, int& tm, int& tn) {
   const int tmc = np / BM, tnc = np / BN, tiles = tmc * tnc;
-  const int total = tiles * nprob;
-  int b = blockIdx.x;
-  if ((total & 7) == 0) b = (b & 7) * (total >> 3) + (b >> 3);
-  p = b / tiles;
-  const int t = b - p * tiles;
+  const int b = blockIdx.x;
+  int t;
+  if ((tiles & 7) == 0) {
+    const int j = b >> 3;
+    p = j % nprob;
+    t = (b & 7) * (tiles >> 3) + j / nprob;
+  } else {
+    p = b / tiles;
+    t = b - p * tiles;
+  }
   constexpr int GROUP = 8;
   const int group = t / (GROUP * tnc);
   const int first = group * GROUP;

@@ -91,6 +91,17 @@ GemmLaunch two(const Problem& p0, const Problem& p1, int np) {
   return g;
 }
 
+GemmLaunch three(const Problem& p0, const Problem& p1, const Problem& p2, int np) {
+  GemmLaunch g;
+  memset(&g, 0, sizeof(g));
+  g.np = np;
+  g.nprob = 3;
+  g.prob[0] = p0;
+  g.prob[1] = p1;
+  g.prob[2] = p2;
+  return g;
+}
+
 GemmLaunch one(const Problem& p, int np) {
   GemmLaunch g;
   memset(&g, 0, sizeof(g));

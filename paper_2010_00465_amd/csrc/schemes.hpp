@@ -52,6 +52,7 @@ void add_in(Problem& p, const void* m, int64_t ld);
 void add_out(Problem& p, const Target& t, double e, double d, std::initializer_list<double> c);
 GemmLaunch one(const Problem& p, int np);
 GemmLaunch two(const Problem& p0, const Problem& p1, int np);
+GemmLaunch three(const Problem& p0, const Problem& p1, const Problem& p2, int np);
 bool modes_for(int64_t n, int dtype, int prod, Modes& m);
 Layout layout_for(const Modes& m);
 sincosm_status read_plan(const sincosm_plan* dev, sincosm_plan* host, hipStream_t stream, int count = 1);

@@ -48,7 +48,8 @@ typedef enum {
   SINCOSM_E_UNSUPPORTED = -2, /* combination not provided (see each call) */
   SINCOSM_E_WORKSPACE = -3,   /* workspace missing or smaller than the query's size */
   SINCOSM_E_NONFINITE = -4,   /* A holds Inf/NaN (or its 1-norm overflows): outputs set to NaN */
-  SINCOSM_E_HIP = -5          /* a HIP runtime call failed */
+  SINCOSM_E_HIP = -5,         /* a HIP runtime call failed */
+  SINCOSM_E_PLAN = -6         /* a caller's plan does not cover ||A||_1: outputs set to NaN */
 } sincosm_status;
 
 /* Storage type of A, C, S and of the gradients. */
@@ -140,6 +141,30 @@ sincosm_status sincosm_eval(int64_t n, int dtype, const void* A, int64_t lda,
                             void* C, int64_t ldc, void* S, int64_t lds,
                             int acc, int prod, void* ws, size_t ws_bytes,
                             sincosm_plan* plan_host, void* stream);
+
+/* sincosm_eval with the plan given by the caller (host pointer plan_in: level
+ * and s, e.g. sincosm_plan_host of a known bound on ||A||_1, or the plan of an
+ * earlier call). Nothing is read back, so the call only enqueues kernels on
+ * `stream` (no synchronisation, no allocation) and can be captured in a HIP
+ * graph; the launches are those sincosm_eval makes for the same plan, so the
+ * results are bitwise the same. The 1-norm is still computed on the device and
+ * the plan checked against it: it covers A when ||A||_1 2^-s <= theta of its
+ * level (Tables 1-2 of the accuracy `acc`). When it does not, or A holds Inf or
+ * NaN, C and S are filled with NaN after the products.
+ *  plan_in (host, read): level in {3, 4, 6, 7} (5 with SINCOSM_PLAN_EXTENDED
+ *  in acc), 0 <= s <= 1100; other fields are ignored.
+ *  plan_dev (device, nullable): receives {level, s, products, status, norm1}
+ *  of this call once the stream reaches it; status SINCOSM_OK,
+ *  SINCOSM_E_PLAN or SINCOSM_E_NONFINITE.
+ *  acc: SINCOSM_ACC_DOUBLE or SINGLE, optionally | SINCOSM_PLAN_EXTENDED (the
+ *  refined-norm flag is not accepted). Other arguments as sincosm_eval.
+ *  Returns SINCOSM_E_ARG for a bad plan_in, otherwise the argument and
+ *  workspace errors of sincosm_eval; the status of the check is on the device. */
+sincosm_status sincosm_eval_planned(int64_t n, int dtype, const void* A, int64_t lda,
+                                    void* C, int64_t ldc, void* S, int64_t lds,
+                                    int acc, int prod, const sincosm_plan* plan_in,
+                                    void* ws, size_t ws_bytes, sincosm_plan* plan_dev,
+                                    void* stream);
 
 /* Plan of the wave-equation schemes for a given ||B||_1, B = t^2 A (host, pure).
  * level in {2,3,4,5} (= products of the Section 2.2 scheme), s = number of

@@ -27,7 +27,7 @@ TUNED_ENTRIES = _autotune.apply_cache()
 __all__ = ["sincosm", "sincosm_eval", "sincosm_eval_batched", "sincosm_backward", "sincosm_matmul",
            "plan_host", "plan_device", "workspace_size", "Plan", "SincosmError", "sincosm_batched",
            "wave_plan_host", "sincosm_wave_eval", "wave", "sincosm_wave_block_eval", "wave_block",
-           "sincosm_expi_eval", "expi"]
+           "sincosm_expi_eval", "expi", "sincosm_eval_planned", "plan_from_device", "PLAN_BYTES"]
 
 
 def _dtype_code(t: torch.Tensor) -> int:
@@ -106,6 +106,44 @@ def sincosm_eval(A: torch.Tensor, C: torch.Tensor, S: torch.Tensor, accuracy: st
         return plan
     check(st, "sincosm_eval")
     return plan
+
+
+PLAN_BYTES = ctypes.sizeof(Plan)
+
+
+def sincosm_eval_planned(A: torch.Tensor, C: torch.Tensor, S: torch.Tensor, plan, accuracy: str = "double",
+                         products: str = "native", ws: torch.Tensor | None = None,
+                         plan_dev: torch.Tensor | None = None, extended: bool = False) -> None:
+    """C-ABI sincosm_eval_planned: cos and sin with the caller's plan (a Plan or (level, s)).
+    Only enqueues work on the current stream (graph-capturable when ``ws`` and ``plan_dev``
+    are given); C and S become NaN if the plan does not cover ||A||_1 or A is not finite.
+    ``plan_dev``: optional device uint8 tensor of at least PLAN_BYTES bytes that receives
+    the call's plan record (read it with ``plan_from_device``)."""
+    _require_cuda(A, C, S)
+    n = A.shape[0]
+    dt = _dtype_code(A)
+    if ws is None:
+        ws = _workspace(workspace_size(n, A.dtype, accuracy, products), A.device)
+    p = Plan()
+    if isinstance(plan, Plan):
+        p.level, p.s = plan.level, plan.s
+    else:
+        p.level, p.s = int(plan[0]), int(plan[1])
+    pd = None
+    if plan_dev is not None:
+        _require_cuda(plan_dev)
+        if plan_dev.numel() * plan_dev.element_size() < PLAN_BYTES:
+            raise ValueError("plan_dev holds fewer than PLAN_BYTES bytes")
+        pd = plan_dev.data_ptr()
+    check(lib.sincosm_eval_planned(n, dt, A.data_ptr(), _ld(A), C.data_ptr(), _ld(C), S.data_ptr(), _ld(S),
+                                   _acc(accuracy, extended), PROD[products], ctypes.byref(p), ws.data_ptr(),
+                                   ws.numel(), pd, _stream(A)), "sincosm_eval_planned")
+
+
+def plan_from_device(plan_dev: torch.Tensor) -> Plan:
+    """Read a plan record that sincosm_eval_planned wrote (synchronises with its stream)."""
+    raw = plan_dev.view(torch.uint8).flatten()[:PLAN_BYTES].cpu().numpy().tobytes()
+    return Plan.from_buffer_copy(raw)
 
 
 def wave_plan_host(normB: float, accuracy: str = "double") -> Plan:

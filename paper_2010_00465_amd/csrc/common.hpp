@@ -199,6 +199,15 @@ sincosm_status launch_norm_sq_plan(int64_t n, int64_t np, const void* Y, bool y_
 sincosm_status launch_transpose_pad(int64_t n, int64_t np, const void* src, int64_t lds, bool src_f64,
                                     void* dst, bool dst_f64, hipStream_t stream);
 sincosm_status launch_fill_nan(int64_t n, void* X, int64_t ld, bool f64, hipStream_t stream);
+// Check a caller's plan (level, s) against the 1-norm in ns (after
+// launch_norm_copy_plan): writes the call's plan record to ns.plan and, when
+// given, to plan_dev; status SINCOSM_E_PLAN when ||A||_1 2^-s > theta_level.
+sincosm_status launch_check_plan(int acc, int level, int s, const NormScratch& ns, sincosm_plan* plan_dev,
+                                 hipStream_t stream);
+// Fill the n x n matrix X with NaN if the plan record at `plan` has a status
+// other than SINCOSM_OK (decided on the device).
+sincosm_status launch_fill_nan_if(const sincosm_plan* plan, int64_t n, void* X, int64_t ld, bool f64,
+                                  hipStream_t stream);
 sincosm_status launch_fill_nan_rect(int64_t rows, int64_t cols, void* X, int64_t ld, bool f64,
                                     hipStream_t stream);
 // dst (n x n complex, leading dimension ldd in complex elements, pairs of the

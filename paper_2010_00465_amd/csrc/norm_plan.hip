@@ -230,6 +230,52 @@ sincosm_status launch_fill_nan(int64_t n, void* X, int64_t ld, bool f64, hipStre
   return launch_fill_nan_rect(n, n, X, ld, f64, stream);
 }
 
+// A caller's plan covers A when ||A||_1 2^-s <= theta of its level (the
+// bounds of Tables 1-2 the plan rule uses).
+__global__ void check_plan_kernel(const unsigned long long* maxbits, int acc, int level, int s,
+                                  sincosm_plan* plan, sincosm_plan* plan_dev) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double nrm = __longlong_as_double((long long)*maxbits);
+  sincosm_plan p;
+  p.level = level;
+  p.s = s;
+  p.products = level + 2 * s;
+  p.norm1 = nrm;
+  const int base = acc & 1;
+  const double th = level == 5 ? plan_theta_level5(base)
+                               : plan_theta(base, level == 3 ? 0 : level == 4 ? 1 : level == 6 ? 2 : 3);
+  if (!(nrm >= 0.0 && nrm <= 1.7976931348623157e308)) p.status = SINCOSM_E_NONFINITE;
+  else p.status = ldexp(nrm, -s) <= th ? SINCOSM_OK : SINCOSM_E_PLAN;
+  *plan = p;
+  if (plan_dev) *plan_dev = p;
+}
+
+sincosm_status launch_check_plan(int acc, int level, int s, const NormScratch& ns, sincosm_plan* plan_dev,
+                                 hipStream_t stream) {
+  check_plan_kernel<<<1, 64, 0, stream>>>(ns.maxbits, acc, level, s, ns.plan, plan_dev);
+  SC_HIP(hipGetLastError());
+  return SINCOSM_OK;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void fill_nan_if_kernel(const sincosm_plan* plan, int64_t cols, T* X,
+                                                          int64_t ld) {
+  if (plan->status == SINCOSM_OK) return;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = blockIdx.y;
+  if (j < cols) X[i * ld + j] = (T)__longlong_as_double(0x7ff8000000000000ll);
+}
+
+sincosm_status launch_fill_nan_if(const sincosm_plan* plan, int64_t n, void* X, int64_t ld, bool f64,
+                                  hipStream_t stream) {
+  if (n <= 0) return SINCOSM_OK;
+  dim3 g((unsigned)((n + 255) / 256), (unsigned)n);
+  if (f64) fill_nan_if_kernel<double><<<g, 256, 0, stream>>>(plan, n, (double*)X, ld);
+  else fill_nan_if_kernel<float><<<g, 256, 0, stream>>>(plan, n, (float*)X, ld);
+  SC_HIP(hipGetLastError());
+  return SINCOSM_OK;
+}
+
 // dst[i][j] = (re[i][j], sgn * im[i][j]) for i, j < n: interleaved complex
 // (real, imaginary) pairs from two zero-padded planes of the same type.
 template <typename T>

@@ -9,6 +9,54 @@
 
 using namespace sc;
 
+namespace {
+
+// The launches that follow the plan: the scheme on 2^-s A (its products read
+// the padded copy in the workspace) and the s double-angle steps, ping-pong
+// between (Q0, Q1) and (Q2, Q3); the last step (or the scheme when s = 0)
+// writes the caller's C and S.
+sincosm_status enqueue_method(Run& r, const Modes& m, const Layout& L, char* base, const sincosm_plan& plan,
+                              const Target& userC, const Target& userS) {
+  void* Q[4];
+  for (int i = 0; i < 4; ++i) Q[i] = base + L.q_off[i];
+  const int s = plan.s;
+  if (s == 0) {
+    r.Cout = userC;
+    r.Sout = userS;
+  } else {
+    r.Cout = internal(Q[1], m, m.sq_f64);
+    r.Sout = internal(Q[0], m, m.sq_f64);
+  }
+  const double sx = ldexp(1.0, -s);
+  SC_TRY(run_scheme(r, plan.level, sx));
+  for (int i = 0; i < s; ++i) {
+    void* Sc = Q[(i & 1) ? 2 : 0];
+    void* Cc = Q[(i & 1) ? 3 : 1];
+    const bool last = (i == s - 1);
+    const Target Sn = last ? userS : internal(Q[(i & 1) ? 0 : 2], m, m.sq_f64);
+    const Target Cn = last ? userC : internal(Q[(i & 1) ? 1 : 3], m, m.sq_f64);
+    SC_TRY(double_angle(r, Sc, Cc, Cn, Sn));
+  }
+  return SINCOSM_OK;
+}
+
+// Argument and workspace checks shared by sincosm_eval and sincosm_eval_planned
+// (n > 0, Modes already derived).
+sincosm_status check_eval_args(int64_t n, int dtype, const void* A, int64_t lda, const void* C, int64_t ldc,
+                               const void* S, int64_t lds, const Modes& m, void* ws, size_t ws_bytes) {
+  if (!A || !C || !S) return SINCOSM_E_ARG;
+  if (lda < n || ldc < n || lds < n) return SINCOSM_E_ARG;
+  const size_t es = dtype == SINCOSM_F64 ? 8 : 4;
+  if (overlaps(A, lda, C, ldc, n, es) || overlaps(A, lda, S, lds, n, es) || overlaps(C, ldc, S, lds, n, es))
+    return SINCOSM_E_ARG;
+  if (m.poly == Arith::BF16X3 && !bf16x3_available()) return SINCOSM_E_UNSUPPORTED;
+  const Layout L = layout_for(m);
+  if (!ws || ws_bytes < L.total || ((uintptr_t)ws & 255u)) return SINCOSM_E_WORKSPACE;
+  return SINCOSM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* sincosm_strerror(int status) {
@@ -19,6 +67,7 @@ const char* sincosm_strerror(int status) {
     case SINCOSM_E_WORKSPACE: return "workspace missing or too small";
     case SINCOSM_E_NONFINITE: return "input holds Inf or NaN";
     case SINCOSM_E_HIP: return "HIP runtime error";
+    case SINCOSM_E_PLAN: return "the given plan does not cover the matrix 1-norm";
     default: return "unknown status";
   }
 }
@@ -69,14 +118,8 @@ sincosm_status sincosm_eval(int64_t n, int dtype, const void* A, int64_t lda, vo
     if (plan_host) { plan_rule(0.0, acc, plan_host); plan_host->level = 0; plan_host->products = 0; }
     return SINCOSM_OK;
   }
-  if (!A || !C || !S) return SINCOSM_E_ARG;
-  if (lda < n || ldc < n || lds < n) return SINCOSM_E_ARG;
-  const size_t es = dtype == SINCOSM_F64 ? 8 : 4;
-  if (overlaps(A, lda, C, ldc, n, es) || overlaps(A, lda, S, lds, n, es) || overlaps(C, ldc, S, lds, n, es))
-    return SINCOSM_E_ARG;
-  if (m.poly == Arith::BF16X3 && !bf16x3_available()) return SINCOSM_E_UNSUPPORTED;
+  SC_TRY(check_eval_args(n, dtype, A, lda, C, ldc, S, lds, m, ws, ws_bytes));
   const Layout L = layout_for(m);
-  if (!ws || ws_bytes < L.total || ((uintptr_t)ws & 255u)) return SINCOSM_E_WORKSPACE;
   hipStream_t stream = (hipStream_t)stream_;
   char* base = (char*)ws;
 
@@ -119,31 +162,49 @@ sincosm_status sincosm_eval(int64_t n, int dtype, const void* A, int64_t lda, vo
     }
     r.y_ready = true;
   }
-  void* Q[4];
-  for (int i = 0; i < 4; ++i) Q[i] = base + L.q_off[i];
   const Target userC{C, ldc, (int)n, m.user_f64};
   const Target userS{S, lds, (int)n, m.user_f64};
-  const int s = plan.s;
-  if (s == 0) {
-    r.Cout = userC;
-    r.Sout = userS;
-  } else {
-    r.Cout = internal(Q[1], m, m.sq_f64);
-    r.Sout = internal(Q[0], m, m.sq_f64);
-  }
-  const double sx = ldexp(1.0, -s);
-  SC_TRY(run_scheme(r, plan.level, sx));
-  // s double-angle steps, ping-pong between (Q0, Q1) and (Q2, Q3); the last
-  // step writes the caller's buffers.
-  for (int i = 0; i < s; ++i) {
-    void* Sc = Q[(i & 1) ? 2 : 0];
-    void* Cc = Q[(i & 1) ? 3 : 1];
-    const bool last = (i == s - 1);
-    const Target Sn = last ? userS : internal(Q[(i & 1) ? 0 : 2], m, m.sq_f64);
-    const Target Cn = last ? userC : internal(Q[(i & 1) ? 1 : 3], m, m.sq_f64);
-    SC_TRY(double_angle(r, Sc, Cc, Cn, Sn));
-  }
-  return SINCOSM_OK;
+  return enqueue_method(r, m, L, base, plan, userC, userS);
+}
+
+sincosm_status sincosm_eval_planned(int64_t n, int dtype, const void* A, int64_t lda, void* C, int64_t ldc,
+                                    void* S, int64_t lds, int acc, int prod, const sincosm_plan* plan_in,
+                                    void* ws, size_t ws_bytes, sincosm_plan* plan_dev, void* stream_) {
+  if (n < 0 || n > (1 << 20) || !plan_in) return SINCOSM_E_ARG;
+  if (!acc_valid(acc, SINCOSM_PLAN_EXTENDED)) return SINCOSM_E_ARG;
+  const int level = plan_in->level, s = plan_in->s;
+  const bool level_ok = level == 3 || level == 4 || level == 6 || level == 7 ||
+                        (level == 5 && (acc & SINCOSM_PLAN_EXTENDED));
+  if (!level_ok || s < 0 || s > 1100) return SINCOSM_E_ARG;
+  Modes m;
+  if (!modes_for(n > 0 ? n : 1, dtype, prod, m)) return SINCOSM_E_ARG;
+  if (n == 0) return SINCOSM_OK;
+  SC_TRY(check_eval_args(n, dtype, A, lda, C, ldc, S, lds, m, ws, ws_bytes));
+  const Layout L = layout_for(m);
+  hipStream_t stream = (hipStream_t)stream_;
+  char* base = (char*)ws;
+  const NormScratch ns = norm_scratch(base + L.norm_off, m.np);
+  void* Ap = base + L.ap_off;
+  Run r;
+  r.m = &m;
+  r.n = n;
+  r.Ap = Ap;
+  for (int i = 0; i < 9; ++i) r.W[i] = base + L.w_off[i];
+  r.stream = stream;
+  r.launched = 0;
+  SC_TRY(launch_norm_copy_plan(n, m.np, A, lda, m.user_f64, Ap, m.poly_f64, acc, ns, stream));
+  SC_TRY(launch_check_plan(acc, level, s, ns, plan_dev, stream));
+  sincosm_plan plan;
+  plan.level = level;
+  plan.s = s;
+  plan.products = level + 2 * s;
+  plan.status = SINCOSM_OK;
+  plan.norm1 = 0.0;
+  const Target userC{C, ldc, (int)n, m.user_f64};
+  const Target userS{S, lds, (int)n, m.user_f64};
+  SC_TRY(enqueue_method(r, m, L, base, plan, userC, userS));
+  SC_TRY(launch_fill_nan_if(ns.plan, n, C, ldc, m.user_f64, stream));
+  return launch_fill_nan_if(ns.plan, n, S, lds, m.user_f64, stream);
 }
 
 size_t sincosm_matmul_workspace_size(int64_t n, int dtype, int prod) {

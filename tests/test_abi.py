@@ -124,3 +124,30 @@ def test_host_plan_extended_matches_oracle(lib):
             assert (p.level, p.s, p.products) == P.plan(float(x), name, extended=True), (x, name)
     lib.sincosm_wave_plan_host.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.POINTER(Plan)]
     assert lib.sincosm_wave_plan_host(1.0, ext, ctypes.byref(Plan())) == -1
+
+
+def test_planned_argument_errors_without_gpu(lib):
+    """sincosm_eval_planned rejects a bad plan or arguments before any device work."""
+    f = lib.sincosm_eval_planned
+    f.restype = ctypes.c_int
+    vp, i64 = ctypes.c_void_p, ctypes.c_int64
+    f.argtypes = [i64, ctypes.c_int, vp, i64, vp, i64, vp, i64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Plan),
+                  vp, ctypes.c_size_t, vp, vp]
+    fake = 1 << 40            # never dereferenced: every call below fails validation first
+
+    def call(level, s, acc=0, n=64, plan=True, ws=fake):
+        p = Plan(level, s, 0, 0, 0.0)
+        return f(n, 0, fake, n, fake + 2 ** 20, n, fake + 2 ** 21, n, acc, 0, ctypes.byref(p) if plan else None,
+                 ws, 1 << 30, None, None)
+
+    assert call(5, 0) == -1                  # level 5 without the extended flag
+    assert call(2, 0) == -1 and call(8, 0) == -1
+    assert call(7, -1) == -1 and call(7, 1101) == -1
+    assert call(7, 3, plan=False) == -1
+    assert call(7, 3, acc=32) == -1          # the refined flag is not accepted here
+    assert call(7, 3, acc=7) == -1
+    assert call(7, 3, n=-1) == -1
+    assert call(7, 3, ws=None) == -3         # workspace missing
+    assert call(7, 3, n=0) == 0              # n = 0 is a no-op
+    lib.sincosm_strerror.restype = ctypes.c_char_p
+    assert lib.sincosm_strerror(-6) == b"the given plan does not cover the matrix 1-norm"

@@ -286,7 +286,8 @@ def bench_level5(torch, sc, W):
 def bench_sizes(torch, sc, W):
     """The anchor matrices (Gaussian, ||A||_1 = 2^e, e in {-4, 0, 4, 10}) at n = 1024 and 8192,
     float64 with the double-accuracy plans and float32 storage with the single-accuracy plans:
-    evaluations/s and algorithmic TFLOP/s over the four anchors."""
+    evaluations/s and algorithmic TFLOP/s over the four anchors; at n = 1024 also through a
+    HIP graph of sincosm_eval_planned with the same plans."""
     out = {"workload": "four Gaussian anchor matrices per order and storage type"}
     for n in (1024, 8192):
         for dt, acc in ((torch.float64, "double"), (torch.float32, "single")):
@@ -304,6 +305,21 @@ def bench_sizes(torch, sc, W):
             key = f"n{n}_{'f64' if dt == torch.float64 else 'f32'}_{acc}"
             out[key] = {"evals_per_s": len(mats) / t, "tflops_algorithmic": flops / t / 1e12,
                         "products": [p.products for p in plans]}
+            if n <= 1024:
+                # the same four evaluations with the plans given (sincosm_eval_planned), captured
+                # once in a HIP graph and replayed: no plan read-back, no host gaps between calls
+                def run_planned():
+                    for m, (c, s_), p in zip(mats, outs, plans):
+                        sc.sincosm_eval_planned(m, c, s_, p, acc, ws=ws)
+
+                run_planned()
+                torch.cuda.synchronize()
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g):
+                    run_planned()
+                tg = _elapsed(torch, g.replay, 5)
+                out[key]["graph_replay"] = {"evals_per_s": len(mats) / tg, "tflops_algorithmic": flops / tg / 1e12}
+                del g
             del mats, outs, ws
     return out
 

@@ -277,9 +277,6 @@ def sincosm_backward(A: torch.Tensor, Gc: torch.Tensor | None, Gs: torch.Tensor 
     return plan
 
 
-PLAN_BYTES = ctypes.sizeof(Plan)
-
-
 class BatchedWorkspace:
     """A workspace prepared for one packed batch (C-ABI sincosm_batched_prepare).
 

@@ -583,8 +583,42 @@ static int tuned_cfg(Arith ar, int cls, int64_t np) {
   return -1;
 }
 
-sincosm_status launch_gemm(Arith ar, int tile, const GemmLaunch& g, hipStream_t stream) {
-  if (g.np % tile_size(tile) != 0) return SINCOSM_E_ARG;
+// Operand scales that are powers of two (with sign) commute with every
+// rounding of a product: the sum over k of (ls a)(rs b) is exactly ls rs times
+// the unscaled sum, away from overflow and the subnormal range. When all
+// k-segments of a problem carry one such factor ls rs, it moves into the
+// coefficients e_o of that problem's outputs (O_o = e_o D + ...) and the
+// kernels run without operand scaling; the results are the same. The factor
+// is kept within 2^-60 .. 2^60 so the unscaled accumulation stays far from
+// the float32 overflow threshold for the plans' operands.
+static bool pow2_scale(double x) {
+  int e = 0;
+  return x != 0.0 && fabs(frexp(x, &e)) == 0.5;
+}
+
+static bool fold_scales(const GemmLaunch& g, GemmLaunch& out) {
+  bool changed = false;
+  out = g;
+  for (int p = 0; p < g.nprob; ++p) {
+    const Problem& P = g.prob[p];
+    if (P.nseg == 0) continue;
+    const double f = P.seg[0].lscale * P.seg[0].rscale;
+    bool ok = f != 1.0 && fabs(f) >= 0x1p-60 && fabs(f) <= 0x1p60;
+    for (int s = 0; ok && s < P.nseg; ++s)
+      ok = pow2_scale(P.seg[s].lscale) && pow2_scale(P.seg[s].rscale) && P.seg[s].lscale * P.seg[s].rscale == f;
+    if (!ok) continue;
+    Problem& Q = out.prob[p];
+    for (int s = 0; s < Q.nseg; ++s) Q.seg[s].lscale = Q.seg[s].rscale = 1.0;
+    for (int o = 0; o < Q.nout; ++o) Q.out[o].e *= f;
+    changed = true;
+  }
+  return changed;
+}
+
+sincosm_status launch_gemm(Arith ar, int tile, const GemmLaunch& g0, hipStream_t stream) {
+  if (g0.np % tile_size(tile) != 0) return SINCOSM_E_ARG;
+  GemmLaunch folded;
+  const GemmLaunch& g = fold_scales(g0, folded) ? folded : g0;
   if (ar == Arith::BF16X3) return launch_gemm_bf16x3(tile, g, stream);
   int count = 0;
   const KernelCfg* t = cfg_table(ar, count);

@@ -347,7 +347,6 @@ sincosm_status sincosm_backward(int64_t n, int dtype, const void* A, int64_t lda
   r.Ap = Bp;
   for (int i = 0; i < 9; ++i) r.W[i] = base + L.w_off[i];
   r.stream = stream;
-  r.launched = 0;
   void* Rb[9];
   for (int i = 0; i < 9; ++i) Rb[i] = base + L.rev_off[i];
   void* cot[4];

@@ -61,7 +61,6 @@ sincosm_status sincosm_expi_eval(int64_t n, int dtype, const void* A, int64_t ld
   r.Ap = Xp;
   for (int i = 0; i < 9; ++i) r.W[i] = base + L.w_off[i];
   r.stream = stream;
-  r.launched = 0;
   void* Q[4];
   for (int i = 0; i < 4; ++i) Q[i] = base + L.q_off[i];
   r.Cout = internal(Q[1], m, m.sq_f64);

@@ -172,13 +172,12 @@ bool overlaps(const void* a, int64_t lda, const void* b, int64_t ldb, int64_t n,
 }
 
 // ----------------------------------------------------------------------------
-// Scheme launch sequences. Each launch adds its product count to r.launched.
+// Scheme launch sequences.
 // ----------------------------------------------------------------------------
 
 Target internal(void* p, const Modes& m, bool f64) { return Target{p, m.np, (int)m.np, f64}; }
 
 sincosm_status gemm(Run& r, Arith ar, const GemmLaunch& g, int kind) {
-  r.launched += g.nprob;
   if (r.rec) {
     if (r.rec->count >= 8) return SINCOSM_E_ARG;
     r.rec->launches[r.rec->count++] = g;

@@ -34,7 +34,6 @@ struct Run {
   void* W[9];
   Target Cout, Sout;   // where the scheme's C and S go (squaring input or user buffers)
   hipStream_t stream;
-  int launched;        // products enqueued so far (a double-angle launch counts two)
   Recorder* rec = nullptr;
   bool y_ready = false;   // W0 already holds Y = (2^-s A)^2: the schemes skip their first product
 };

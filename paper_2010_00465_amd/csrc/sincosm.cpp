@@ -131,7 +131,6 @@ sincosm_status sincosm_eval(int64_t n, int dtype, const void* A, int64_t lda, vo
   r.Ap = Ap;
   for (int i = 0; i < 9; ++i) r.W[i] = base + L.w_off[i];
   r.stream = stream;
-  r.launched = 0;
   SC_TRY(launch_norm_copy_plan(n, m.np, A, lda, m.user_f64, Ap, m.poly_f64, acc, ns, stream));
   sincosm_plan plans[2];
   if (refined) {
@@ -191,7 +190,6 @@ sincosm_status sincosm_eval_planned(int64_t n, int dtype, const void* A, int64_t
   r.Ap = Ap;
   for (int i = 0; i < 9; ++i) r.W[i] = base + L.w_off[i];
   r.stream = stream;
-  r.launched = 0;
   SC_TRY(launch_norm_copy_plan(n, m.np, A, lda, m.user_f64, Ap, m.poly_f64, acc, ns, stream));
   SC_TRY(launch_check_plan(acc, level, s, ns, plan_dev, stream));
   sincosm_plan plan;

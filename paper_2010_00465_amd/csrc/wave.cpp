@@ -237,7 +237,6 @@ static sincosm_status wave_body(WaveCall& c, int64_t n, double t, const Target* 
   r.Ap = c.base + c.L.ap_off;
   for (int i = 0; i < 9; ++i) r.W[i] = c.base + c.L.w_off[i];
   r.stream = c.stream;
-  r.launched = 0;
   void* Q[4];
   for (int i = 0; i < 4; ++i) Q[i] = c.base + c.L.q_off[i];
   const int s = c.plan.s;

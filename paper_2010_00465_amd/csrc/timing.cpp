@@ -32,7 +32,10 @@ TimingMark timing_begin(int kind, hipStream_t stream) {
   if (!enabled) return m;
   std::lock_guard<std::mutex> g(mu);
   m.a = take();
-  if (m.a) hipEventRecord((hipEvent_t)m.a, stream);
+  if (m.a && hipEventRecord((hipEvent_t)m.a, stream) != hipSuccess) {   // measurement only: skip it
+    pool.push_back((hipEvent_t)m.a);
+    m.a = nullptr;
+  }
   return m;
 }
 
@@ -40,8 +43,15 @@ void timing_end(const TimingMark& m, hipStream_t stream) {
   if (!enabled || !m.a) return;
   std::lock_guard<std::mutex> g(mu);
   hipEvent_t b = take();
-  if (!b) return;
-  hipEventRecord(b, stream);
+  if (!b) {
+    pool.push_back((hipEvent_t)m.a);
+    return;
+  }
+  if (hipEventRecord(b, stream) != hipSuccess) {
+    pool.push_back((hipEvent_t)m.a);
+    pool.push_back(b);
+    return;
+  }
   recs.push_back(Rec{m.kind, (hipEvent_t)m.a, b});
 }
 

@@ -603,10 +603,12 @@ static bool fold_scales(const GemmLaunch& g, GemmLaunch& out) {
     const Problem& P = g.prob[p];
     if (P.nseg == 0) continue;
     const double f = P.seg[0].lscale * P.seg[0].rscale;
-    bool ok = f != 1.0 && fabs(f) >= 0x1p-60 && fabs(f) <= 0x1p60;
-    for (int s = 0; ok && s < P.nseg; ++s)
+    bool scaled = false, ok = fabs(f) >= 0x1p-60 && fabs(f) <= 0x1p60;
+    for (int s = 0; ok && s < P.nseg; ++s) {
       ok = pow2_scale(P.seg[s].lscale) && pow2_scale(P.seg[s].rscale) && P.seg[s].lscale * P.seg[s].rscale == f;
-    if (!ok) continue;
+      scaled |= P.seg[s].lscale != 1.0 || P.seg[s].rscale != 1.0;
+    }
+    if (!ok || !scaled) continue;
     Problem& Q = out.prob[p];
     for (int s = 0; s < Q.nseg; ++s) Q.seg[s].lscale = Q.seg[s].rscale = 1.0;
     for (int o = 0; o < Q.nout; ++o) Q.out[o].e *= f;

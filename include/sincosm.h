@@ -311,10 +311,14 @@ sincosm_status sincosm_timing_read(int kind, double* total_ms, int64_t* count);
  * table used by launches of several problems with equal k-work (the
  * double-angle steps); with SINCOSM_TUNE_UNEVEN, the table of the remaining
  * launches: problems of unequal k-work or one problem with several k-segments
- * (the reverse pass). Both flags together are an error. Such launches use the
- * plain table where their own has no entry. Host-side state shared by all
+ * (the reverse pass). Such launches use the plain table where their own has
+ * no entry. With SINCOSM_TUNE_BATCHED, the entries choose the output tile of
+ * sincosm_eval_batched's per-matrix products by padded order: configuration 0
+ * is 64 x 64 (the default), 1 is 32 x 32; the choice is read when
+ * sincosm_eval_batched is called (a captured graph keeps the choice made at
+ * capture). More than one flag is an error. Host-side state shared by all
  * devices, thread-safe; results do not depend on it beyond rounding order. */
-enum { SINCOSM_TUNE_MULTI = 16, SINCOSM_TUNE_UNEVEN = 32 };
+enum { SINCOSM_TUNE_MULTI = 16, SINCOSM_TUNE_UNEVEN = 32, SINCOSM_TUNE_BATCHED = 64 };
 int sincosm_tune_num_configs(int arith);
 sincosm_status sincosm_tune_config_info(int arith, int idx, int32_t* info);
 sincosm_status sincosm_tune_set(int arith, int64_t np_lo, int64_t np_hi, int idx);

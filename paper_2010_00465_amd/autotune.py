@@ -11,7 +11,10 @@ steps): it forces each configuration for that class only
 ``sincosm_eval`` call with the library's launch timing. A third pass (float64)
 tunes the launches of unequal problems or several k-segments, which only the
 reverse pass makes (``SINCOSM_TUNE_UNEVEN``): it times whole
-``sincosm_backward`` calls with each configuration forced for that class. The fastest
+``sincosm_backward`` calls with each configuration forced for that class. A
+fourth pass picks the output tile of the batched kernel's per-matrix products
+(``SINCOSM_TUNE_BATCHED``: 64 x 64 or 32 x 32) per padded order, timing
+``sincosm_eval_batched`` on batches of one order. The fastest
 configuration per probe and class is written to a JSON cache with the range of
 padded orders it covers (midpoints between probes). ``apply_cache`` installs a
 cache in the library; the package calls it at import for the cache shipped
@@ -36,8 +39,10 @@ DEFAULT_CACHE = os.path.join(HERE, "tune_gfx950.json")
 ARITH = {"f64": 0, "f32": 1}
 MULTI = 16          # SINCOSM_TUNE_MULTI: the table of launches of several equal problems
 UNEVEN = 32         # SINCOSM_TUNE_UNEVEN: launches of unequal problems or several k-segments
-CLASS_FLAG = {"": 0, "multi": MULTI, "uneven": UNEVEN}
+BATCHED = 64        # SINCOSM_TUNE_BATCHED: the batched kernel's output tile per padded order
+CLASS_FLAG = {"": 0, "multi": MULTI, "uneven": UNEVEN, "batched": BATCHED}
 UNEVEN_PROBES = (256, 512, 1024, 2048, 4096)
+BATCHED_PROBES = (16, 32, 48, 64, 96, 128, 192, 256)
 PROBES = (256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096, 6144, 8192)
 
 
@@ -46,11 +51,11 @@ def padded(n: int) -> int:
     return (n + g - 1) // g * g
 
 
-def configs(arith: str):
+def configs(arith: str, flags: int = 0):
     out = []
-    for i in range(lib.sincosm_tune_num_configs(ARITH[arith])):
+    for i in range(lib.sincosm_tune_num_configs(ARITH[arith] | flags)):
         info = (ctypes.c_int32 * 8)()
-        lib.sincosm_tune_config_info(ARITH[arith], i, info)
+        lib.sincosm_tune_config_info(ARITH[arith] | flags, i, info)
         out.append({"idx": i, "bm": info[0], "bn": info[1], "bk": info[2], "wgm": info[3], "wgn": info[4],
                     "wpe": info[5], "direct": info[6], "kgroups": info[7]})
     return out
@@ -68,7 +73,8 @@ def apply_cache(path: str | None = None) -> int:
         arith, _, cls = key.partition("_")
         if arith not in ARITH or cls not in CLASS_FLAG:
             continue
-        if data.get("configs", {}).get(arith) != configs(arith):
+        table = arith + "_batched" if cls == "batched" else arith
+        if data.get("configs", {}).get(table) != configs(arith, CLASS_FLAG[cls] & BATCHED):
             continue   # tuned against another configuration table: its indices mean other kernels
         code = ARITH[arith] | CLASS_FLAG[cls]
         for e in entries:
@@ -146,18 +152,65 @@ def time_config_uneven(torch, sc, n: int, idx: int, reps: int) -> float:
     return e0.elapsed_time(e1) / reps
 
 
+def time_config_batched(torch, sc, arith: str, n: int, idx: int, reps: int) -> float:
+    """Average duration (ms) of sincosm_eval_batched on a batch of Gaussian matrices of order
+    n (||A||_1 = 8: level 7, s = 1) with batched tile configuration idx forced for that order."""
+    np_ = (n + 15) // 16 * 16
+    dt = torch.float64 if arith == "f64" else torch.float32
+    count = max(256, min(8192, int(2e8 // n ** 3)))
+    g = torch.Generator(device="cuda").manual_seed(n)
+    A = torch.randn(count, n, n, dtype=dt, device="cuda", generator=g)
+    A *= 8.0 / A.abs().sum(1).amax(1).view(count, 1, 1)
+    C, S = torch.empty_like(A), torch.empty_like(A)
+    ns, offs = [n] * count, [k * n * n for k in range(count)]
+    lib.sincosm_tune_set(ARITH[arith] | BATCHED, np_, np_, idx)
+    w = sc.BatchedWorkspace(ns, offs, dt, "cuda")
+    w.run(A, C, S)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        w.run(A, C, S)
+    e1.record()
+    torch.cuda.synchronize()
+    lib.sincosm_tune_set(ARITH[arith] | BATCHED, np_, np_, -1)
+    return e0.elapsed_time(e1) / reps
+
+
 def _ranges(nps, k):
     lo = 1 if k == 0 else (nps[k - 1] + nps[k]) // 2 + 1
     hi = 1 << 30 if k == len(nps) - 1 else (nps[k] + nps[k + 1]) // 2
     return lo, hi
 
 
-def tune(ariths=("f64", "f32"), probes=PROBES, reps=5, log=print):
+def tune_batched(torch, sc, arith: str, reps: int, log):
+    entries, timings = [], {}
+    nps = sorted({(n + 15) // 16 * 16 for n in BATCHED_PROBES})
+    for k, np_ in enumerate(nps):
+        best = None
+        timings[str(np_)] = {}
+        for c in configs(arith, BATCHED):
+            ms = time_config_batched(torch, sc, arith, np_, c["idx"], reps)
+            timings[str(np_)][str(c["idx"])] = ms
+            if best is None or ms < best[1]:
+                best = (c["idx"], ms)
+        lo, hi = _ranges(nps, k)
+        entries.append({"np_lo": lo, "np_hi": hi, "idx": best[0], "probe_np": np_, "ms": best[1]})
+        log(f"{arith} batched np={np_}: best tile {configs(arith, BATCHED)[best[0]]['bm']} {best[1]:.3f} ms")
+    return entries, timings
+
+
+def tune(ariths=("f64", "f32"), probes=PROBES, reps=5, log=print, batched_only=False):
     import torch
     import paper_2010_00465_amd as sc
     result = {"device": torch.cuda.get_device_name(0), "created": time.strftime("%Y-%m-%d %H:%M:%S"),
-              "configs": {a: configs(a) for a in ariths}, "entries": {}, "timings": {}}
+              "configs": {} if batched_only else {a: configs(a) for a in ariths}, "entries": {}, "timings": {}}
     for arith in ariths:
+        result["configs"][arith + "_batched"] = configs(arith, BATCHED)
+        result["entries"][arith + "_batched"], result["timings"][arith + "_batched"] = \
+            tune_batched(torch, sc, arith, reps, log)
+        if batched_only:
+            continue
         entries, timings = [], {}
         nps = sorted({padded(n) for n in probes})
         for k, np_ in enumerate(nps):
@@ -231,8 +284,17 @@ def main():
     ap.add_argument("--out", default=DEFAULT_CACHE)
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--arith", default="f64,f32")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="tune only the batched kernel's tiles and merge them into the --out cache")
     args = ap.parse_args()
-    res = tune(tuple(args.arith.split(",")), reps=args.reps, log=lambda s: print(s, flush=True))
+    res = tune(tuple(args.arith.split(",")), reps=args.reps, log=lambda s: print(s, flush=True),
+               batched_only=args.batched_only)
+    if args.batched_only and os.path.exists(args.out):
+        with open(args.out) as f:
+            old = json.load(f)
+        for key in ("configs", "entries", "timings"):
+            old.setdefault(key, {}).update(res[key])
+        res = old
     with open(args.out, "w") as f:
         json.dump(res, f, indent=1)
     print(f"wrote {args.out}")

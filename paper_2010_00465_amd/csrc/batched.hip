@@ -25,9 +25,9 @@
 namespace sc {
 namespace {
 
-constexpr int BT = 64;        // output tile of the per-workgroup product loop
+constexpr int BT = 64;        // largest output tile of the per-workgroup product loop
 constexpr int BBK = 16;       // k step
-constexpr int BNT = 256;      // threads (4 waves, 2 x 2 of 32 x 32)
+constexpr int BNT = 256;      // threads (4 waves in a 2 x 2 grid)
 constexpr int WG_PER_CU = 4;  // resident workgroups per CU the arena is sized for
 constexpr int NMAX = 256;     // largest order of the batched path
 
@@ -56,6 +56,7 @@ __host__ __device__ inline int level_index(int level) { return level == 3 ? 0 : 
 struct BatchArgs {
   int batch;
   int acc;
+  int8_t tile32[NMAX / 16 + 1];   // per padded order / 16: 1 = 32 x 32 output tiles, 0 = 64 x 64
   const int32_t* nmat;
   const int64_t* off;
   const int32_t* order;
@@ -116,18 +117,24 @@ struct Smem {
 };
 
 // One product of the current problem P (in LDS) over the whole np x np matrix,
-// by this workgroup alone: tiles of 64 x 64, operands staged through LDS with
-// rows/columns beyond np read as zero, MFMA blocks beyond np skipped.
+// by this workgroup alone: output tiles of tb x tb (tb = 2^lt, 64 or 32; the
+// four waves take tb/2 x tb/2 each), operands staged through LDS with
+// rows/columns beyond np read as zero, MFMA blocks beyond np skipped. The
+// smaller tile keeps all four waves busy on small orders. The tile is a
+// run-time value so that one copy of the loop serves both (a second inlined
+// copy pushes the kernel past its register budget).
 template <typename T>
-__device__ void wg_gemm(const Problem& P, int np, T* smem) {
+__device__ void wg_gemm(const Problem& P, int np, T* smem, int lt) {
   using M = BMma<T>;
   using acc_t = typename M::acc_t;
   using vec_t = typename Vec<T>::t;
   constexpr int VEC = Vec<T>::N;
   constexpr int LDA = Smem<T>::LDA, LDB = Smem<T>::LDB, LDE = Smem<T>::LDE;
-  constexpr int A_LOADS = BT * BBK / VEC / BNT;
-  constexpr int B_LOADS = BBK * BT / VEC / BNT;
-  static_assert(A_LOADS >= 1 && B_LOADS >= 1, "staging");
+  constexpr int F = BT / 32;                    // MFMA blocks per wave side at the largest tile
+  constexpr int A_LOADS = (BT * BBK / VEC + BNT - 1) / BNT;
+  constexpr int B_LOADS = (BBK * BT / VEC + BNT - 1) / BNT;
+  const int TB = 1 << lt, WT = TB >> 1;         // tile, wave tile
+  const bool two = WT > 16;                     // a wave holds 2 x 2 MFMA blocks
   T* const As0 = smem;
   T* const Bs0 = smem + 2 * BT * LDA;
 
@@ -136,15 +143,15 @@ __device__ void wg_gemm(const Problem& P, int np, T* smem) {
   const int lr = lane & 15, lg = lane >> 4;
   const int nseg = P.nseg, nin = P.nin, nout = P.nout, nvalid = P.nvalid;
   const int nk = np / BBK, nkt = nseg * nk;
-  const int tiles = (np + BT - 1) / BT;
+  const int tiles = (np + TB - 1) >> lt;
 
   for (int tm = 0; tm < tiles; ++tm) {
     for (int tn = 0; tn < tiles; ++tn) {
-      acc_t acc[2][2];
+      acc_t acc[F][F];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < F; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < F; ++j)
 #pragma unroll
           for (int r = 0; r < 4; ++r) acc[i][j][r] = (T)0;
       vec_t ra[A_LOADS], rb[B_LOADS];
@@ -157,16 +164,16 @@ __device__ void wg_gemm(const Problem& P, int np, T* smem) {
         for (int i = 0; i < A_LOADS; ++i) {
           const int e = (i * BNT + tid) * VEC;
           const int r = e / BBK, c = e - r * BBK;
-          const int gr = tm * BT + r;
-          if (gr < np) ra[i] = *(const vec_t*)(L + (int64_t)gr * np + k0 + c);
+          const int gr = tm * TB + r;
+          if (e < TB * BBK && gr < np) ra[i] = *(const vec_t*)(L + (int64_t)gr * np + k0 + c);
           else ra[i] = (vec_t)0;
         }
 #pragma unroll
         for (int i = 0; i < B_LOADS; ++i) {
           const int e = (i * BNT + tid) * VEC;
-          const int r = e / BT, c = e - r * BT;
-          const int gc = tn * BT + c;
-          if (gc < np) rb[i] = *(const vec_t*)(R + (int64_t)(k0 + r) * np + gc);
+          const int r = e >> lt, c = e - (r << lt);
+          const int gc = tn * TB + c;
+          if (e < BBK * TB && gc < np) rb[i] = *(const vec_t*)(R + (int64_t)(k0 + r) * np + gc);
           else rb[i] = (vec_t)0;
         }
       };
@@ -179,18 +186,20 @@ __device__ void wg_gemm(const Problem& P, int np, T* smem) {
         for (int i = 0; i < A_LOADS; ++i) {
           const int e = (i * BNT + tid) * VEC;
           const int r = e / BBK, c = e - r * BBK;
+          if (e < TB * BBK) {
 #pragma unroll
-          for (int q = 0; q < VEC; ++q) as[r * LDA + c + q] = ra[i][q] * ls;
+            for (int q = 0; q < VEC; ++q) as[r * LDA + c + q] = ra[i][q] * ls;
+          }
         }
 #pragma unroll
         for (int i = 0; i < B_LOADS; ++i) {
           const int e = (i * BNT + tid) * VEC;
-          const int r = e / BT, c = e - r * BT;
-          *(vec_t*)(bs + r * LDB + c) = rb[i] * rs;
+          const int r = e >> lt, c = e - (r << lt);
+          if (e < BBK * TB) *(vec_t*)(bs + r * LDB + c) = rb[i] * rs;
         }
       };
-      const bool rowok0 = tm * BT + wm * 32 < np, rowok1 = tm * BT + wm * 32 + 16 < np;
-      const bool colok0 = tn * BT + wn * 32 < np, colok1 = tn * BT + wn * 32 + 16 < np;
+      const bool rowok0 = tm * TB + wm * WT < np, rowok1 = two && tm * TB + wm * WT + 16 < np;
+      const bool colok0 = tn * TB + wn * WT < np, colok1 = two && tn * TB + wn * WT + 16 < np;
       if (nkt > 0) {
         gload(0);
         lstore(0, 0);
@@ -200,10 +209,12 @@ __device__ void wg_gemm(const Problem& P, int np, T* smem) {
         const int cur = kt & 1;
         if (kt + 1 < nkt) gload(kt + 1);
         if (rowok0 && colok0) {  // wave-uniform: this wave has at least one live block
-          const T* as = As0 + cur * (BT * LDA) + (wm * 32 + lr) * LDA + lg;
-          const T* bs = Bs0 + cur * (BBK * LDB) + lg * LDB + wn * 32 + lr;
+          const T* as = As0 + cur * (BT * LDA) + (wm * WT + lr) * LDA + lg;
+          const T* bs = Bs0 + cur * (BBK * LDB) + lg * LDB + wn * WT + lr;
 #pragma unroll
           for (int kk = 0; kk < BBK / 4; ++kk) {
+            // the second row/column of blocks lies inside the LDS tile also
+            // when tb = 32 (reads of unused staging), its products are skipped
             const T a0 = as[kk * 4], a1 = as[16 * LDA + kk * 4];
             const T b0 = bs[kk * 4 * LDB], b1 = bs[kk * 4 * LDB + 16];
             acc[0][0] = M::mma(a0, b0, acc[0][0]);
@@ -215,24 +226,26 @@ __device__ void wg_gemm(const Problem& P, int np, T* smem) {
         if (kt + 1 < nkt) lstore(cur ^ 1, kt + 1);
         __syncthreads();
       }
-      // epilogue: two bands of 32 rows staged through LDS, then coalesced
+      // epilogue: two bands of WT rows staged through LDS, then coalesced
       T* const E = smem;
       for (int band = 0; band < 2; ++band) {
         if (wm == band) {
 #pragma unroll
-          for (int i = 0; i < 2; ++i)
+          for (int i = 0; i < F; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < F; ++j)
+              if ((i == 0 && j == 0) || two) {
 #pragma unroll
-              for (int r = 0; r < 4; ++r)
-                E[(i * 16 + M::row_in_block(lg, r)) * LDE + wn * 32 + j * 16 + lr] = acc[i][j][r];
+                for (int r = 0; r < 4; ++r)
+                  E[(i * 16 + M::row_in_block(lg, r)) * LDE + wn * WT + j * 16 + lr] = acc[i][j][r];
+              }
         }
         __syncthreads();
 #pragma unroll 1
-        for (int e = tid * VEC; e < 32 * BT; e += BNT * VEC) {
-          const int br = e / BT, bc = e - br * BT;
-          const int row = tm * BT + band * 32 + br;
-          const int col = tn * BT + bc;
+        for (int e = tid * VEC; e < WT * TB; e += BNT * VEC) {
+          const int br = e >> lt, bc = e - (br << lt);
+          const int row = tm * TB + band * WT + br;
+          const int col = tn * TB + bc;
           if (row >= np || col >= np) continue;
           const vec_t v = *(const vec_t*)(E + br * LDE + bc);
           vec_t x[MAX_IN];
@@ -296,6 +309,7 @@ __global__ __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(3))) void b
     const int n = a.nmat[i];
     const int64_t off = a.off[i];
     const int np = (n + 15) & ~15;
+    const int lt = a.tile32[np >> 4] ? 5 : 6;   // log2 of the product tile
     const T* Ai = (const T*)a.A + off;
     T* Ci = (T*)a.C + off;
     T* Si = (T*)a.S + off;
@@ -379,7 +393,7 @@ __global__ __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(3))) void b
         }
       }
       __syncthreads();
-      wg_gemm<T>(prob, np, smem);
+      wg_gemm<T>(prob, np, smem, lt);
     }
     // s double-angle steps from (S, C) to (S', C'), ping-pong between the two
     // slot pairs; the last step writes the caller's matrices.
@@ -412,7 +426,7 @@ __global__ __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(3))) void b
           o.d = half == 0 ? 1.0 : 0.0;
         }
         __syncthreads();
-        wg_gemm<T>(prob, np, smem);
+        wg_gemm<T>(prob, np, smem, lt);
       }
     }
   }
@@ -590,6 +604,8 @@ sincosm_status sincosm_eval_batched(int64_t batch, int dtype, const void* A, voi
   a.arena = base + pr.L.arena_off;
   a.slot_bytes = (int64_t)pr.L.slot_bytes;
   a.counter = (unsigned int*)(base + pr.L.counter_off);
+  for (int b = 0; b <= NMAX / 16; ++b)   // product tile per padded order, from the tuning table
+    a.tile32[b] = (int8_t)(batched_tile(dtype == SINCOSM_F64 ? Arith::F64 : Arith::F32, 16 * b) == 1);
   const TimingMark t = timing_begin(SINCOSM_TIMING_BATCHED, stream);
   reset_counter_kernel<<<1, 64, 0, stream>>>(a.counter);
   if (dtype == SINCOSM_F64) batched_kernel<double><<<pr.L.slots, BNT, 0, stream>>>(a);

@@ -164,6 +164,9 @@ enum class Arith { F64, F32, BF16X3 };
 // Launch one GEMM-with-epilogue over all problems. `tile` selects the tile
 // configuration (see gemm.hip); np must be a multiple of tile_size(tile).
 sincosm_status launch_gemm(Arith ar, int tile, const GemmLaunch& g, hipStream_t stream);
+// Output tile (64 or 32) of the batched kernel's products for padded order np,
+// from the tuning table (64 where it has no entry).
+int batched_tile(Arith ar, int64_t np);
 int tile_size(int tile);
 int choose_tile(Arith ar, int64_t n);
 bool bf16x3_available();

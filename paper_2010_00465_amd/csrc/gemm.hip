@@ -563,6 +563,8 @@ static const KernelCfg* cfg_table(Arith ar, int& count) {
 //      equal problems can leave CUs idle here, so this class is tuned on its
 //      own and falls back to the single-product entries.
 // Classes 1 and 2 use class 0 entries when none of their own matches.
+// Class 3 holds the batched kernel's output tile per padded order instead of
+// a configuration of this file's kernels (0: 64 x 64, 1: 32 x 32).
 struct TuneEntry { int ar; int cls; int64_t lo, hi; int idx; };
 static std::mutex tune_mu;
 static std::vector<TuneEntry> tune_table;
@@ -573,6 +575,11 @@ static int launch_class(const GemmLaunch& g) {
     if (g.prob[p].nseg != g.prob[0].nseg) return 2;
   return 1;
 }
+
+static constexpr int TUNE_FLAGS = SINCOSM_TUNE_MULTI | SINCOSM_TUNE_UNEVEN | SINCOSM_TUNE_BATCHED;
+static constexpr int BATCHED_CLASS = 3;
+// Output tiles of the batched kernel, by configuration index.
+static const int kBatchedTile[] = {64, 32};
 
 static int tuned_cfg(Arith ar, int cls, int64_t np) {
   std::lock_guard<std::mutex> g(tune_mu);
@@ -617,6 +624,11 @@ static bool fold_scales(const GemmLaunch& g, GemmLaunch& out) {
   return changed;
 }
 
+int batched_tile(Arith ar, int64_t np) {
+  const int idx = tuned_cfg(ar, BATCHED_CLASS, np);
+  return idx == 1 ? 32 : 64;
+}
+
 sincosm_status launch_gemm(Arith ar, int tile, const GemmLaunch& g0, hipStream_t stream) {
   if (g0.np % tile_size(tile) != 0) return SINCOSM_E_ARG;
   GemmLaunch folded;
@@ -638,14 +650,21 @@ extern "C" {
 
 int sincosm_tune_num_configs(int arith) {
   int count = 0;
-  sc::cfg_table((sc::Arith)(arith & ~(int)(SINCOSM_TUNE_MULTI | SINCOSM_TUNE_UNEVEN)), count);
+  sc::cfg_table((sc::Arith)(arith & ~sc::TUNE_FLAGS), count);
+  if (count && (arith & SINCOSM_TUNE_BATCHED)) return (int)(sizeof(sc::kBatchedTile) / sizeof(int));
   return count;
 }
 
 sincosm_status sincosm_tune_config_info(int arith, int idx, int32_t* info) {
   int count = 0;
-  const sc::KernelCfg* t =
-      sc::cfg_table((sc::Arith)(arith & ~(int)(SINCOSM_TUNE_MULTI | SINCOSM_TUNE_UNEVEN)), count);
+  const sc::KernelCfg* t = sc::cfg_table((sc::Arith)(arith & ~sc::TUNE_FLAGS), count);
+  if (t && info && (arith & SINCOSM_TUNE_BATCHED)) {
+    if (idx < 0 || idx >= sincosm_tune_num_configs(arith)) return SINCOSM_E_ARG;
+    const int tb = sc::kBatchedTile[idx];   // four waves of tb/2 x tb/2, k depth 16, staged
+    info[0] = tb; info[1] = tb; info[2] = 16; info[3] = 2; info[4] = 2; info[5] = 3;
+    info[6] = 0; info[7] = 1;
+    return SINCOSM_OK;
+  }
   if (!t || !info || idx < 0 || idx >= count) return SINCOSM_E_ARG;
   info[0] = t[idx].bm; info[1] = t[idx].bn; info[2] = t[idx].bk;
   info[3] = t[idx].wgm; info[4] = t[idx].wgn; info[5] = t[idx].wpe; info[6] = t[idx].dl;
@@ -654,11 +673,13 @@ sincosm_status sincosm_tune_config_info(int arith, int idx, int32_t* info) {
 }
 
 sincosm_status sincosm_tune_set(int arith, int64_t np_lo, int64_t np_hi, int idx) {
-  if ((arith & SINCOSM_TUNE_MULTI) && (arith & SINCOSM_TUNE_UNEVEN)) return SINCOSM_E_ARG;
-  const int cls = (arith & SINCOSM_TUNE_UNEVEN) ? 2 : (arith & SINCOSM_TUNE_MULTI) ? 1 : 0;
-  const int ar = arith & ~(int)(SINCOSM_TUNE_MULTI | SINCOSM_TUNE_UNEVEN);
-  int count = 0;
-  sc::cfg_table((sc::Arith)ar, count);
+  const int flags = arith & sc::TUNE_FLAGS;
+  if (flags & (flags - 1)) return SINCOSM_E_ARG;   // at most one table flag
+  const int cls = (arith & SINCOSM_TUNE_BATCHED)  ? sc::BATCHED_CLASS
+                  : (arith & SINCOSM_TUNE_UNEVEN) ? 2
+                  : (arith & SINCOSM_TUNE_MULTI)  ? 1 : 0;
+  const int ar = arith & ~sc::TUNE_FLAGS;
+  int count = sincosm_tune_num_configs(arith);
   if (count == 0 || np_lo > np_hi) return SINCOSM_E_ARG;
   std::lock_guard<std::mutex> g(sc::tune_mu);
   if (idx < 0) {   // clear entries of this arithmetic and class overlapping the range

@@ -50,13 +50,17 @@ def test_shipped_cache_is_consistent(lib):
     data = json.load(open(path))
     for key, entries in data["entries"].items():
         arith, _, cls = key.partition("_")
-        assert cls in ("", "multi", "uneven"), key
-        n = lib.sincosm_tune_num_configs(autotune.ARITH[arith])
+        assert cls in ("", "multi", "uneven", "batched"), key
+        flag = autotune.CLASS_FLAG[cls] & autotune.BATCHED
+        n = lib.sincosm_tune_num_configs(autotune.ARITH[arith] | flag)
         prev_hi = 0
         for e in entries:
             assert 0 <= e["idx"] < n
             assert e["np_lo"] == prev_hi + 1 and e["np_hi"] >= e["np_lo"]
             prev_hi = e["np_hi"]
+            if flag:     # batched orders are padded to 16; the tile need not divide them
+                assert e["probe_np"] % 16 == 0 and e["probe_np"] <= 256
+                continue
             info = data["configs"][arith][e["idx"]]
             assert e["probe_np"] % info["bm"] == 0 and e["probe_np"] % info["bn"] == 0
 
@@ -66,6 +70,8 @@ def test_shipped_cache_matches_table_and_applies(lib):
     data = json.load(open(autotune.DEFAULT_CACHE))
     for arith in autotune.ARITH:
         assert data["configs"][arith] == autotune.configs(arith)
+        if arith + "_batched" in data["configs"]:
+            assert data["configs"][arith + "_batched"] == autotune.configs(arith, autotune.BATCHED)
     expected = sum(len(v) for v in data["entries"].values())
     assert autotune.apply_cache() == expected
 
@@ -78,10 +84,12 @@ def test_cache_of_another_table_is_skipped(lib, tmp_path):
     p.write_text(json.dumps(data))
     try:
         applied = autotune.apply_cache(str(p))
-        assert applied == sum(len(v) for k, v in data["entries"].items() if not k.startswith("f64"))
+        # the f64 product-kernel classes are skipped; the batched tile table is its own
+        skipped = [k for k in data["entries"] if k.startswith("f64") and not k.endswith("_batched")]
+        assert applied == sum(len(v) for k, v in data["entries"].items() if k not in skipped)
     finally:
         for arith in autotune.ARITH.values():
-            for code in (arith, arith | autotune.MULTI):
+            for code in (arith, arith | autotune.MULTI, arith | autotune.UNEVEN, arith | autotune.BATCHED):
                 lib.sincosm_tune_set(code, 1, 1 << 30, -1)
         autotune.apply_cache()
 
@@ -107,6 +115,28 @@ def test_uneven_class_flag(lib):
     assert lib.sincosm_tune_set(autotune.UNEVEN | autotune.MULTI, 1 << 40, 1 << 41, 1) == -1
     data = json.load(open(autotune.DEFAULT_CACHE))
     assert "f64_uneven" in data["entries"] and "f32_uneven" not in data["entries"]
+
+
+def test_batched_class_flag(lib):
+    """SINCOSM_TUNE_BATCHED addresses the batched kernel's tile table: two configurations
+    (64 x 64 and 32 x 32 output tiles); no other class flag may accompany it."""
+    from paper_2010_00465_amd import autotune
+    info = (ctypes.c_int32 * 8)()
+    for arith in (0, 1):
+        code = arith | autotune.BATCHED
+        assert lib.sincosm_tune_num_configs(code) == 2
+        tiles = []
+        for i in range(2):
+            assert lib.sincosm_tune_config_info(code, i, info) == 0
+            tiles.append((info[0], info[1], info[3], info[4]))
+        assert tiles == [(64, 64, 2, 2), (32, 32, 2, 2)]
+        assert lib.sincosm_tune_config_info(code, 2, info) == -1
+        assert lib.sincosm_tune_set(code, 1 << 40, 1 << 41, 2) == -1
+        assert lib.sincosm_tune_set(code, 1 << 40, 1 << 41, 1) == 0
+        assert lib.sincosm_tune_set(code, 1 << 40, 1 << 41, -1) == 0
+        for other in (autotune.MULTI, autotune.UNEVEN):
+            assert lib.sincosm_tune_set(code | other, 1 << 40, 1 << 41, 0) == -1
+    assert lib.sincosm_tune_num_configs(7 | autotune.BATCHED) == 0
 
 
 def test_padding_rule_matches_library(lib):

@@ -205,3 +205,49 @@ def test_batched_config_full_float32(env):
         tol = 5e-6 * max(1, 2 ** pl[i].s / 16)
         assert rel_fro(Cc[o:o + n * n].reshape(n, n), Cr) <= tol
         assert rel_fro(Sc[o:o + n * n].reshape(n, n), Sr) <= tol
+
+
+def _restore_batched_tiles(lib):
+    """Drop forced batched-tile entries and re-install the shipped cache's batched entries."""
+    import json
+    from paper_2010_00465_amd import autotune
+    for arith in autotune.ARITH.values():
+        lib.sincosm_tune_set(arith | autotune.BATCHED, 1, 1 << 30, -1)
+    data = json.load(open(autotune.DEFAULT_CACHE))
+    for key, entries in data.get("entries", {}).items():
+        arith, _, cls = key.partition("_")
+        if cls == "batched" and data["configs"].get(key) == autotune.configs(arith, autotune.BATCHED):
+            for e in entries:
+                lib.sincosm_tune_set(autotune.ARITH[arith] | autotune.BATCHED, e["np_lo"], e["np_hi"], e["idx"])
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_batched_tile_modes(env, dt):
+    """Each output tile of the batched kernel (64 x 64 and 32 x 32, forced through the tuning
+    table for every order) on a mixed batch: oracle parity, and the two tiles give bitwise the
+    same results (the tile changes which workgroup wave computes an element, not the order of
+    its k accumulation)."""
+    torch, sc = env
+    from paper_2010_00465_amd import _lib, autotune
+    lib = _lib.lib
+    sizes = [1, 5, 16, 17, 32, 33, 48, 63, 64, 65, 96, 100, 129, 160, 200, 255, 256]
+    mats = [W.gaussian(n, 2.0 ** (1 + (i % 7)), key=(88, n)) for i, n in enumerate(sizes)]
+    dtype, acc = (None, "double") if dt == "f64" else (torch.float32, "single")
+    if dt == "f32":
+        mats = [m.astype(np.float32).astype(np.float64) for m in mats]
+    results = []
+    try:
+        for idx in (0, 1):
+            print("[case] batched tile config", dt, idx, flush=True)
+            assert lib.sincosm_tune_set(autotune.ARITH[dt] | autotune.BATCHED, 1, 1 << 30, idx) == 0
+            out, plans = run_batch(env, mats, accuracy=acc, dtype=dtype)
+            results.append(out)
+            for A, (C, S), p in zip(mats, out, plans):
+                assert p.status == 0
+                Cr, Sr = R.sincosm(A)
+                tol = 1e-12 if dt == "f64" else 5e-6 * max(1, 2 ** p.s / 16)
+                assert rel_fro(C, Cr) <= tol and rel_fro(S, Sr) <= tol, (dt, idx, A.shape)
+    finally:
+        _restore_batched_tiles(lib)
+    for (C0, S0), (C1, S1) in zip(*results):
+        assert np.array_equal(C0, C1) and np.array_equal(S0, S1)

@@ -463,7 +463,7 @@ sincosm_status build_templates() {
     r.Cout = Target{(void*)(intptr_t)(ID_COUT + 1), 16, 16, true};
     r.Sout = Target{(void*)(intptr_t)(ID_SOUT + 1), 16, 16, true};
     r.stream = nullptr;
-      r.rec = &rec;
+    r.rec = &rec;
     SC_TRY(run_scheme(r, levels[li], SX_SENTINEL));
     for (int t = 0; t < rec.count; ++t) {
       if (rec.launches[t].nprob != 1) return SINCOSM_E_ARG;

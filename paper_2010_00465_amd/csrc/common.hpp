@@ -167,6 +167,21 @@ sincosm_status launch_gemm(Arith ar, int tile, const GemmLaunch& g, hipStream_t 
 // Output tile (64 or 32) of the batched kernel's products for padded order np,
 // from the tuning table (64 where it has no entry).
 int batched_tile(Arith ar, int64_t np);
+
+// Product-kernel configurations the autotuner chooses among: tile rows and
+// columns, k depth, wave grid, waves per SIMD, direct loads into LDS, k groups,
+// and the launcher. Entries 0, 1, 2 are the defaults for the padding
+// granularities 128, 64 and 32. cfg_table returns nullptr (count 0) for an
+// arithmetic without a table.
+typedef sincosm_status (*LaunchFn)(const GemmLaunch&, hipStream_t);
+struct KernelCfg {
+  int bm, bn, bk, wgm, wgn, wpe, dl, ks;
+  LaunchFn fn;
+};
+const KernelCfg* cfg_table(Arith ar, int& count);
+// Tuned configuration index for (arithmetic, launch class, padded order), or -1.
+// Classes 1 and 2 fall back to class 0 entries.
+int tuned_cfg(Arith ar, int cls, int64_t np);
 int tile_size(int tile);
 int choose_tile(Arith ar, int64_t n);
 bool bf16x3_available();

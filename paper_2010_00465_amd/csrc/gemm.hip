@@ -514,11 +514,6 @@ static sincosm_status launch_cfg(const GemmLaunch& g, hipStream_t stream) {
 // Entries 0, 1, 2 are the defaults for the three padding granularities 128, 64
 // and 32.
 // ----------------------------------------------------------------------------
-typedef sincosm_status (*LaunchFn)(const GemmLaunch&, hipStream_t);
-struct KernelCfg {
-  int bm, bn, bk, wgm, wgn, wpe, dl, ks;
-  LaunchFn fn;
-};
 
 #define SC_CFG(T, BM, BN, BK, WGM, WGN, WPE, DL) \
   { BM, BN, BK, WGM, WGN, WPE, DL, 1, &launch_cfg<T, BM, BN, BK, WGM, WGN, WPE, DL, 1> }
@@ -547,47 +542,20 @@ static const KernelCfg kF32[] = {
     SC_CFG_KS(float, 64, 64, 32, 2, 2, 2, 1, 2), SC_CFG_KS(float, 64, 64, 16, 2, 2, 2, 1, 2),
 };
 
-static const KernelCfg* cfg_table(Arith ar, int& count) {
+const KernelCfg* cfg_table(Arith ar, int& count) {
   if (ar == Arith::F64) { count = (int)(sizeof(kF64) / sizeof(kF64[0])); return kF64; }
   if (ar == Arith::F32) { count = (int)(sizeof(kF32) / sizeof(kF32[0])); return kF32; }
   count = 0;
   return nullptr;
 }
 
-// Tuning table: for (arith, launch class, padded order in [lo, hi]) use
-// configuration idx. Launch classes:
-//   0  one problem with at most one k-segment (a plain product);
-//   1  several problems with equal k-work (the double-angle steps);
-//   2  the rest: problems of unequal k-work, or one problem with several
-//      k-segments (the reverse pass). A tile that is a good choice for two
-//      equal problems can leave CUs idle here, so this class is tuned on its
-//      own and falls back to the single-product entries.
-// Classes 1 and 2 use class 0 entries when none of their own matches.
-// Class 3 holds the batched kernel's output tile per padded order instead of
-// a configuration of this file's kernels (0: 64 x 64, 1: 32 x 32).
-struct TuneEntry { int ar; int cls; int64_t lo, hi; int idx; };
-static std::mutex tune_mu;
-static std::vector<TuneEntry> tune_table;
-
+// Launch class of a product launch for the tuning table: 0 one problem with at
+// most one k-segment, 1 several problems of equal k-work, 2 the rest.
 static int launch_class(const GemmLaunch& g) {
   if (g.nprob <= 1) return g.prob[0].nseg <= 1 ? 0 : 2;
   for (int p = 1; p < g.nprob; ++p)
     if (g.prob[p].nseg != g.prob[0].nseg) return 2;
   return 1;
-}
-
-static constexpr int TUNE_FLAGS = SINCOSM_TUNE_MULTI | SINCOSM_TUNE_UNEVEN | SINCOSM_TUNE_BATCHED;
-static constexpr int BATCHED_CLASS = 3;
-// Output tiles of the batched kernel, by configuration index.
-static const int kBatchedTile[] = {64, 32};
-
-static int tuned_cfg(Arith ar, int cls, int64_t np) {
-  std::lock_guard<std::mutex> g(tune_mu);
-  const int order[2] = {cls, 0};
-  for (int k = 0; k < (cls == 0 ? 1 : 2); ++k)
-    for (auto it = tune_table.rbegin(); it != tune_table.rend(); ++it)
-      if (it->ar == (int)ar && it->cls == order[k] && np >= it->lo && np <= it->hi) return it->idx;
-  return -1;
 }
 
 // Operand scales that are powers of two (with sign) commute with every
@@ -624,11 +592,6 @@ static bool fold_scales(const GemmLaunch& g, GemmLaunch& out) {
   return changed;
 }
 
-int batched_tile(Arith ar, int64_t np) {
-  const int idx = tuned_cfg(ar, BATCHED_CLASS, np);
-  return idx == 1 ? 32 : 64;
-}
-
 sincosm_status launch_gemm(Arith ar, int tile, const GemmLaunch& g0, hipStream_t stream) {
   if (g0.np % tile_size(tile) != 0) return SINCOSM_E_ARG;
   GemmLaunch folded;
@@ -643,59 +606,5 @@ sincosm_status launch_gemm(Arith ar, int tile, const GemmLaunch& g0, hipStream_t
     idx = tile;
   return t[idx].fn(g, stream);
 }
-
-}  // namespace sc
-
-extern "C" {
-
-int sincosm_tune_num_configs(int arith) {
-  int count = 0;
-  sc::cfg_table((sc::Arith)(arith & ~sc::TUNE_FLAGS), count);
-  if (count && (arith & SINCOSM_TUNE_BATCHED)) return (int)(sizeof(sc::kBatchedTile) / sizeof(int));
-  return count;
-}
-
-sincosm_status sincosm_tune_config_info(int arith, int idx, int32_t* info) {
-  int count = 0;
-  const sc::KernelCfg* t = sc::cfg_table((sc::Arith)(arith & ~sc::TUNE_FLAGS), count);
-  if (t && info && (arith & SINCOSM_TUNE_BATCHED)) {
-    if (idx < 0 || idx >= sincosm_tune_num_configs(arith)) return SINCOSM_E_ARG;
-    const int tb = sc::kBatchedTile[idx];   // four waves of tb/2 x tb/2, k depth 16, staged
-    info[0] = tb; info[1] = tb; info[2] = 16; info[3] = 2; info[4] = 2; info[5] = 3;
-    info[6] = 0; info[7] = 1;
-    return SINCOSM_OK;
-  }
-  if (!t || !info || idx < 0 || idx >= count) return SINCOSM_E_ARG;
-  info[0] = t[idx].bm; info[1] = t[idx].bn; info[2] = t[idx].bk;
-  info[3] = t[idx].wgm; info[4] = t[idx].wgn; info[5] = t[idx].wpe; info[6] = t[idx].dl;
-  info[7] = t[idx].ks;
-  return SINCOSM_OK;
-}
-
-sincosm_status sincosm_tune_set(int arith, int64_t np_lo, int64_t np_hi, int idx) {
-  const int flags = arith & sc::TUNE_FLAGS;
-  if (flags & (flags - 1)) return SINCOSM_E_ARG;   // at most one table flag
-  const int cls = (arith & SINCOSM_TUNE_BATCHED)  ? sc::BATCHED_CLASS
-                  : (arith & SINCOSM_TUNE_UNEVEN) ? 2
-                  : (arith & SINCOSM_TUNE_MULTI)  ? 1 : 0;
-  const int ar = arith & ~sc::TUNE_FLAGS;
-  int count = sincosm_tune_num_configs(arith);
-  if (count == 0 || np_lo > np_hi) return SINCOSM_E_ARG;
-  std::lock_guard<std::mutex> g(sc::tune_mu);
-  if (idx < 0) {   // clear entries of this arithmetic and class overlapping the range
-    std::vector<sc::TuneEntry> keep;
-    for (auto& e : sc::tune_table)
-      if (!(e.ar == ar && e.cls == cls && e.hi >= np_lo && e.lo <= np_hi)) keep.push_back(e);
-    sc::tune_table.swap(keep);
-    return SINCOSM_OK;
-  }
-  if (idx >= count) return SINCOSM_E_ARG;
-  sc::tune_table.push_back(sc::TuneEntry{ar, cls, np_lo, np_hi, idx});
-  return SINCOSM_OK;
-}
-
-}  // extern "C"
-
-namespace sc {
 
 }  // namespace sc

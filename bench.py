@@ -78,6 +78,43 @@ def cpu_baseline(mats):
     return time.perf_counter() - t0, threads, out
 
 
+def cpu_host(n, products_per_step):
+    """The host CPU and the like-for-like CPU figure for the method: one float64 DGEMM of
+    order n through numpy (all threads, then one thread) times the step's product count."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((n, n))
+    Y = rng.standard_normal((n, n))
+    X @ Y
+    t0 = time.perf_counter()
+    X @ Y
+    t_all = time.perf_counter() - t0
+    t_one = None
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(1):
+            t0 = time.perf_counter()
+            X @ Y
+            t_one = time.perf_counter() - t0
+    except Exception:  # pragma: no cover - informational only
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "dgemm_s": t_all, "dgemm_1thread_s": t_one,
+            "products_per_step": products_per_step,
+            "paper_algorithm_evals_per_s": len(products_per_step) / (sum(products_per_step) * t_all),
+            "paper_algorithm_evals_per_s_1thread":
+                (len(products_per_step) / (sum(products_per_step) * t_one)) if t_one else None,
+            "note": f"(products per evaluation) x (one n={n} numpy DGEMM on this host): the CPU time of "
+                    "the method's own products, without its O(n^2) work"}
+
+
 KERNEL_SOURCES = ("gemm.hip", "epilogue.hpp")
 
 
@@ -476,6 +513,7 @@ def main():
 
     rel = None
     cpu = None
+    host = None
     if not args.no_cpu_baseline:
         secs, threads, ref = cpu_baseline(mats)
         rel = {"reference": "float64 CPU oracle (Taylor m=9 + double angle), same inputs",
@@ -490,6 +528,7 @@ def main():
         cpu = {"value": len(mats) / secs, "unit": "evals/s", "cores": threads, "kind": "oracle",
                "sample": f"one whole step (the four n={n} anchor matrices once each) through the float64 "
                          f"oracle on the host, {secs:.1f} s"}
+        host = cpu_host(n, products)
 
     extras = {}
     if not args.no_extras and n == N:
@@ -534,6 +573,7 @@ def main():
                             "tflops": (2.0 * n ** 3 / (sch_ms / sch_cnt / 1e3) / 1e12) if sch_cnt else None},
         "rel_err": rel,
         "cpu_baseline": cpu,
+        "cpu_host": host,
     }
     out.update(extras)
     print(json.dumps(out))

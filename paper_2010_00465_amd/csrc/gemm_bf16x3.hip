@@ -24,24 +24,33 @@
 namespace sc {
 
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
 typedef float v4f_b __attribute__((ext_vector_type(4)));
-typedef unsigned short v4us __attribute__((ext_vector_type(4)));
-typedef unsigned short v8us __attribute__((ext_vector_type(8)));
 
 struct MmaBf16 {
   typedef v4f_b acc_t;
   __device__ static inline int row_in_block(int lg, int r) { return 4 * lg + r; }
 };
 
-__device__ inline unsigned short bf16_rne(float x) {
-  const unsigned u = __float_as_uint(x);
-  return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+// hi = bf16(x), lo = bf16(x - hi) for four values, both rounded to nearest
+// even: gfx950 converts two float32 values to a bfloat16 pair in one
+// instruction; the pair widens back with a shift and a mask of its 32 bits,
+// and x - hi is exact.
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+typedef float v2f_b __attribute__((ext_vector_type(2)));
+__device__ inline void split2(float x0, float x1, unsigned& hi, unsigned& lo) {
+  const v2f_b x = {x0, x1};
+  const v2bf h = __builtin_convertvector(x, v2bf);
+  hi = __builtin_bit_cast(unsigned, h);
+  const v2f_b hf = {__uint_as_float(hi << 16), __uint_as_float(hi & 0xffff0000u)};
+  lo = __builtin_bit_cast(unsigned, __builtin_convertvector(x - hf, v2bf));
 }
-
-__device__ inline void split2(float x, unsigned short& hi, unsigned short& lo) {
-  hi = bf16_rne(x);
-  const float h = __uint_as_float((unsigned)hi << 16);
-  lo = bf16_rne(x - h);
+__device__ inline void split4(v4f_b x, v4bf& hi, v4bf& lo) {
+  unsigned h[2], l[2];
+  split2(x[0], x[1], h[0], l[0]);
+  split2(x[2], x[3], h[1], l[1]);
+  hi = __builtin_bit_cast(v4bf, h);
+  lo = __builtin_bit_cast(v4bf, l);
 }
 
 __device__ inline void tile_coords_b(int np, int BM, int BN, int nprob, int& p, int& tm, int& tn) {
@@ -60,7 +69,9 @@ __device__ inline void tile_coords_b(int np, int BM, int BN, int nprob, int& p, 
   tn = in_group / rows;
 }
 
-template <int BM, int BN, int WGM, int WGN, int WPE>
+// SCALED: some k-segment carries an operand scale other than 1 (otherwise
+// the split skips the multiplications).
+template <int BM, int BN, int WGM, int WGN, int WPE, bool SCALED>
 __global__ __launch_bounds__(WGM * WGN * 64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void gemm_bf16x3_kernel(const GemmLaunch g) {
   constexpr int NT = WGM * WGN * 64;
@@ -109,7 +120,7 @@ void gemm_bf16x3_kernel(const GemmLaunch g) {
     ldsA[i] = r * LDK + c;
   }
   const int bcol = tid % BN, bgrp = tid / BN;   // B: one column, rows bgrp*B_ROWS ..
-  const int offB = bgrp * B_ROWS * np + bcol;
+  const unsigned boffB = (unsigned)(bgrp * B_ROWS * np + bcol) * 4u;
   const int ldsB = bcol * LDK + bgrp * B_ROWS;
 
   const int nk = np / BK;
@@ -126,42 +137,34 @@ void gemm_bf16x3_kernel(const GemmLaunch g) {
     const float* R = (const float*)P.seg[sidx].R + b_tile + (int64_t)k0 * np;
 #pragma unroll
     for (int i = 0; i < A_LOADS; ++i) ra[i] = *(const v4f_b*)(L + offA[i]);
+    // row j of this thread's column: a uniform row pointer plus the thread's
+    // 32-bit byte offset (one scalar base per load, no 64-bit vector adds)
 #pragma unroll
-    for (int j = 0; j < B_ROWS; ++j) rb[j] = R[offB + j * np];
+    for (int j = 0; j < B_ROWS; ++j)
+      rb[j] = *(const float*)((const char*)(R + (int64_t)j * np) + boffB);
   };
 
   auto lstore = [&](int buf, int kt) {
     const Seg& S = P.seg[kt / nk];
-    const float ls = (float)S.lscale, rs = (float)S.rscale;
+    const float ls = SCALED ? (float)S.lscale : 1.f, rs = SCALED ? (float)S.rscale : 1.f;
     unsigned short* ahi = sm + buf * BUF;
     unsigned short* alo = ahi + PLANE_A;
     unsigned short* bhi = alo + PLANE_A;
     unsigned short* blo = bhi + PLANE_B;
 #pragma unroll
     for (int i = 0; i < A_LOADS; ++i) {
-      v4us h, l;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        unsigned short hh, ll;
-        split2(ra[i][q] * ls, hh, ll);
-        h[q] = hh;
-        l[q] = ll;
-      }
-      *(v4us*)(ahi + ldsA[i]) = h;
-      *(v4us*)(alo + ldsA[i]) = l;
+      v4bf h, l;
+      split4(ra[i] * ls, h, l);
+      *(v4bf*)(ahi + ldsA[i]) = h;
+      *(v4bf*)(alo + ldsA[i]) = l;
     }
 #pragma unroll
     for (int j0 = 0; j0 < B_ROWS; j0 += 4) {
-      v4us h, l;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        unsigned short hh, ll;
-        split2(rb[j0 + q] * rs, hh, ll);
-        h[q] = hh;
-        l[q] = ll;
-      }
-      *(v4us*)(bhi + ldsB + j0) = h;
-      *(v4us*)(blo + ldsB + j0) = l;
+      const v4f_b x = {rb[j0] * rs, rb[j0 + 1] * rs, rb[j0 + 2] * rs, rb[j0 + 3] * rs};
+      v4bf h, l;
+      split4(x, h, l);
+      *(v4bf*)(bhi + ldsB + j0) = h;
+      *(v4bf*)(blo + ldsB + j0) = l;
     }
   };
 
@@ -210,7 +213,14 @@ template <int BM, int BN, int WGM, int WGN, int WPE>
 static sincosm_status launch_b(const GemmLaunch& g, hipStream_t stream) {
   const int tiles = (g.np / BM) * (g.np / BN) * g.nprob;
   if (tiles <= 0) return SINCOSM_OK;
-  gemm_bf16x3_kernel<BM, BN, WGM, WGN, WPE><<<tiles, WGM * WGN * 64, 0, stream>>>(g);
+  bool scaled = false;
+  for (int p = 0; p < g.nprob; ++p)
+    for (int s = 0; s < g.prob[p].nseg; ++s)
+      scaled |= g.prob[p].seg[s].lscale != 1.0 || g.prob[p].seg[s].rscale != 1.0;
+  if (scaled)
+    gemm_bf16x3_kernel<BM, BN, WGM, WGN, WPE, true><<<tiles, WGM * WGN * 64, 0, stream>>>(g);
+  else
+    gemm_bf16x3_kernel<BM, BN, WGM, WGN, WPE, false><<<tiles, WGM * WGN * 64, 0, stream>>>(g);
   SC_HIP(hipGetLastError());
   return SINCOSM_OK;
 }

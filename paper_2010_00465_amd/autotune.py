@@ -42,7 +42,7 @@ UNEVEN = 32         # SINCOSM_TUNE_UNEVEN: launches of unequal problems or sever
 BATCHED = 64        # SINCOSM_TUNE_BATCHED: the batched kernel's output tile per padded order
 CLASS_FLAG = {"": 0, "multi": MULTI, "uneven": UNEVEN, "batched": BATCHED}
 UNEVEN_PROBES = (256, 512, 1024, 2048, 4096)
-BATCHED_PROBES = (16, 32, 48, 64, 96, 128, 192, 256)
+BATCHED_PROBES = (16, 32, 48, 64, 96, 128, 144, 160, 176, 192, 208, 224, 240, 256)
 PROBES = (256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096, 6144, 8192)
 
 
@@ -157,7 +157,7 @@ def time_config_batched(torch, sc, arith: str, n: int, idx: int, reps: int) -> f
     n (||A||_1 = 8: level 7, s = 1) with batched tile configuration idx forced for that order."""
     np_ = (n + 15) // 16 * 16
     dt = torch.float64 if arith == "f64" else torch.float32
-    count = max(256, min(8192, int(2e8 // n ** 3)))
+    count = 4096   # several matrices per resident workgroup of either kernel
     g = torch.Generator(device="cuda").manual_seed(n)
     A = torch.randn(count, n, n, dtype=dt, device="cuda", generator=g)
     A *= 8.0 / A.abs().sum(1).amax(1).view(count, 1, 1)

@@ -116,6 +116,45 @@ struct Smem {
   static constexpr int ELEMS = STAGE > EPI ? STAGE : EPI;
 };
 
+// Output stage of one VEC-wide piece of a product at (row, col) of the padded
+// np x np matrix, D = v: every output o of P receives e_o D + d_o I + the sum
+// over q of c_oq In_q (I only within the matrix's true order), coalesced
+// vector stores where the output is the padded matrix itself.
+template <typename T>
+__device__ inline void epi_piece(const Problem& P, int np, typename Vec<T>::t v, int row, int col, int nin,
+                                 int nout, int nvalid) {
+  using vec_t = typename Vec<T>::t;
+  constexpr int VEC = Vec<T>::N;
+  vec_t x[MAX_IN];
+#pragma unroll
+  for (int q = 0; q < MAX_IN; ++q)
+    if (q < nin) x[q] = *(const vec_t*)((const T*)P.in[q].p + (int64_t)row * np + col);
+  // outputs one at a time (coefficients re-read from LDS): keeps the
+  // register footprint small, the inputs stay in registers
+#pragma unroll 1
+  for (int o = 0; o < nout; ++o) {
+    const EpiOut& O = P.out[o];
+    vec_t val;
+#pragma unroll
+    for (int t = 0; t < VEC; ++t) {
+      T y = (row == col + t && row < nvalid) ? (T)O.d : (T)0;
+      y = __builtin_fma((T)O.e, v[t], y);
+#pragma unroll
+      for (int q = 0; q < MAX_IN; ++q)
+        if (q < nin) y = __builtin_fma((T)O.c[q], x[q][t], y);
+      val[t] = y;
+    }
+    const int64_t off = (int64_t)row * O.ld + col;
+    if (O.lim == np && O.ld == np && (((uintptr_t)O.p) & 15u) == 0) {
+      *(vec_t*)((T*)O.p + off) = val;
+    } else if (row < O.lim) {
+#pragma unroll
+      for (int t = 0; t < VEC; ++t)
+        if (col + t < O.lim) ((T*)O.p)[off + t] = val[t];
+    }
+  }
+}
+
 // One product of the current problem P (in LDS) over the whole np x np matrix,
 // by this workgroup alone: output tiles of tb x tb (tb = 2^lt, 64 or 32; the
 // four waves take tb/2 x tb/2 each), operands staged through LDS with
@@ -247,35 +286,7 @@ __device__ void wg_gemm(const Problem& P, int np, T* smem, int lt) {
           const int row = tm * TB + band * WT + br;
           const int col = tn * TB + bc;
           if (row >= np || col >= np) continue;
-          const vec_t v = *(const vec_t*)(E + br * LDE + bc);
-          vec_t x[MAX_IN];
-#pragma unroll
-          for (int q = 0; q < MAX_IN; ++q)
-            if (q < nin) x[q] = *(const vec_t*)((const T*)P.in[q].p + (int64_t)row * np + col);
-          // outputs one at a time (coefficients re-read from LDS): keeps the
-          // register footprint small, the inputs stay in registers
-#pragma unroll 1
-          for (int o = 0; o < nout; ++o) {
-            const EpiOut& O = P.out[o];
-            vec_t val;
-#pragma unroll
-            for (int t = 0; t < VEC; ++t) {
-              T y = (row == col + t && row < nvalid) ? (T)O.d : (T)0;
-              y = __builtin_fma((T)O.e, v[t], y);
-#pragma unroll
-              for (int q = 0; q < MAX_IN; ++q)
-                if (q < nin) y = __builtin_fma((T)O.c[q], x[q][t], y);
-              val[t] = y;
-            }
-            const int64_t off = (int64_t)row * O.ld + col;
-            if (O.lim == np && O.ld == np && (((uintptr_t)O.p) & 15u) == 0) {
-              *(vec_t*)((T*)O.p + off) = val;
-            } else if (row < O.lim) {
-#pragma unroll
-              for (int t = 0; t < VEC; ++t)
-                if (col + t < O.lim) ((T*)O.p)[off + t] = val[t];
-            }
-          }
+          epi_piece<T>(P, np, *(const vec_t*)(E + br * LDE + bc), row, col, nin, nout, nvalid);
         }
         __syncthreads();
       }
@@ -349,61 +360,60 @@ __global__ __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(3))) void b
     int c0, s0, c1, s1;
     squaring_slots(li, c0, s0, c1, s1);
 
+    // the scheme's products, then s double-angle steps of two products from
+    // (S, C) to (S', C'), ping-pong between the two slot pairs (the last step
+    // writes the caller's matrices); one product call site for all of them
     const int nst = g_tmpl_count[li];
-    for (int t = 0; t < nst; ++t) {
-      {  // cooperative word copy of the template into LDS
-        const unsigned long long* src = (const unsigned long long*)&g_tmpl[li][t];
-        unsigned long long* dst = (unsigned long long*)&prob;
-        for (int w = tid; w < (int)(sizeof(Problem) / 8); w += BNT) dst[w] = src[w];
-      }
-      __syncthreads();
-      if (tid == 0) {
-        prob.nvalid = n;
-        for (int q = 0; q < prob.nseg; ++q) {
-          Seg& g = prob.seg[q];
-          g.L = resolve<T>(g.L, slot, np);
-          g.R = resolve<T>(g.R, slot, np);
-          g.ldl = g.ldr = np;
-          if (g.lscale == SX_SENTINEL) g.lscale = sx;
-          if (g.rscale == SX_SENTINEL) g.rscale = sx;
+    for (int t = 0; t < nst + 2 * s; ++t) {
+      if (t < nst) {
+        {  // cooperative word copy of the template into LDS
+          const unsigned long long* src = (const unsigned long long*)&g_tmpl[li][t];
+          unsigned long long* dst = (unsigned long long*)&prob;
+          for (int w = tid; w < (int)(sizeof(Problem) / 8); w += BNT) dst[w] = src[w];
         }
-        for (int q = 0; q < prob.nin; ++q) {
-          prob.in[q].p = resolve<T>(prob.in[q].p, slot, np);
-          prob.in[q].ld = np;
-        }
-        for (int q = 0; q < prob.nout; ++q) {
-          EpiOut& o = prob.out[q];
-          const intptr_t id = (intptr_t)o.p - 1;
-          if (id == ID_COUT || id == ID_SOUT) {
-            if (s == 0) {
-              o.p = id == ID_COUT ? (void*)Ci : (void*)Si;
-              o.ld = n;
-              o.lim = n;
+        __syncthreads();
+        if (tid == 0) {
+          prob.nvalid = n;
+          for (int q = 0; q < prob.nseg; ++q) {
+            Seg& g = prob.seg[q];
+            g.L = resolve<T>(g.L, slot, np);
+            g.R = resolve<T>(g.R, slot, np);
+            g.ldl = g.ldr = np;
+            if (g.lscale == SX_SENTINEL) g.lscale = sx;
+            if (g.rscale == SX_SENTINEL) g.rscale = sx;
+          }
+          for (int q = 0; q < prob.nin; ++q) {
+            prob.in[q].p = resolve<T>(prob.in[q].p, slot, np);
+            prob.in[q].ld = np;
+          }
+          for (int q = 0; q < prob.nout; ++q) {
+            EpiOut& o = prob.out[q];
+            const intptr_t id = (intptr_t)o.p - 1;
+            if (id == ID_COUT || id == ID_SOUT) {
+              if (s == 0) {
+                o.p = id == ID_COUT ? (void*)Ci : (void*)Si;
+                o.ld = n;
+                o.lim = n;
+              } else {
+                o.p = slot + (int64_t)(id == ID_COUT ? c0 : s0) * np * np;
+                o.ld = np;
+                o.lim = np;
+              }
             } else {
-              o.p = slot + (int64_t)(id == ID_COUT ? c0 : s0) * np * np;
+              o.p = resolve<T>(o.p, slot, np);
               o.ld = np;
               o.lim = np;
             }
-          } else {
-            o.p = resolve<T>(o.p, slot, np);
-            o.ld = np;
-            o.lim = np;
+            o.f64 = sizeof(T) == 8;
           }
-          o.f64 = sizeof(T) == 8;
         }
-      }
-      __syncthreads();
-      wg_gemm<T>(prob, np, smem, lt);
-    }
-    // s double-angle steps from (S, C) to (S', C'), ping-pong between the two
-    // slot pairs; the last step writes the caller's matrices.
-    for (int j = 0; j < s; ++j) {
-      const bool last = j == s - 1;
-      T* Sc = slot + (int64_t)((j & 1) ? s1 : s0) * np * np;
-      T* Cc = slot + (int64_t)((j & 1) ? c1 : c0) * np * np;
-      T* Sn = last ? Si : slot + (int64_t)((j & 1) ? s0 : s1) * np * np;
-      T* Cn = last ? Ci : slot + (int64_t)((j & 1) ? c0 : c1) * np * np;
-      for (int half = 0; half < 2; ++half) {
+      } else {
+        const int j = (t - nst) >> 1, half = (t - nst) & 1;
+        const bool last = j == s - 1;
+        T* Sc = slot + (int64_t)((j & 1) ? s1 : s0) * np * np;
+        T* Cc = slot + (int64_t)((j & 1) ? c1 : c0) * np * np;
+        T* Sn = last ? Si : slot + (int64_t)((j & 1) ? s0 : s1) * np * np;
+        T* Cn = last ? Ci : slot + (int64_t)((j & 1) ? c0 : c1) * np * np;
         {
           unsigned long long* dst = (unsigned long long*)&prob;
           for (int w = tid; w < (int)(sizeof(Problem) / 8); w += BNT) dst[w] = 0ull;
@@ -425,9 +435,9 @@ __global__ __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(3))) void b
           o.e = half == 0 ? -2.0 : 2.0;
           o.d = half == 0 ? 1.0 : 0.0;
         }
-        __syncthreads();
-        wg_gemm<T>(prob, np, smem, lt);
       }
+      __syncthreads();
+      wg_gemm<T>(prob, np, smem, lt);
     }
   }
 }
@@ -605,7 +615,7 @@ sincosm_status sincosm_eval_batched(int64_t batch, int dtype, const void* A, voi
   a.slot_bytes = (int64_t)pr.L.slot_bytes;
   a.counter = (unsigned int*)(base + pr.L.counter_off);
   for (int b = 0; b <= NMAX / 16; ++b)   // product tile per padded order, from the tuning table
-    a.tile32[b] = (int8_t)(batched_tile(dtype == SINCOSM_F64 ? Arith::F64 : Arith::F32, 16 * b) == 1);
+    a.tile32[b] = (int8_t)(batched_tile(dtype == SINCOSM_F64 ? Arith::F64 : Arith::F32, 16 * b) == 32);
   const TimingMark t = timing_begin(SINCOSM_TIMING_BATCHED, stream);
   reset_counter_kernel<<<1, 64, 0, stream>>>(a.counter);
   if (dtype == SINCOSM_F64) batched_kernel<double><<<pr.L.slots, BNT, 0, stream>>>(a);

@@ -20,7 +20,7 @@ namespace {
 //      own and falls back to the single-product entries.
 // Classes 1 and 2 use class 0 entries when none of their own matches.
 // Class 3 holds the batched kernel's output tile per padded order instead of
-// a configuration of the product kernel (0: 64 x 64, 1: 32 x 32).
+// a configuration of the product kernel (0: 64 x 64, the default; 1: 32 x 32).
 struct TuneEntry { int ar; int cls; int64_t lo, hi; int idx; };
 std::mutex tune_mu;
 std::vector<TuneEntry> tune_table;
@@ -43,7 +43,7 @@ int tuned_cfg(Arith ar, int cls, int64_t np) {
 
 int batched_tile(Arith ar, int64_t np) {
   const int idx = tuned_cfg(ar, BATCHED_CLASS, np);
-  return idx == 1 ? 32 : 64;
+  return idx < 0 ? 64 : kBatchedTile[idx];
 }
 
 }  // namespace sc

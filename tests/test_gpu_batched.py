@@ -225,8 +225,8 @@ def _restore_batched_tiles(lib):
 def test_batched_tile_modes(env, dt):
     """Each output tile of the batched kernel (64 x 64 and 32 x 32, forced through the tuning
     table for every order) on a mixed batch: oracle parity, and the two tiles give bitwise the
-    same results (the tile changes which workgroup wave computes an element, not the order of
-    its k accumulation)."""
+    same results (the tile changes which wave computes an element, not the order of its k
+    accumulation)."""
     torch, sc = env
     from paper_2010_00465_amd import _lib, autotune
     lib = _lib.lib
@@ -249,5 +249,6 @@ def test_batched_tile_modes(env, dt):
                 assert rel_fro(C, Cr) <= tol and rel_fro(S, Sr) <= tol, (dt, idx, A.shape)
     finally:
         _restore_batched_tiles(lib)
-    for (C0, S0), (C1, S1) in zip(*results):
-        assert np.array_equal(C0, C1) and np.array_equal(S0, S1)
+    for other in results[1:]:
+        for (C0, S0), (C1, S1) in zip(results[0], other):
+            assert np.array_equal(C0, C1) and np.array_equal(S0, S1)

@@ -154,17 +154,18 @@ def time_config_uneven(torch, sc, n: int, idx: int, reps: int) -> float:
 
 def time_config_batched(torch, sc, arith: str, n: int, idx: int, reps: int) -> float:
     """Average duration (ms) of sincosm_eval_batched on a batch of Gaussian matrices of order
-    n (||A||_1 = 8: level 7, s = 1) with batched tile configuration idx forced for that order."""
+    n (||A||_1 = 8: level 7 with s = 3 in double, s = 1 in single) with batched tile
+    configuration idx forced for that order."""
     np_ = (n + 15) // 16 * 16
     dt = torch.float64 if arith == "f64" else torch.float32
-    count = 4096   # several matrices per resident workgroup of either kernel
+    count = 4096   # several matrices per resident workgroup
     g = torch.Generator(device="cuda").manual_seed(n)
     A = torch.randn(count, n, n, dtype=dt, device="cuda", generator=g)
     A *= 8.0 / A.abs().sum(1).amax(1).view(count, 1, 1)
     C, S = torch.empty_like(A), torch.empty_like(A)
     ns, offs = [n] * count, [k * n * n for k in range(count)]
     lib.sincosm_tune_set(ARITH[arith] | BATCHED, np_, np_, idx)
-    w = sc.BatchedWorkspace(ns, offs, dt, "cuda")
+    w = sc.BatchedWorkspace(ns, offs, dt, "cuda", "double" if arith == "f64" else "single")
     w.run(A, C, S)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

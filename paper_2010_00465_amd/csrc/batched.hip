@@ -317,7 +317,9 @@ __global__ __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(3))) void b
     __syncthreads();
     if (item >= a.batch) break;
     const int i = a.order[item];
+    if (i < 0 || i >= a.batch) continue;     // metadata not written by the prepare call
     const int n = a.nmat[i];
+    if (n < 1 || n > NMAX) continue;
     const int64_t off = a.off[i];
     const int np = (n + 15) & ~15;
     const int lt = a.tile32[np >> 4] ? 5 : 6;   // log2 of the product tile

@@ -185,6 +185,24 @@ def test_n4096_identities(env, e):
 # ---------------------------------------------------------------------------
 # Closed forms, edge cases, invariants
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("e", [33.0, 40.0])
+def test_large_norm_scaled_operands(env, e):
+    """||A||_1 = 2^e needs s > 30: the first product's operand scale 4^-s then lies outside
+    the range in which it moves into the epilogue, so the kernels scale the operands
+    themselves. Against eigh of a symmetric A; the s double-angle steps amplify rounding by
+    about 2^s, so the bar is 2^s 64 u (a missing or doubled scale gives errors of order 1)."""
+    say("eval large norm", e)
+    A = W.symmetric_gaussian(48, 2.0 ** e, key=(60, int(e)))
+    w, V = np.linalg.eigh(A)
+    Cr, Sr = (V * np.cos(w)) @ V.T, (V * np.sin(w)) @ V.T
+    C, S, plan = run(env, A)
+    assert plan_ok(plan, A) and plan.s > 30
+    tol = 2.0 ** plan.s * 64 * 2.0 ** -53
+    assert rel_fro(C, Cr) <= tol and rel_fro(S, Sr) <= tol
+    Cp, Sp = PA.sincosm(A)     # the same algorithm in float64 on the host
+    assert rel_fro(C, Cp) <= tol and rel_fro(S, Sp) <= tol
+
+
 def test_n1(env):
     for x in (0.0, 1e-3, 0.7, -2.5, 40.0):
         C, S, plan = run(env, np.array([[x]]))

@@ -75,6 +75,30 @@ def test_extra_scaling_is_accepted(env):
     assert rel_fro(C.cpu().numpy(), Cr) <= 1e-11 and rel_fro(S.cpu().numpy(), Sr) <= 1e-11
 
 
+@pytest.mark.parametrize("prod,acc,tol", [("native", "double", 1e-13), ("f32", "single", 2e-5),
+                                           ("bf16x3", "single", 8 * 7 * 2.0 ** -18)])
+def test_extra_scaling_beyond_fold_range(env, prod, acc, tol):
+    """A plan with s = 35 on a symmetric A with ||A||_1 = 1: the first product's operand scale
+    4^-35 lies outside the range in which a power-of-two scale moves into the epilogue, so
+    the product kernels (float64, float32 and split-bf16) scale the staged operands
+    themselves. For this A the extra double-angle steps add no error beyond rounding
+    (checked on the host with the oracle's schemes), so the bars are those of the
+    arithmetic: float64 near u, float32 and bf16x3 at their product error."""
+    torch, sc = env
+    print("[case] planned s=35", prod, acc, flush=True)
+    n = 64
+    A = W.symmetric_gaussian(n, 1.0, key=(61,))
+    w, V = np.linalg.eigh(A)
+    Cr, Sr = (V * np.cos(w)) @ V.T, (V * np.sin(w)) @ V.T
+    At = torch.from_numpy(A).cuda()
+    C, S = torch.empty_like(At), torch.empty_like(At)
+    pd = plan_buffer(torch)
+    sc.sincosm_eval_planned(At, C, S, (7, 35), acc, prod, plan_dev=pd)
+    rec = sc.plan_from_device(pd)
+    assert (rec.level, rec.s, rec.status) == (7, 35, 0)
+    assert rel_fro(C.cpu().numpy(), Cr) <= tol and rel_fro(S.cpu().numpy(), Sr) <= tol
+
+
 @pytest.mark.parametrize("acc", ["double", "single"])
 def test_plan_that_does_not_cover(env, acc):
     """||A||_1 2^-s just above the level's theta: status SINCOSM_E_PLAN, C and S all NaN;

@@ -5,7 +5,8 @@
 // (longest first), and runs that matrix's whole method alone: zero-padded
 // copy and 1-norm, plan (Tables 1-2), the scheme's products (Section 2.1) and
 // the s double-angle steps (Section 1), each product as a loop over 64 x 64
-// output tiles of the workgroup. Matrices never share a workgroup, so there
+// or 32 x 32 output tiles of the workgroup (per padded order, from the
+// tuning table). Matrices never share a workgroup, so there
 // is no synchronisation between workgroups; each resident workgroup owns one
 // arena slot of 10 padded matrices, so the workspace does not grow with the
 // batch. The stage descriptors of the four schemes are recorded once from the

@@ -322,6 +322,12 @@ enum { SINCOSM_TUNE_MULTI = 16, SINCOSM_TUNE_UNEVEN = 32, SINCOSM_TUNE_BATCHED =
 int sincosm_tune_num_configs(int arith);
 sincosm_status sincosm_tune_config_info(int arith, int idx, int32_t* info);
 sincosm_status sincosm_tune_set(int arith, int64_t np_lo, int64_t np_hi, int idx);
+/* The configuration index the table gives for padded order np in the table
+ * `arith` addresses (flags as for sincosm_tune_set; launches of several or
+ * unequal problems fall back to the plain table as the launches do), or -1
+ * when no entry covers it (the launch then uses its default) or `arith` is
+ * invalid. */
+int sincosm_tune_lookup(int arith, int64_t np);
 
 #ifdef __cplusplus
 }

@@ -73,6 +73,7 @@ SYMBOLS = {
     "sincosm_tune_num_configs": (_int, [_int]),
     "sincosm_tune_config_info": (_int, [_int, _int, ctypes.POINTER(_i32)]),
     "sincosm_tune_set": (_int, [_int, _i64, _i64, _int]),
+    "sincosm_tune_lookup": (_int, [_int, _i64]),
     "sincosm_timing_enable": (_int, [_int]),
     "sincosm_timing_read": (_int, [_int, ctypes.POINTER(_dbl), ctypes.POINTER(_i64)]),
     "sincosm_matmul_workspace_size": (_sz, [_i64, _int, _int]),

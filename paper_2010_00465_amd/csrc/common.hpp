@@ -180,7 +180,7 @@ struct KernelCfg {
 };
 const KernelCfg* cfg_table(Arith ar, int& count);
 // Tuned configuration index for (arithmetic, launch class, padded order), or -1.
-// Classes 1 and 2 fall back to class 0 entries.
+// Classes 1 and 2 fall back to class 0 entries; class 3 (the batched tile) does not.
 int tuned_cfg(Arith ar, int cls, int64_t np);
 int tile_size(int tile);
 int choose_tile(Arith ar, int64_t n);

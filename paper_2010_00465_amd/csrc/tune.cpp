@@ -35,7 +35,8 @@ const int kBatchedTile[] = {64, 32};
 int tuned_cfg(Arith ar, int cls, int64_t np) {
   std::lock_guard<std::mutex> g(tune_mu);
   const int order[2] = {cls, 0};
-  for (int k = 0; k < (cls == 0 ? 1 : 2); ++k)
+  const bool fallback = cls == 1 || cls == 2;   // the batched tile table has none
+  for (int k = 0; k < (fallback ? 2 : 1); ++k)
     for (auto it = tune_table.rbegin(); it != tune_table.rend(); ++it)
       if (it->ar == (int)ar && it->cls == order[k] && np >= it->lo && np <= it->hi) return it->idx;
   return -1;
@@ -43,7 +44,8 @@ int tuned_cfg(Arith ar, int cls, int64_t np) {
 
 int batched_tile(Arith ar, int64_t np) {
   const int idx = tuned_cfg(ar, BATCHED_CLASS, np);
-  return idx < 0 ? 64 : kBatchedTile[idx];
+  const int count = (int)(sizeof(kBatchedTile) / sizeof(kBatchedTile[0]));
+  return idx < 0 || idx >= count ? 64 : kBatchedTile[idx];
 }
 
 }  // namespace sc
@@ -102,6 +104,16 @@ sincosm_status sincosm_tune_set(int arith, int64_t np_lo, int64_t np_hi, int idx
            tt.end());
   tt.push_back(sc::TuneEntry{ar, cls, np_lo, np_hi, idx});
   return SINCOSM_OK;
+}
+
+int sincosm_tune_lookup(int arith, int64_t np) {
+  const int flags = arith & sc::TUNE_FLAGS;
+  if (flags & (flags - 1)) return -1;
+  const int cls = (arith & SINCOSM_TUNE_BATCHED)  ? sc::BATCHED_CLASS
+                  : (arith & SINCOSM_TUNE_UNEVEN) ? 2
+                  : (arith & SINCOSM_TUNE_MULTI)  ? 1 : 0;
+  if (sincosm_tune_num_configs(arith) == 0) return -1;
+  return sc::tuned_cfg((sc::Arith)(arith & ~sc::TUNE_FLAGS), cls, np);
 }
 
 }  // extern "C"

@@ -145,3 +145,37 @@ def test_padding_rule_matches_library(lib):
     for n in (1, 31, 200, 256, 1000, 1535, 1536, 4096, 4100):
         np_ = autotune.padded(n)
         assert lib.sincosm_matmul_workspace_size(n, 0, 0) == 2 * ((np_ * np_ * 8 + 255) // 256 * 256)
+
+
+def test_tune_lookup(lib):
+    """sincosm_tune_lookup reports what the launches use: later entries win (an entry set
+    again for the same range becomes the latest), clearing removes the range, the classes of
+    several or unequal problems fall back to the plain table, and the batched tile table
+    stands alone (no fallback: its indices are not product-kernel configurations)."""
+    from paper_2010_00465_amd import autotune
+    lo, hi = 1 << 40, (1 << 40) + 1000          # orders no cache entry covers
+    for code in (0, autotune.MULTI, autotune.UNEVEN, autotune.BATCHED):
+        assert lib.sincosm_tune_lookup(code, lo) == -1
+    try:
+        assert lib.sincosm_tune_set(0, lo, hi, 1) == 0
+        assert lib.sincosm_tune_lookup(0, lo + 5) == 1
+        assert lib.sincosm_tune_lookup(autotune.MULTI, lo + 5) == 1     # falls back to the plain table
+        assert lib.sincosm_tune_lookup(autotune.UNEVEN, lo + 5) == 1
+        assert lib.sincosm_tune_lookup(autotune.BATCHED, lo + 5) == -1  # no fallback for the batched tile
+        assert lib.sincosm_tune_set(0, lo, lo + 10, 2) == 0               # later, narrower entry wins
+        assert lib.sincosm_tune_lookup(0, lo + 5) == 2 and lib.sincosm_tune_lookup(0, lo + 500) == 1
+        assert lib.sincosm_tune_set(0, lo, hi, 0) == 0                    # the first range again: now the latest
+        assert lib.sincosm_tune_lookup(0, lo + 5) == 0 and lib.sincosm_tune_lookup(0, lo + 500) == 0
+        assert lib.sincosm_tune_set(autotune.MULTI, lo, hi, 3) == 0
+        assert lib.sincosm_tune_lookup(autotune.MULTI, lo + 500) == 3
+        assert lib.sincosm_tune_lookup(autotune.UNEVEN, lo + 500) == 0
+        assert lib.sincosm_tune_set(autotune.BATCHED, lo, hi, 1) == 0
+        assert lib.sincosm_tune_lookup(autotune.BATCHED, lo + 500) == 1
+        assert lib.sincosm_tune_lookup(1, lo + 500) == -1                 # other arithmetic untouched
+        assert lib.sincosm_tune_lookup(autotune.MULTI | autotune.UNEVEN, lo) == -1
+        assert lib.sincosm_tune_lookup(7, lo) == -1
+    finally:
+        for code in (0, autotune.MULTI, autotune.BATCHED):
+            assert lib.sincosm_tune_set(code, lo, hi, -1) == 0
+    for code in (0, autotune.MULTI, autotune.BATCHED):
+        assert lib.sincosm_tune_lookup(code, lo + 5) == -1

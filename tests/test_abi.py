@@ -151,3 +151,33 @@ def test_planned_argument_errors_without_gpu(lib):
     assert call(7, 3, n=0) == 0              # n = 0 is a no-op
     lib.sincosm_strerror.restype = ctypes.c_char_p
     assert lib.sincosm_strerror(-6) == b"the given plan does not cover the matrix 1-norm"
+
+
+def test_batched_argument_errors_without_gpu(lib):
+    """Argument checks of the batched entry points that come before any device work."""
+    i32 = ctypes.c_int32
+    ns = (i32 * 3)(4, 17, 256)
+    bad_n = (i32 * 2)(4, 257)
+    zero_n = (i32 * 2)(0, 5)
+    offs = (ctypes.c_int64 * 3)(0, 16, 16 + 289)
+    neg_offs = (ctypes.c_int64 * 3)(0, -1, 400)
+    lib.sincosm_batched_workspace_size.restype = ctypes.c_size_t
+    assert lib.sincosm_batched_workspace_size(0, ns, 0, 0, 0) == 0          # empty batch
+    assert lib.sincosm_batched_workspace_size(2, bad_n, 0, 0, 0) == 0       # order above 256
+    assert lib.sincosm_batched_workspace_size(2, zero_n, 0, 0, 0) == 0      # order 0
+    assert lib.sincosm_batched_workspace_size(3, ns, 7, 0, 0) == 0          # bad dtype
+    assert lib.sincosm_batched_workspace_size(3, ns, 0, 0, 2) == 0          # products other than native
+    assert lib.sincosm_batched_workspace_size(3, None, 0, 0, 0) == 0
+    assert lib.sincosm_batched_prepare(0, ns, offs, 0, None, 0, None) == -1
+    assert lib.sincosm_batched_prepare(2, bad_n, offs, 0, None, 0, None) == -1
+    assert lib.sincosm_batched_prepare(3, ns, neg_offs, 0, None, 0, None) == -1
+    assert lib.sincosm_batched_prepare(3, ns, None, 0, None, 0, None) == -1
+    assert lib.sincosm_batched_prepare(3, ns, offs, 5, None, 0, None) == -1
+    # sincosm_eval_batched: an empty batch is a no-op; bad enums and unprepared workspaces fail
+    assert lib.sincosm_eval_batched(0, 0, None, None, None, 0, 0, None, 0, None, None) == 0
+    assert lib.sincosm_eval_batched(-1, 0, None, None, None, 0, 0, None, 0, None, None) == -1
+    buf = ctypes.create_string_buffer(64)
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    assert lib.sincosm_eval_batched(3, 0, p, p, p, 9, 0, p, 64, None, None) == -1      # bad accuracy
+    assert lib.sincosm_eval_batched(3, 0, p, p, p, 0, 2, p, 64, None, None) == -2      # unsupported products
+    assert lib.sincosm_eval_batched(3, 0, p, p, p, 0, 0, p, 64, None, None) == -3      # never prepared

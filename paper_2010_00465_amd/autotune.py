@@ -16,7 +16,10 @@ fourth pass picks the output tile of the batched kernel's per-matrix products
 (``SINCOSM_TUNE_BATCHED``: 64 x 64 or 32 x 32) per padded order, timing
 ``sincosm_eval_batched`` on batches of one order. The fastest
 configuration per probe and class is written to a JSON cache with the range of
-padded orders it covers (midpoints between probes). ``apply_cache`` installs a
+padded orders it covers (midpoints between probes); for the single-product and
+double-angle classes the choice is then settled on whole evaluations (every
+pairing of each class's three fastest configurations on four anchor
+evaluations). ``apply_cache`` installs a
 cache in the library; the package calls it at import for the cache shipped
 next to this file (``tune_gfx950.json``) or the file named by
 ``SINCOSM_TUNE_CACHE``. Entries of an arithmetic whose recorded configuration
@@ -255,6 +258,7 @@ def tune(ariths=("f64", "f32"), probes=PROBES, reps=5, log=print, batched_only=F
                 f"({flops / (best[1] * 1e-3) / 1e12:.1f} TFLOP/s)")
         result["entries"][arith + "_multi"] = entries_m
         result["timings"][arith + "_multi"] = timings_m
+        refine_whole(torch, sc, result, arith, log=log)
         if arith != "f64":
             continue
         # launches of the reverse pass, with both tables above installed
@@ -278,6 +282,60 @@ def tune(ariths=("f64", "f32"), probes=PROBES, reps=5, log=print, batched_only=F
         result["entries"][arith + "_uneven"] = entries_u
         result["timings"][arith + "_uneven"] = timings_u
     return result
+
+
+def time_whole(torch, sc, arith: str, n: int, reps: int) -> float:
+    """Average duration (ms) of the four anchor evaluations (Gaussian, ||A||_1 = 2^-4, 2^0,
+    2^4, 2^10; 4, 7, 15 and 27 products in double) at order n, with the current table."""
+    dt = torch.float64 if arith == "f64" else torch.float32
+    acc = "double" if arith == "f64" else "single"
+    g = torch.Generator(device="cuda").manual_seed(n)
+    mats = []
+    for e in (-4, 0, 4, 10):
+        A = torch.randn(n, n, dtype=torch.float64, device="cuda", generator=g)
+        mats.append((A * (2.0 ** e / float(A.abs().sum(0).max()))).to(dt))
+    C, S = torch.empty_like(mats[0]), torch.empty_like(mats[0])
+    ws = torch.empty(sc.workspace_size(n, dt, acc), dtype=torch.uint8, device="cuda")
+    for A in mats:
+        sc.sincosm_eval(A, C, S, acc, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for A in mats:
+            sc.sincosm_eval(A, C, S, acc, ws=ws)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps
+
+
+def refine_whole(torch, sc, result, arith: str, top: int = 3, reps: int = 2, log=print):
+    """Whole-evaluation pass: per probe order, the `top` fastest configurations of the
+    single-product and the double-angle classes (from the launch timings above) are tried in
+    every pairing on four anchor evaluations, and the fastest pairing replaces the entries of
+    that probe's range. The launch timings alone miss what consecutive launches of one
+    evaluation do to each other (caches, the other class's tail)."""
+    ent, ent_m = result["entries"][arith], result["entries"][arith + "_multi"]
+    tim, tim_m = result["timings"][arith], result["timings"][arith + "_multi"]
+    code = ARITH[arith]
+    for e, em in zip(ent, ent_m):
+        np_ = e["probe_np"]
+        c0 = sorted(tim[str(np_)], key=lambda k: tim[str(np_)][k])[:top]
+        c1 = sorted(tim_m[str(np_)], key=lambda k: tim_m[str(np_)][k])[:top]
+        best = None
+        for a in c0:
+            for b in c1:
+                lib.sincosm_tune_set(code, np_, np_, int(a))
+                lib.sincosm_tune_set(code | MULTI, np_, np_, int(b))
+                ms = time_whole(torch, sc, arith, np_, reps)
+                if best is None or ms < best[2]:
+                    best = (int(a), int(b), ms)
+        lib.sincosm_tune_set(code, np_, np_, -1)
+        lib.sincosm_tune_set(code | MULTI, np_, np_, -1)
+        lib.sincosm_tune_set(code, int(e["np_lo"]), int(e["np_hi"]), best[0])
+        lib.sincosm_tune_set(code | MULTI, int(em["np_lo"]), int(em["np_hi"]), best[1])
+        log(f"{arith} np={np_}: whole evaluations best with configs {best[0]} / {best[1]} "
+            f"({best[2]:.2f} ms for four anchors; launch timings chose {e['idx']} / {em['idx']})")
+        e["idx"], em["idx"] = best[0], best[1]
+        e["whole_ms"] = em["whole_ms"] = best[2]
 
 
 def main():

@@ -63,6 +63,19 @@ def copy_calibration(n):
                                            "copy_kernel_bytes_written": 8 * n * n}}))
 
 
+def product_config(lib, n, flags):
+    """The product-kernel configuration the tuning table gives launches of this class at
+    padded order n (the bench's n is a multiple of 128, so it is its own padded order)."""
+    import ctypes
+    idx = lib.sincosm_tune_lookup(flags, n)
+    if idx < 0:
+        return "default configuration"
+    info = (ctypes.c_int32 * 8)()
+    lib.sincosm_tune_config_info(0, idx, info)
+    return (f"configuration {idx}: {info[0]}x{info[1]} tile, k step {info[2]}, {info[3] * info[4] * info[7]} waves"
+            + (", direct loads" if info[6] else "") + (f", {info[7]} k groups" if info[7] > 1 else ""))
+
+
 def cpu_baseline(mats):
     """Time the float64 oracle on one whole step (every anchor matrix once).
 
@@ -564,7 +577,7 @@ def main():
         "tflops_algorithmic": tflops,
         "pct_fp64_mfma_peak": 100.0 * tflops / FP64_MFMA_PEAK_TFLOPS,
         "roofline": {"bound": "mfma", "kernel": "double-angle product launch (FP64 MFMA product kernel, "
-                                                "2 problems, configuration from the tuning cache)",
+                                                "2 problems, " + product_config(_lib.lib, n, 16) + ")",
                      "achieved": sq_tflops, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": (sq_tflops / FP64_MFMA_PEAK_TFLOPS) if sq_tflops else None,
                      "traffic": measured_traffic(), "launches": sq_cnt,

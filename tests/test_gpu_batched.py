@@ -252,3 +252,19 @@ def test_batched_tile_modes(env, dt):
     for other in results[1:]:
         for (C0, S0), (C1, S1) in zip(results[0], other):
             assert np.array_equal(C0, C1) and np.array_equal(S0, S1)
+
+
+def test_sincosm_batched_list_helper(env):
+    """The list front end packs square GPU matrices (views included) into one batched call:
+    each result equals the oracle, and an empty list gives empty lists."""
+    torch, sc = env
+    big = torch.from_numpy(W.gaussian(120, 6.0, key=(89, 0))).cuda()
+    mats = [big[:100, :100], torch.from_numpy(W.gaussian(37, 0.5, key=(89, 1))).cuda(),
+            torch.from_numpy(W.gaussian(1, 3.0, key=(89, 2))).cuda(), big[10:74, 20:84]]
+    Cs, Ss = sc.sincosm_batched(mats)
+    torch.cuda.synchronize()
+    for M, C, S in zip(mats, Cs, Ss):
+        Cr, Sr = R.sincosm(M.cpu().numpy())
+        assert C.shape == M.shape and S.shape == M.shape
+        assert rel_fro(C.cpu().numpy(), Cr) <= 1e-12 and rel_fro(S.cpu().numpy(), Sr) <= 1e-12
+    assert sc.sincosm_batched([]) == ([], [])

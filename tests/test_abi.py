@@ -181,3 +181,16 @@ def test_batched_argument_errors_without_gpu(lib):
     assert lib.sincosm_eval_batched(3, 0, p, p, p, 9, 0, p, 64, None, None) == -1      # bad accuracy
     assert lib.sincosm_eval_batched(3, 0, p, p, p, 0, 2, p, 64, None, None) == -2      # unsupported products
     assert lib.sincosm_eval_batched(3, 0, p, p, p, 0, 0, p, 64, None, None) == -3      # never prepared
+
+
+def test_python_host_plan_helpers():
+    """The package's host plan helpers marshal to the C ABI: same integers as the oracle."""
+    import paper_2010_00465_amd as sc
+    from oracle import plan as P
+    from oracle import wave as Wv
+    for x in (0.0, 1e-3, 0.5, 1.0, 2.0, 37.5, 2.0 ** 10):
+        for acc in ("double", "single"):
+            p = sc.plan_host(x, acc)
+            assert (p.level, p.s, p.products, p.status) == (*P.plan(x, acc), 0)
+            q = sc.wave_plan_host(x, acc)
+            assert (q.level, q.s, q.products, q.status) == (*Wv.wave_plan(x, acc), 0)

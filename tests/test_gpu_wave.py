@@ -294,3 +294,17 @@ def test_block_n1(env):
         A = torch.tensor([[a]], dtype=torch.float64, device="cuda")
         E = sc.wave_block(A, 0.9).cpu().numpy()
         assert rel_fro(E, Pr.symplectic(np.array([[a]]), 0.9)) <= 1e-14
+
+
+def test_wave_helper_matches_entry_point(env):
+    """sc.wave allocates and calls sincosm_wave_eval on a contiguous copy: bitwise the same
+    results for a strided view."""
+    torch, sc = env
+    big = torch.from_numpy(W.gaussian(150, 3.0, key=(95,))).cuda()
+    A = big[5:133, 7:135]
+    C, S = sc.wave(A, 0.75)
+    Ac = A.contiguous()
+    C1, S1 = torch.empty_like(Ac), torch.empty_like(Ac)
+    sc.sincosm_wave_eval(Ac, 0.75, C1, S1)
+    torch.cuda.synchronize()
+    assert torch.equal(C, C1) and torch.equal(S, S1)

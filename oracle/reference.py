@@ -23,7 +23,9 @@ triangular integer matrices against the exact finite Taylor sum in rationals;
 the 2x2 overscaling family [[c, c*lam], [0, -c]] (A^2 = c^2 I) and the
 rotation generator tJ (cos(tJ) = cosh(t) I, sin(tJ) = sinh(t) J) in closed
 form; 1x1 matrices against libm; random 8x8 matrices against mpmath's
-cosm/sinm at 60 digits; cos^2 + sin^2 = I and CS = SC.
+cosm/sinm at 60 digits; nonnormal matrices with ||A||_1 <= 1e-3 against 40-term
+Taylor sums in mpmath at 50 digits (C - I to a few units of rounding);
+cos^2 + sin^2 = I and CS = SC.
 """
 from __future__ import annotations
 

@@ -4,8 +4,9 @@ Each test compares with something fixed by mathematics, not by the oracle:
 elementwise cos/sin on diagonal matrices, eigendecomposition for symmetric
 matrices, exact rational finite sums for nilpotent matrices, closed forms for
 matrices with A^2 = c^2 I and for the rotation generator, libm on 1x1
-matrices, mpmath's arbitrary-precision cosm/sinm on random matrices, and the
-identities cos^2 + sin^2 = I, CS = SC.
+matrices, mpmath's arbitrary-precision cosm/sinm on random matrices, 40-term
+Taylor sums at 50 digits on tiny nonnormal matrices, and the identities
+cos^2 + sin^2 = I, CS = SC.
 """
 import math
 from fractions import Fraction
@@ -119,6 +120,53 @@ def test_mpmath_random_nonsymmetric(e):
     C, S = R.sincosm(A)
     assert rel_fro(C, Cm) <= 1e-14 * max(1, 2.0 ** e)
     assert rel_fro(S, Sm) <= 1e-14 * max(1, 2.0 ** e)
+
+
+def _mp_taylor(A, terms=40, dps=50):
+    """cos A and sin A as the plain Taylor sums that define them (Section 2.1), powers A^0 ..
+    A^(2 terms - 1), every product and sum in mpmath at `dps` digits; also C - I."""
+    with mpmath.workdps(dps):
+        n = A.shape[0]
+        M = mpmath.matrix(A.tolist())
+        P = mpmath.eye(n)
+        C = mpmath.zeros(n, n)
+        S = mpmath.zeros(n, n)
+        fact = mpmath.mpf(1)
+        for k in range(2 * terms):
+            if k > 0:
+                P = P * M
+                fact *= k
+            term = P / fact
+            if k % 2 == 0:
+                C += term if (k // 2) % 2 == 0 else -term
+            else:
+                S += term if (k // 2) % 2 == 0 else -term
+        I = mpmath.eye(n)
+        to_np = lambda X: np.array([[float(X[i, j]) for j in range(n)] for i in range(n)])
+        return to_np(C), to_np(S), to_np(C - I)
+
+
+@pytest.mark.parametrize("norm", [1e-3, 1e-5, 1e-8])
+@pytest.mark.parametrize("kind", ["gaussian", "triangular"])
+def test_tiny_norm_mpmath_taylor(norm, kind):
+    """||A||_1 <= 1e-3, nonnormal: the oracle (s = 0, Horner to degree 18/19) against a
+    40-term Taylor sum at 50 digits. C - I is compared separately, with an absolute bar of a
+    few units of rounding of C (its entries are near those of I), so that the A^2 term
+    beneath the identity is pinned: at ||A||_1 = 1e-3 it is 1e-7, nine orders of magnitude
+    above the bar, so a wrong sign or factorial there fails (measured: at most 1.5 u)."""
+    if kind == "gaussian":
+        A = W.gaussian(10, norm, key=(16, int(-math.log10(norm))))
+    else:
+        G = np.triu(W.rng(17, int(-math.log10(norm))).standard_normal((10, 10)))
+        G[np.triu_indices(10, 1)] *= 30.0        # strongly nonnormal, not nilpotent
+        A = W.rescale(G, norm)
+    Cm, Sm, CmI = _mp_taylor(A)
+    C, S = R.sincosm(A)
+    assert R.scaling_used(A) == 0
+    u = 2.0 ** -53
+    assert rel_fro(C, Cm) <= 2e-16
+    assert rel_fro(S, Sm) <= 4e-16
+    assert np.linalg.norm((C - np.eye(10)) - CmI) <= 4 * u * 10 ** 0.5
 
 
 def test_long_double_agrees_with_mpmath():

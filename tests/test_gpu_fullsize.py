@@ -94,7 +94,7 @@ def test_sincosm_f32_single_n8192(env, eig):
     rows = sample_rows(N, 2)
     Cr = rows_of(eig, N, rows, lambda l: np.cos(c * l))
     Sr = rows_of(eig, N, rows, lambda l: np.sin(c * l))
-    tol = 5e-6 * max(1, 2 ** plan.s / 16)
+    tol = 5e-6
     assert rel_fro(C[rows].double().cpu().numpy(), Cr) <= tol
     assert rel_fro(S[rows].double().cpu().numpy(), Sr) <= tol
 

@@ -5,8 +5,7 @@ schemes with the same plan, oracle/wave.py paper_wave) for the double-accuracy f
 path, and against the independent Taylor reference (oracle/wave.py reference) where the
 two oracles themselves agree to well below that (||t^2 A||_1 <= 2^8); plan integers equal
 the oracle's wave plan (either neighbour accepted within 1e-12 relative of a breakpoint).
-Float32 storage / single accuracy: 5e-6 relative (the single-accuracy bar), scaled by
-2^s / 16 for the double-angle growth as in the cos/sin tests."""
+Float32 storage / single accuracy: 5e-6 relative (the single-accuracy bar)."""
 import math
 import sys
 
@@ -247,7 +246,7 @@ def test_float32_single(env, n, e):
     C, S, plan = run(env, A32, t, accuracy="single", dtype=torch.float32)
     assert plan_ok(plan, A32.astype(np.float64), t, "single")
     Cr, Sr = Wv.reference(A32.astype(np.float64), t)
-    tol = 5e-6 * max(1, 2 ** plan.s / 16)
+    tol = 5e-6
     assert rel_fro(C, Cr) <= tol and rel_fro(S, Sr) <= tol
 
 

@@ -49,7 +49,8 @@ typedef enum {
   SINCOSM_E_WORKSPACE = -3,   /* workspace missing or smaller than the query's size */
   SINCOSM_E_NONFINITE = -4,   /* A holds Inf/NaN (or its 1-norm overflows): outputs set to NaN */
   SINCOSM_E_HIP = -5,         /* a HIP runtime call failed */
-  SINCOSM_E_PLAN = -6         /* a caller's plan does not cover ||A||_1: outputs set to NaN */
+  SINCOSM_E_PLAN = -6,        /* a caller's plan does not cover ||A||_1: outputs set to NaN */
+  SINCOSM_E_TOO_LARGE = -7    /* the matrix needs more workspace than the library's static scratch */
 } sincosm_status;
 
 /* Storage type of A, C, S and of the gradients. */
@@ -165,6 +166,30 @@ sincosm_status sincosm_eval_planned(int64_t n, int dtype, const void* A, int64_t
                                     int acc, int prod, const sincosm_plan* plan_in,
                                     void* ws, size_t ws_bytes, sincosm_plan* plan_dev,
                                     void* stream);
+
+/* Size in bytes of the static device scratch array behind
+ * sincosm_eval_planned_noalloc (one per GPU the library runs on, held until
+ * the process ends). */
+#define SINCOSM_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/* sincosm_eval_planned without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). The workspace is a static device array of
+ * SINCOSM_NOALLOC_SCRATCH_BYTES bytes that the library holds per GPU; the call
+ * makes no hipMalloc, hipFree or other allocating call, no synchronisation and
+ * records no timing events. Arguments, launches, results (bitwise) and errors
+ * are those of sincosm_eval_planned; in addition it returns SINCOSM_E_TOO_LARGE
+ * (nothing enqueued) when sincosm_workspace_size(n, dtype, acc, prod) exceeds
+ * the scratch size (float64 storage with native products up to n = 512,
+ * float32 storage up to n = 768).
+ * Every call on a GPU shares that GPU's array, which keeps the last call's
+ * contents: calls that overlap in time on one GPU (other streams, other host
+ * threads) race and give undefined results; calls ordered on one stream are
+ * safe. */
+sincosm_status sincosm_eval_planned_noalloc(int64_t n, int dtype, const void* A, int64_t lda,
+                                            void* C, int64_t ldc, void* S, int64_t lds,
+                                            int acc, int prod, const sincosm_plan* plan_in,
+                                            sincosm_plan* plan_dev, void* stream);
 
 /* Plan of the wave-equation schemes for a given ||B||_1, B = t^2 A (host, pure).
  * level in {2,3,4,5} (= products of the Section 2.2 scheme), s = number of

@@ -27,7 +27,8 @@ TUNED_ENTRIES = _autotune.apply_cache()
 __all__ = ["sincosm", "sincosm_eval", "sincosm_eval_batched", "sincosm_backward", "sincosm_matmul",
            "plan_host", "plan_device", "workspace_size", "Plan", "SincosmError", "sincosm_batched",
            "wave_plan_host", "sincosm_wave_eval", "wave", "sincosm_wave_block_eval", "wave_block",
-           "sincosm_expi_eval", "expi", "sincosm_eval_planned", "plan_from_device", "PLAN_BYTES"]
+           "sincosm_expi_eval", "expi", "sincosm_eval_planned", "plan_from_device", "PLAN_BYTES",
+           "sincosm_eval_planned_noalloc"]
 
 
 def _dtype_code(t: torch.Tensor) -> int:
@@ -138,6 +139,31 @@ def sincosm_eval_planned(A: torch.Tensor, C: torch.Tensor, S: torch.Tensor, plan
     check(lib.sincosm_eval_planned(n, dt, A.data_ptr(), _ld(A), C.data_ptr(), _ld(C), S.data_ptr(), _ld(S),
                                    _acc(accuracy, extended), PROD[products], ctypes.byref(p), ws.data_ptr(),
                                    ws.numel(), pd, _stream(A)), "sincosm_eval_planned")
+
+
+def sincosm_eval_planned_noalloc(A: torch.Tensor, C: torch.Tensor, S: torch.Tensor, plan,
+                                 accuracy: str = "double", products: str = "native",
+                                 plan_dev: torch.Tensor | None = None, extended: bool = False) -> None:
+    """C-ABI sincosm_eval_planned_noalloc: sincosm_eval_planned on the library's static device
+    scratch (no workspace, nothing allocated by the call). Raises SincosmError with status
+    E_TOO_LARGE when the order needs more than NOALLOC_SCRATCH_BYTES of workspace. Calls
+    that overlap in time on one GPU share the scratch and race."""
+    _require_cuda(A, C, S)
+    n = A.shape[0]
+    p = Plan()
+    if isinstance(plan, Plan):
+        p.level, p.s = plan.level, plan.s
+    else:
+        p.level, p.s = int(plan[0]), int(plan[1])
+    pd = None
+    if plan_dev is not None:
+        _require_cuda(plan_dev)
+        if plan_dev.numel() * plan_dev.element_size() < PLAN_BYTES:
+            raise ValueError("plan_dev holds fewer than PLAN_BYTES bytes")
+        pd = plan_dev.data_ptr()
+    check(lib.sincosm_eval_planned_noalloc(n, _dtype_code(A), A.data_ptr(), _ld(A), C.data_ptr(), _ld(C),
+                                           S.data_ptr(), _ld(S), _acc(accuracy, extended), PROD[products],
+                                           ctypes.byref(p), pd, _stream(A)), "sincosm_eval_planned_noalloc")
 
 
 def plan_from_device(plan_dev: torch.Tensor) -> Plan:

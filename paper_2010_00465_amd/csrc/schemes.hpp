@@ -36,6 +36,7 @@ struct Run {
   hipStream_t stream;
   Recorder* rec = nullptr;
   bool y_ready = false;   // W0 already holds Y = (2^-s A)^2: the schemes skip their first product
+  bool timed = true;      // launch timing may record events (off where nothing may be allocated)
 };
 
 // Launch capture used to build the batched path's stage templates from the
@@ -65,5 +66,10 @@ sincosm_status scheme6(Run& r, double sx);
 sincosm_status scheme7(Run& r, double sx);
 sincosm_status run_scheme(Run& r, int level, double sx);
 sincosm_status double_angle(Run& r, const void* Sc, const void* Cc, const Target& Cn, const Target& Sn);
+// Body of sincosm_eval_planned on a given workspace (timed = false: no launch
+// timing events, so nothing is allocated).
+sincosm_status eval_planned(int64_t n, int dtype, const void* A, int64_t lda, void* C, int64_t ldc, void* S,
+                            int64_t lds, int acc, int prod, const sincosm_plan* plan_in, void* ws,
+                            size_t ws_bytes, sincosm_plan* plan_dev, hipStream_t stream, bool timed);
 
 }  // namespace sc

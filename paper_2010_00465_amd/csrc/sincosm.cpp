@@ -57,6 +57,49 @@ sincosm_status check_eval_args(int64_t n, int dtype, const void* A, int64_t lda,
 
 }  // namespace
 
+namespace sc {
+
+sincosm_status eval_planned(int64_t n, int dtype, const void* A, int64_t lda, void* C, int64_t ldc, void* S,
+                            int64_t lds, int acc, int prod, const sincosm_plan* plan_in, void* ws,
+                            size_t ws_bytes, sincosm_plan* plan_dev, hipStream_t stream, bool timed) {
+  if (n < 0 || n > (1 << 20) || !plan_in) return SINCOSM_E_ARG;
+  if (!acc_valid(acc, SINCOSM_PLAN_EXTENDED)) return SINCOSM_E_ARG;
+  const int level = plan_in->level, s = plan_in->s;
+  const bool level_ok = level == 3 || level == 4 || level == 6 || level == 7 ||
+                        (level == 5 && (acc & SINCOSM_PLAN_EXTENDED));
+  if (!level_ok || s < 0 || s > 1100) return SINCOSM_E_ARG;
+  Modes m;
+  if (!modes_for(n > 0 ? n : 1, dtype, prod, m)) return SINCOSM_E_ARG;
+  if (n == 0) return SINCOSM_OK;
+  SC_TRY(check_eval_args(n, dtype, A, lda, C, ldc, S, lds, m, ws, ws_bytes));
+  const Layout L = layout_for(m);
+  char* base = (char*)ws;
+  const NormScratch ns = norm_scratch(base + L.norm_off, m.np);
+  void* Ap = base + L.ap_off;
+  Run r;
+  r.m = &m;
+  r.n = n;
+  r.Ap = Ap;
+  for (int i = 0; i < 9; ++i) r.W[i] = base + L.w_off[i];
+  r.stream = stream;
+  r.timed = timed;
+  SC_TRY(launch_norm_copy_plan(n, m.np, A, lda, m.user_f64, Ap, m.poly_f64, acc, ns, stream));
+  SC_TRY(launch_check_plan(acc, level, s, ns, plan_dev, stream));
+  sincosm_plan plan;
+  plan.level = level;
+  plan.s = s;
+  plan.products = level + 2 * s;
+  plan.status = SINCOSM_OK;
+  plan.norm1 = 0.0;
+  const Target userC{C, ldc, (int)n, m.user_f64};
+  const Target userS{S, lds, (int)n, m.user_f64};
+  SC_TRY(enqueue_method(r, m, L, base, plan, userC, userS));
+  SC_TRY(launch_fill_nan_if(ns.plan, n, C, ldc, m.user_f64, stream));
+  return launch_fill_nan_if(ns.plan, n, S, lds, m.user_f64, stream);
+}
+
+}  // namespace sc
+
 extern "C" {
 
 const char* sincosm_strerror(int status) {
@@ -68,6 +111,7 @@ const char* sincosm_strerror(int status) {
     case SINCOSM_E_NONFINITE: return "input holds Inf or NaN";
     case SINCOSM_E_HIP: return "HIP runtime error";
     case SINCOSM_E_PLAN: return "the given plan does not cover the matrix 1-norm";
+    case SINCOSM_E_TOO_LARGE: return "the matrix needs more workspace than the static scratch holds";
     default: return "unknown status";
   }
 }
@@ -169,40 +213,8 @@ sincosm_status sincosm_eval(int64_t n, int dtype, const void* A, int64_t lda, vo
 sincosm_status sincosm_eval_planned(int64_t n, int dtype, const void* A, int64_t lda, void* C, int64_t ldc,
                                     void* S, int64_t lds, int acc, int prod, const sincosm_plan* plan_in,
                                     void* ws, size_t ws_bytes, sincosm_plan* plan_dev, void* stream_) {
-  if (n < 0 || n > (1 << 20) || !plan_in) return SINCOSM_E_ARG;
-  if (!acc_valid(acc, SINCOSM_PLAN_EXTENDED)) return SINCOSM_E_ARG;
-  const int level = plan_in->level, s = plan_in->s;
-  const bool level_ok = level == 3 || level == 4 || level == 6 || level == 7 ||
-                        (level == 5 && (acc & SINCOSM_PLAN_EXTENDED));
-  if (!level_ok || s < 0 || s > 1100) return SINCOSM_E_ARG;
-  Modes m;
-  if (!modes_for(n > 0 ? n : 1, dtype, prod, m)) return SINCOSM_E_ARG;
-  if (n == 0) return SINCOSM_OK;
-  SC_TRY(check_eval_args(n, dtype, A, lda, C, ldc, S, lds, m, ws, ws_bytes));
-  const Layout L = layout_for(m);
-  hipStream_t stream = (hipStream_t)stream_;
-  char* base = (char*)ws;
-  const NormScratch ns = norm_scratch(base + L.norm_off, m.np);
-  void* Ap = base + L.ap_off;
-  Run r;
-  r.m = &m;
-  r.n = n;
-  r.Ap = Ap;
-  for (int i = 0; i < 9; ++i) r.W[i] = base + L.w_off[i];
-  r.stream = stream;
-  SC_TRY(launch_norm_copy_plan(n, m.np, A, lda, m.user_f64, Ap, m.poly_f64, acc, ns, stream));
-  SC_TRY(launch_check_plan(acc, level, s, ns, plan_dev, stream));
-  sincosm_plan plan;
-  plan.level = level;
-  plan.s = s;
-  plan.products = level + 2 * s;
-  plan.status = SINCOSM_OK;
-  plan.norm1 = 0.0;
-  const Target userC{C, ldc, (int)n, m.user_f64};
-  const Target userS{S, lds, (int)n, m.user_f64};
-  SC_TRY(enqueue_method(r, m, L, base, plan, userC, userS));
-  SC_TRY(launch_fill_nan_if(ns.plan, n, C, ldc, m.user_f64, stream));
-  return launch_fill_nan_if(ns.plan, n, S, lds, m.user_f64, stream);
+  return eval_planned(n, dtype, A, lda, C, ldc, S, lds, acc, prod, plan_in, ws, ws_bytes, plan_dev,
+                      (hipStream_t)stream_, true);
 }
 
 size_t sincosm_matmul_workspace_size(int64_t n, int dtype, int prod) {

@@ -200,6 +200,28 @@ def bench_batched(torch, sc, W):
     loop()
     t_loop = _elapsed(torch, loop, 1)
     loop_flops = float(sum(p.products * 2.0 * int(n) ** 3 for p, n in zip(pl[:k], ns[:k])))
+    # the same loop with the plan decided on the device (no read-back; s <= 8 for these norms),
+    # eagerly and as one captured HIP graph of all 400 calls
+    s_max = 8
+
+    def loop_async():
+        for m, (c, s_) in zip(mats, outs):
+            sc.sincosm_eval_async(m, c, s_, s_max, ws=ws)
+
+    loop_async()
+    t_loop_async = _elapsed(torch, loop_async, 1)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        loop_async()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g_loop = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g_loop):
+        loop_async()
+    g_loop.replay()
+    t_loop_graph = _elapsed(torch, g_loop.replay, 3)
+    del g_loop
     # the same call captured in a HIP graph and replayed
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
@@ -222,6 +244,10 @@ def bench_batched(torch, sc, W):
             "graph_replay_ms": 1e3 * t_graph,
             "loop_of_sincosm_eval": {"matrices": k, "evals_per_s": k / t_loop,
                                      "tflops_algorithmic": loop_flops / t_loop / 1e12},
+            "loop_of_sincosm_eval_async": {"matrices": k, "s_max": s_max, "evals_per_s": k / t_loop_async,
+                                           "tflops_algorithmic": loop_flops / t_loop_async / 1e12,
+                                           "graph_replay_evals_per_s": k / t_loop_graph,
+                                           "graph_replay_tflops_algorithmic": loop_flops / t_loop_graph / 1e12},
             "speedup_vs_loop": (len(ns) / t) / (k / t_loop),
             "float32_single": {"ms_per_batch": 1e3 * t32, "evals_per_s": len(ns) / t32,
                                "tflops_algorithmic": flops32 / t32 / 1e12,

@@ -24,7 +24,8 @@
  *  - `stream` is a hipStream_t passed as void*; NULL means the default
  *    stream. Work is enqueued on it. sincosm_eval and sincosm_backward read
  *    the 24-byte plan back to the host (one stream synchronisation) before
- *    they enqueue the products, so they return after the plan is known.
+ *    they enqueue the products, so they return after the plan is known;
+ *    sincosm_eval_async decides the plan on the device and never waits.
  *  - The caller owns every buffer. The library allocates no device memory:
  *    each call takes a workspace whose size the matching *_workspace_size
  *    query returns. Results are deterministic (bitwise) for identical inputs,
@@ -50,7 +51,8 @@ typedef enum {
   SINCOSM_E_NONFINITE = -4,   /* A holds Inf/NaN (or its 1-norm overflows): outputs set to NaN */
   SINCOSM_E_HIP = -5,         /* a HIP runtime call failed */
   SINCOSM_E_PLAN = -6,        /* a caller's plan does not cover ||A||_1: outputs set to NaN */
-  SINCOSM_E_TOO_LARGE = -7    /* the matrix needs more workspace than the library's static scratch */
+  SINCOSM_E_TOO_LARGE = -7,   /* the matrix needs more workspace than the library's static scratch */
+  SINCOSM_E_SCALING = -8      /* the plan needs more double-angle steps than the call allowed: NaN outputs */
 } sincosm_status;
 
 /* Storage type of A, C, S and of the gradients. */
@@ -166,6 +168,32 @@ sincosm_status sincosm_eval_planned(int64_t n, int dtype, const void* A, int64_t
                                     int acc, int prod, const sincosm_plan* plan_in,
                                     void* ws, size_t ws_bytes, sincosm_plan* plan_dev,
                                     void* stream);
+
+/* sincosm_eval with the plan decided on the device: the call only enqueues
+ * kernels on `stream` (no read-back, no synchronisation, no allocation), so it
+ * can be captured in a HIP graph without knowing the plan (Tables 1-2 applied
+ * to ||A||_1 on the device). It enqueues a fixed sequence: the 1-norm and the
+ * plan (2 launches), the schemes' shared first product, the other products of
+ * the four schemes packed into 6 launches (7 with SINCOSM_PLAN_EXTENDED) whose
+ * workgroups compute the product of the plan's level, s_max double-angle
+ * steps whose workgroups return at once beyond the plan's s, and a copy of
+ * the result into C and S. The products computed are those sincosm_eval
+ * computes for the same plan, with the 2^-s scales resolved on the device, so
+ * the results are bitwise those of sincosm_eval.
+ *  s_max: 0 <= s_max <= 1100, the largest number of double-angle steps the
+ *  call may need; a plan with s > s_max gives status SINCOSM_E_SCALING and C
+ *  and S filled with NaN (double table: s_max = k covers ||A||_1 <=
+ *  1.8548 * 2^k). Each unused step costs one launch that does no work.
+ *  plan_dev (device, nullable): receives the plan record {level, s, products,
+ *  status, norm1} once the stream reaches it; status SINCOSM_OK,
+ *  SINCOSM_E_NONFINITE (C, S = NaN) or SINCOSM_E_SCALING (C, S = NaN).
+ *  acc: DOUBLE or SINGLE, optionally | SINCOSM_PLAN_EXTENDED (the refined-norm
+ *  flag is not accepted). Other arguments, the workspace and the synchronous
+ *  argument errors as sincosm_eval. */
+sincosm_status sincosm_eval_async(int64_t n, int dtype, const void* A, int64_t lda,
+                                  void* C, int64_t ldc, void* S, int64_t lds,
+                                  int acc, int prod, int32_t s_max, void* ws, size_t ws_bytes,
+                                  sincosm_plan* plan_dev, void* stream);
 
 /* Size in bytes of the static device scratch array behind
  * sincosm_eval_planned_noalloc (one per GPU the library runs on, held until

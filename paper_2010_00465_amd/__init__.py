@@ -28,7 +28,7 @@ __all__ = ["sincosm", "sincosm_eval", "sincosm_eval_batched", "sincosm_backward"
            "plan_host", "plan_device", "workspace_size", "Plan", "SincosmError", "sincosm_batched",
            "wave_plan_host", "sincosm_wave_eval", "wave", "sincosm_wave_block_eval", "wave_block",
            "sincosm_expi_eval", "expi", "sincosm_eval_planned", "plan_from_device", "PLAN_BYTES",
-           "sincosm_eval_planned_noalloc"]
+           "sincosm_eval_planned_noalloc", "sincosm_eval_async"]
 
 
 def _dtype_code(t: torch.Tensor) -> int:
@@ -139,6 +139,30 @@ def sincosm_eval_planned(A: torch.Tensor, C: torch.Tensor, S: torch.Tensor, plan
     check(lib.sincosm_eval_planned(n, dt, A.data_ptr(), _ld(A), C.data_ptr(), _ld(C), S.data_ptr(), _ld(S),
                                    _acc(accuracy, extended), PROD[products], ctypes.byref(p), ws.data_ptr(),
                                    ws.numel(), pd, _stream(A)), "sincosm_eval_planned")
+
+
+def sincosm_eval_async(A: torch.Tensor, C: torch.Tensor, S: torch.Tensor, s_max: int = 16,
+                       accuracy: str = "double", products: str = "native", ws: torch.Tensor | None = None,
+                       plan_dev: torch.Tensor | None = None, extended: bool = False) -> None:
+    """C-ABI sincosm_eval_async: cos and sin with the plan decided on the device. Only
+    enqueues work on the current stream (no read-back; graph-capturable when ``ws`` and
+    ``plan_dev`` are given). ``s_max`` bounds the double-angle steps enqueued (the double
+    table's plan needs s <= s_max for ||A||_1 <= 1.8548 * 2^s_max); beyond it, and for
+    non-finite A, C and S become NaN and the plan record's status says why."""
+    _require_cuda(A, C, S)
+    n = A.shape[0]
+    dt = _dtype_code(A)
+    if ws is None:
+        ws = _workspace(workspace_size(n, A.dtype, accuracy, products), A.device)
+    pd = None
+    if plan_dev is not None:
+        _require_cuda(plan_dev)
+        if plan_dev.numel() * plan_dev.element_size() < PLAN_BYTES:
+            raise ValueError("plan_dev holds fewer than PLAN_BYTES bytes")
+        pd = plan_dev.data_ptr()
+    check(lib.sincosm_eval_async(n, dt, A.data_ptr(), _ld(A), C.data_ptr(), _ld(C), S.data_ptr(), _ld(S),
+                                 _acc(accuracy, extended), PROD[products], int(s_max), ws.data_ptr(),
+                                 ws.numel(), pd, _stream(A)), "sincosm_eval_async")
 
 
 def sincosm_eval_planned_noalloc(A: torch.Tensor, C: torch.Tensor, S: torch.Tensor, plan,

@@ -21,6 +21,7 @@ E_NONFINITE = -4
 E_HIP = -5
 E_PLAN = -6
 E_TOO_LARGE = -7
+E_SCALING = -8
 NOALLOC_SCRATCH_BYTES = 32 << 20   # SINCOSM_NOALLOC_SCRATCH_BYTES
 
 F64, F32 = 0, 1
@@ -61,6 +62,8 @@ SYMBOLS = {
     "sincosm_eval": (_int, [_i64, _int, _vp, _i64, _vp, _i64, _vp, _i64, _int, _int, _vp, _sz, _PlanP, _vp]),
     "sincosm_eval_planned": (_int, [_i64, _int, _vp, _i64, _vp, _i64, _vp, _i64, _int, _int, _PlanP, _vp, _sz,
                                     _vp, _vp]),
+    "sincosm_eval_async": (_int, [_i64, _int, _vp, _i64, _vp, _i64, _vp, _i64, _int, _int, _i32, _vp, _sz, _vp,
+                                  _vp]),
     "sincosm_eval_planned_noalloc": (_int, [_i64, _int, _vp, _i64, _vp, _i64, _vp, _i64, _int, _int, _PlanP,
                                             _vp, _vp]),
     "sincosm_wave_plan_host": (_int, [_dbl, _int, _PlanP]),

@@ -152,11 +152,59 @@ struct Problem {
   EpiOut out[MAX_OUT];
 };
 
+// Operand scale resolved on the device to 2^-s of the launch's plan record
+// (a value no launch uses as a scale: scales are signed powers of two).
+constexpr double SCALE_2_POW_MINUS_S = 3.0;
+
+// A launch decided on the device by a plan record that an earlier kernel of
+// the stream wrote (plan == nullptr: the launch always runs). Every workgroup
+// returns at once when the record's status is not SINCOSM_OK, when level > 0
+// and the record's level differs, or when step >= 0 and step >= the record's
+// s. With select = 1 the launch's problems are alternatives for different
+// levels: the grid covers the tiles of one problem, and it computes the
+// problem q whose prob_level[q] is the record's level (none: nothing).
+// Operand scales equal to SCALE_2_POW_MINUS_S become 2^-s.
+struct DevCond {
+  const sincosm_plan* plan;
+  int32_t level;
+  int32_t step;
+  int32_t select;
+  int32_t prob_level[MAX_PROB];
+};
+
 struct GemmLaunch {
   int32_t np;        // padded order (multiple of the tile); M = N = K = np per segment
   int32_t nprob;
   Problem prob[MAX_PROB];
+  DevCond cond;
 };
+
+// Decision of a device-planned launch, taken by every workgroup at its start
+// (uniform scalar loads of the plan record). Returns false when the launch
+// does not apply; s and level receive the record's s and level.
+__device__ inline bool cond_applies(const DevCond& c, int& s, int& level) {
+  const int status = c.plan->status, ps = c.plan->s;
+  level = c.plan->level;
+  s = ps;
+  if (status != SINCOSM_OK) return false;
+  if (c.level > 0 && level != c.level) return false;
+  if (c.step >= 0 && c.step >= ps) return false;
+  return true;
+}
+
+// The launch's problem index and tile of this workgroup. A select launch
+// (see DevCond) has the tiles of one problem and takes the problem of the
+// plan's level (-1: none applies).
+__device__ inline int cond_problem(const DevCond& c, int nprob, int level) {
+  for (int q = 0; q < nprob; ++q)
+    if (c.prob_level[q] == level) return q;
+  return -1;
+}
+
+// An operand scale of a launch, with the device-resolved 2^-s substituted.
+__host__ __device__ inline double resolve_scale(double v, int s) {
+  return v == SCALE_2_POW_MINUS_S ? ldexp(1.0, -s) : v;
+}
 
 // Product arithmetic of one GEMM launch.
 enum class Arith { F64, F32, BF16X3 };
@@ -203,10 +251,12 @@ NormScratch norm_scratch(void* base, int64_t np);
 // each element multiplied by `pre` in float64) and the zero-padded copy
 // Ap = pre * A (np x np, type dst_f64 ? double : float); then the plan:
 // mode 0 the cos/sin rule, mode 1 the wave rule (pre = t^2, so the norm is ||B||_1).
+// s_max >= 0 (device-planned calls): the plan's status becomes SINCOSM_E_SCALING
+// when s > s_max; plan_dev (nullable) receives a copy of the plan record.
 sincosm_status launch_norm_copy_plan(int64_t n, int64_t np, const void* A, int64_t lda, bool src_f64,
                                      void* Ap, bool dst_f64, int acc,
                                      const NormScratch& ns, hipStream_t stream, int mode = 0,
-                                     double pre = 1.0);
+                                     double pre = 1.0, int s_max = -1, sincosm_plan* plan_dev = nullptr);
 // dst (np x np, zero padded) = src^T for an n x n src.
 // 1-norm of the np x np padded Y (its n x n part) into the second max slot, then
 // the refined plan: theta' = min(||A||_1, ||Y||_1^(1/2)) when both are finite
@@ -222,6 +272,11 @@ sincosm_status launch_fill_nan(int64_t n, void* X, int64_t ld, bool f64, hipStre
 // given, to plan_dev; status SINCOSM_E_PLAN when ||A||_1 2^-s > theta_level.
 sincosm_status launch_check_plan(int acc, int level, int s, const NormScratch& ns, sincosm_plan* plan_dev,
                                  hipStream_t stream);
+// Device-planned calls: copy the n x n result pair from the ping-pong buffers
+// (np x np, the storage type) that hold it for the record's s into C and S,
+// or fill C and S with NaN when the record's status is not SINCOSM_OK.
+sincosm_status launch_copy_result(const sincosm_plan* plan, int64_t n, int64_t np, void* const q[4], void* C,
+                                  int64_t ldc, void* S, int64_t lds, bool f64, hipStream_t stream);
 // Fill the n x n matrix X with NaN if the plan record at `plan` has a status
 // other than SINCOSM_OK (decided on the device).
 sincosm_status launch_fill_nan_if(const sincosm_plan* plan, int64_t n, void* X, int64_t ld, bool f64,

@@ -118,7 +118,12 @@ __device__ inline void tile_coords(int np, int BM, int BN, int nprob, int& p, in
 // buffer (k+1)&1 in step k+1 start after B_k. With two k groups this holds
 // for each group's own pair of buffers, k counting that group's steps; the
 // groups take equally many steps and share the barriers.
-template <typename T, int BM, int BN, int BK, int WGM, int WGN, int WPE, int DL, int KS>
+//
+// COND: the launch is decided on the device (DevCond): every workgroup first
+// reads the plan record and returns when the launch does not apply; operand
+// scales marked SCALE_2_POW_MINUS_S take the record's 2^-s. Launches without
+// a device plan use the COND = false kernels, which carry none of this.
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int WPE, int DL, int KS, bool COND>
 __global__ __launch_bounds__(WGM * WGN * KS * 64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void gemm_kernel(const GemmLaunch g) {
   using M = Mma<T>;
@@ -175,9 +180,20 @@ void gemm_kernel(const GemmLaunch g) {
   T* const As0 = smem + grp * GROUP_ELEMS;
   T* const Bs0 = As0 + 2 * BM * LDA;
 
+  int dyn_s = 0, dyn_level = 0;
+  if constexpr (COND) {
+    if (!cond_applies(g.cond, dyn_s, dyn_level)) return;   // uniform: the whole workgroup leaves
+  }
+
   const int np = g.np;
   int p, tile_m, tile_n;
-  tile_coords(np, BM, BN, g.nprob, p, tile_m, tile_n);
+  if (COND && g.cond.select) {
+    tile_coords(np, BM, BN, 1, p, tile_m, tile_n);
+    p = cond_problem(g.cond, g.nprob, dyn_level);
+    if (p < 0) return;
+  } else {
+    tile_coords(np, BM, BN, g.nprob, p, tile_m, tile_n);
+  }
   const Problem& P = g.prob[p];
 
   acc_t acc[FM][FN];
@@ -244,8 +260,8 @@ void gemm_kernel(const GemmLaunch g) {
     const int si = s < nseg ? s : 0;
     segL[s] = (const T*)P.seg[si].L + a_tile;
     segR[s] = (const T*)P.seg[si].R + b_tile;
-    segl[s] = (T)P.seg[si].lscale;
-    segr[s] = (T)P.seg[si].rscale;
+    segl[s] = (T)(COND ? resolve_scale(P.seg[si].lscale, dyn_s) : P.seg[si].lscale);
+    segr[s] = (T)(COND ? resolve_scale(P.seg[si].rscale, dyn_s) : P.seg[si].rscale);
   }
   auto pick = [](auto a0, auto a1, auto a2, int s) { return s == 0 ? a0 : (s == 1 ? a1 : a2); };
 
@@ -485,24 +501,32 @@ int choose_tile(Arith ar, int64_t n) {
   return 2;
 }
 
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int WPE, int DL, int KS, bool COND>
+static void launch_variant(const GemmLaunch& g, bool scaled, int tiles, hipStream_t stream) {
+  if constexpr (DL != 0) {
+    if (scaled)
+      gemm_kernel<T, BM, BN, BK, WGM, WGN, WPE, 2, KS, COND><<<tiles, WGM * WGN * KS * 64, 0, stream>>>(g);
+    else
+      gemm_kernel<T, BM, BN, BK, WGM, WGN, WPE, 1, KS, COND><<<tiles, WGM * WGN * KS * 64, 0, stream>>>(g);
+  } else {
+    (void)scaled;
+    gemm_kernel<T, BM, BN, BK, WGM, WGN, WPE, 0, KS, COND><<<tiles, WGM * WGN * KS * 64, 0, stream>>>(g);
+  }
+}
+
 template <typename T, int BM, int BN, int BK, int WGM, int WGN, int WPE, int DL, int KS>
 static sincosm_status launch_cfg(const GemmLaunch& g, hipStream_t stream) {
-  const int tiles = (g.np / BM) * (g.np / BN) * g.nprob;
+  const int tiles = (g.np / BM) * (g.np / BN) * (g.cond.plan && g.cond.select ? 1 : g.nprob);
   if (tiles <= 0) return SINCOSM_OK;
   if ((g.np / BK) % KS != 0) return SINCOSM_E_ARG;   // k groups need a step count divisible by KS
   bool scaled = false;
   for (int p = 0; p < g.nprob; ++p)
     for (int s = 0; s < g.prob[p].nseg; ++s)
       scaled |= g.prob[p].seg[s].lscale != 1.0 || g.prob[p].seg[s].rscale != 1.0;
-  if constexpr (DL != 0) {
-    if (scaled)
-      gemm_kernel<T, BM, BN, BK, WGM, WGN, WPE, 2, KS><<<tiles, WGM * WGN * KS * 64, 0, stream>>>(g);
-    else
-      gemm_kernel<T, BM, BN, BK, WGM, WGN, WPE, 1, KS><<<tiles, WGM * WGN * KS * 64, 0, stream>>>(g);
-  } else {
-    (void)scaled;
-    gemm_kernel<T, BM, BN, BK, WGM, WGN, WPE, 0, KS><<<tiles, WGM * WGN * KS * 64, 0, stream>>>(g);
-  }
+  if (g.cond.plan)
+    launch_variant<T, BM, BN, BK, WGM, WGN, WPE, DL, KS, true>(g, scaled, tiles, stream);
+  else
+    launch_variant<T, BM, BN, BK, WGM, WGN, WPE, DL, KS, false>(g, scaled, tiles, stream);
   SC_HIP(hipGetLastError());
   return SINCOSM_OK;
 }
@@ -552,6 +576,7 @@ const KernelCfg* cfg_table(Arith ar, int& count) {
 // Launch class of a product launch for the tuning table: 0 one problem with at
 // most one k-segment, 1 several problems of equal k-work, 2 the rest.
 static int launch_class(const GemmLaunch& g) {
+  if (g.cond.plan && g.cond.select) return 0;   // one of the problems runs, each a single product
   if (g.nprob <= 1) return g.prob[0].nseg <= 1 ? 0 : 2;
   for (int p = 1; p < g.nprob; ++p)
     if (g.prob[p].nseg != g.prob[0].nseg) return 2;

@@ -71,7 +71,9 @@ __device__ inline void tile_coords_b(int np, int BM, int BN, int nprob, int& p, 
 
 // SCALED: some k-segment carries an operand scale other than 1 (otherwise
 // the split skips the multiplications).
-template <int BM, int BN, int WGM, int WGN, int WPE, bool SCALED>
+// COND: the launch is decided on the device (DevCond), as in the FP64/FP32
+// product kernel; COND = false kernels carry none of it.
+template <int BM, int BN, int WGM, int WGN, int WPE, bool SCALED, bool COND>
 __global__ __launch_bounds__(WGM * WGN * 64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void gemm_bf16x3_kernel(const GemmLaunch g) {
   constexpr int NT = WGM * WGN * 64;
@@ -93,9 +95,20 @@ void gemm_bf16x3_kernel(const GemmLaunch g) {
   __shared__ __attribute__((aligned(16))) unsigned char smem_raw[SMEM_BYTES];
   unsigned short* const sm = (unsigned short*)smem_raw;
 
+  int dyn_s = 0, dyn_level = 0;
+  if constexpr (COND) {
+    if (!cond_applies(g.cond, dyn_s, dyn_level)) return;   // uniform: the whole workgroup leaves
+  }
+
   const int np = g.np;
   int p, tile_m, tile_n;
-  tile_coords_b(np, BM, BN, g.nprob, p, tile_m, tile_n);
+  if (COND && g.cond.select) {
+    tile_coords_b(np, BM, BN, 1, p, tile_m, tile_n);
+    p = cond_problem(g.cond, g.nprob, dyn_level);
+    if (p < 0) return;
+  } else {
+    tile_coords_b(np, BM, BN, g.nprob, p, tile_m, tile_n);
+  }
   const Problem& P = g.prob[p];
 
   const int tid = threadIdx.x;
@@ -146,7 +159,8 @@ void gemm_bf16x3_kernel(const GemmLaunch g) {
 
   auto lstore = [&](int buf, int kt) {
     const Seg& S = P.seg[kt / nk];
-    const float ls = SCALED ? (float)S.lscale : 1.f, rs = SCALED ? (float)S.rscale : 1.f;
+    const float ls = SCALED ? (float)(COND ? resolve_scale(S.lscale, dyn_s) : S.lscale) : 1.f;
+    const float rs = SCALED ? (float)(COND ? resolve_scale(S.rscale, dyn_s) : S.rscale) : 1.f;
     unsigned short* ahi = sm + buf * BUF;
     unsigned short* alo = ahi + PLANE_A;
     unsigned short* bhi = alo + PLANE_A;
@@ -211,16 +225,21 @@ void gemm_bf16x3_kernel(const GemmLaunch g) {
 
 template <int BM, int BN, int WGM, int WGN, int WPE>
 static sincosm_status launch_b(const GemmLaunch& g, hipStream_t stream) {
-  const int tiles = (g.np / BM) * (g.np / BN) * g.nprob;
+  const int tiles = (g.np / BM) * (g.np / BN) * (g.cond.plan && g.cond.select ? 1 : g.nprob);
   if (tiles <= 0) return SINCOSM_OK;
   bool scaled = false;
   for (int p = 0; p < g.nprob; ++p)
     for (int s = 0; s < g.prob[p].nseg; ++s)
       scaled |= g.prob[p].seg[s].lscale != 1.0 || g.prob[p].seg[s].rscale != 1.0;
-  if (scaled)
-    gemm_bf16x3_kernel<BM, BN, WGM, WGN, WPE, true><<<tiles, WGM * WGN * 64, 0, stream>>>(g);
+  const bool cond = g.cond.plan != nullptr;
+  if (scaled && cond)
+    gemm_bf16x3_kernel<BM, BN, WGM, WGN, WPE, true, true><<<tiles, WGM * WGN * 64, 0, stream>>>(g);
+  else if (scaled)
+    gemm_bf16x3_kernel<BM, BN, WGM, WGN, WPE, true, false><<<tiles, WGM * WGN * 64, 0, stream>>>(g);
+  else if (cond)
+    gemm_bf16x3_kernel<BM, BN, WGM, WGN, WPE, false, true><<<tiles, WGM * WGN * 64, 0, stream>>>(g);
   else
-    gemm_bf16x3_kernel<BM, BN, WGM, WGN, WPE, false><<<tiles, WGM * WGN * 64, 0, stream>>>(g);
+    gemm_bf16x3_kernel<BM, BN, WGM, WGN, WPE, false, false><<<tiles, WGM * WGN * 64, 0, stream>>>(g);
   SC_HIP(hipGetLastError());
   return SINCOSM_OK;
 }

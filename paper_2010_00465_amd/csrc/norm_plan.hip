@@ -11,7 +11,7 @@
 //            over columns is taken with an integer atomicMax on the float64
 //            bit pattern (order-independent, so still deterministic; NaN and
 //            Inf patterns compare above every finite value);
-//   stage 3: one thread applies the plan rule.
+//   stage 3: the block of stage 2 that finishes last applies the plan rule.
 #include "common.hpp"
 
 namespace sc {
@@ -36,22 +36,41 @@ NormScratch norm_scratch(void* base, int64_t np) {
   return s;
 }
 
+// counter (nullable): the block count of the fused stage 2 + 3 kernel, reset here.
 template <typename TS, typename TD>
 __global__ __launch_bounds__(NORM_COLS) void norm_copy_kernel(int64_t n, int64_t np, const TS* __restrict__ A,
                                                              int64_t lda, double pre, TD* __restrict__ Ap,
                                                              double* __restrict__ partial,
-                                                             unsigned long long* maxbits) {
+                                                             unsigned long long* maxbits,
+                                                             unsigned int* counter = nullptr) {
   const int64_t j = (int64_t)blockIdx.x * NORM_COLS + threadIdx.x;
   const int64_t i0 = (int64_t)blockIdx.y * NORM_ROWS;
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *maxbits = 0ull;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    *maxbits = 0ull;
+    if (counter) *counter = 0u;
+  }
   if (j >= np) return;
   double sum = 0.0;
   const int64_t i1 = i0 + NORM_ROWS < np ? i0 + NORM_ROWS : np;
-  for (int64_t i = i0; i < i1; ++i) {
-    double v = 0.0;
-    if (i < n && j < n) v = (double)A[i * lda + j] * pre;
-    if (Ap) Ap[i * np + j] = (TD)v;
-    sum += fabs(v);
+  // rows in groups of U: the group's loads are issued together (two memory
+  // round trips per chunk), then added in row order (the same sum as one row
+  // at a time)
+  constexpr int U = NORM_ROWS / 2;
+  for (int64_t ib = i0; ib < i1; ib += U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = ib + u;
+      v[u] = (i < i1 && i < n && j < n) ? (double)A[i * lda + j] * pre : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = ib + u;
+      if (i < i1) {
+        if (Ap) Ap[i * np + j] = (TD)v[u];
+        sum += fabs(v[u]);
+      }
+    }
   }
   partial[(int64_t)blockIdx.y * np + j] = sum;
 }
@@ -63,8 +82,16 @@ __global__ __launch_bounds__(NORM_COLS) void norm_reduce_kernel(int64_t np, int 
   const int64_t j = (int64_t)blockIdx.x * NORM_COLS + threadIdx.x;
   unsigned long long bits = 0ull;
   if (j < np) {
+    // chunk partials in chunk order, loads issued in groups of 8
     double s = 0.0;
-    for (int c = 0; c < nchunks; ++c) s += partial[(int64_t)c * np + j];
+    for (int c0 = 0; c0 < nchunks; c0 += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = c0 + u < nchunks ? partial[(int64_t)(c0 + u) * np + j] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (c0 + u < nchunks) s += v[u];
+    }
     bits = (unsigned long long)__double_as_longlong(s);
   }
   red[threadIdx.x] = bits;
@@ -79,14 +106,57 @@ __global__ __launch_bounds__(NORM_COLS) void norm_reduce_kernel(int64_t np, int 
   if (threadIdx.x == 0) atomicMax(maxbits, red[0]);
 }
 
-// mode 0: plan of the cos/sin schemes; mode 1: plan of the wave schemes (norm of B = t^2 A)
-__global__ void plan_kernel(const unsigned long long* maxbits, int acc, int mode, sincosm_plan* plan) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const double nrm = __longlong_as_double((long long)*maxbits);
+// Stages 2 and 3 in one launch: the column sums and their maximum as in
+// norm_reduce_kernel; the block that finishes last (a device-scope counter,
+// reset by norm_copy_kernel) reads the maximum and applies the plan rule as
+// plan_kernel does.
+__global__ __launch_bounds__(NORM_COLS) void norm_reduce_plan_kernel(int64_t np, int nchunks,
+                                                                    const double* __restrict__ partial,
+                                                                    unsigned long long* maxbits,
+                                                                    unsigned int* counter, int acc, int mode,
+                                                                    sincosm_plan* plan, int s_max,
+                                                                    sincosm_plan* plan_dev) {
+  __shared__ unsigned long long red[NORM_COLS];
+  __shared__ int last;
+  const int64_t j = (int64_t)blockIdx.x * NORM_COLS + threadIdx.x;
+  unsigned long long bits = 0ull;
+  if (j < np) {
+    // chunk partials in chunk order, loads issued in groups of 8
+    double s = 0.0;
+    for (int c0 = 0; c0 < nchunks; c0 += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = c0 + u < nchunks ? partial[(int64_t)(c0 + u) * np + j] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (c0 + u < nchunks) s += v[u];
+    }
+    bits = (unsigned long long)__double_as_longlong(s);
+  }
+  red[threadIdx.x] = bits;
+  __syncthreads();
+  for (int w = NORM_COLS / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      const unsigned long long o = red[threadIdx.x + w];
+      if (o > red[threadIdx.x]) red[threadIdx.x] = o;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicMax(maxbits, red[0]);
+    __threadfence();
+    last = atomicAdd(counter, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last || threadIdx.x != 0) return;
+  __threadfence();
+  const double nrm = __longlong_as_double((long long)atomicMax(maxbits, 0ull));   // the final maximum
   sincosm_plan p;
   if (mode == 1) plan_rule_wave(nrm, acc, &p);
   else plan_rule(nrm, acc, &p);
+  if (s_max >= 0 && p.status == SINCOSM_OK && p.s > s_max) p.status = SINCOSM_E_SCALING;
   *plan = p;
+  if (plan_dev) *plan_dev = p;
 }
 
 __global__ void plan_sq_kernel(const unsigned long long* maxbits, int acc, sincosm_plan* plan) {
@@ -127,22 +197,27 @@ sincosm_status launch_norm_sq_plan(int64_t n, int64_t np, const void* Y, bool y_
 
 template <typename TS, typename TD>
 static void launch_norm_t(int64_t n, int64_t np, const void* A, int64_t lda, void* Ap, const NormScratch& ns,
-                          int acc, int mode, double pre, hipStream_t stream) {
+                          int acc, int mode, double pre, int s_max, sincosm_plan* plan_dev, hipStream_t stream) {
+  unsigned int* counter = (unsigned int*)(ns.maxbits + 2);
   dim3 g1((unsigned)((np + NORM_COLS - 1) / NORM_COLS), (unsigned)ns.nchunks);
   norm_copy_kernel<TS, TD><<<g1, NORM_COLS, 0, stream>>>(n, np, (const TS*)A, lda, pre, (TD*)Ap,
-                                                         ns.partial, ns.maxbits);
+                                                         ns.partial, ns.maxbits, counter);
   dim3 g2((unsigned)((np + NORM_COLS - 1) / NORM_COLS));
-  norm_reduce_kernel<<<g2, NORM_COLS, 0, stream>>>(np, ns.nchunks, ns.partial, ns.maxbits);
-  plan_kernel<<<1, 64, 0, stream>>>(ns.maxbits, acc, mode, ns.plan);
+  norm_reduce_plan_kernel<<<g2, NORM_COLS, 0, stream>>>(np, ns.nchunks, ns.partial, ns.maxbits, counter, acc,
+                                                        mode, ns.plan, s_max, plan_dev);
 }
 
 sincosm_status launch_norm_copy_plan(int64_t n, int64_t np, const void* A, int64_t lda, bool src_f64, void* Ap,
                                      bool dst_f64, int acc, const NormScratch& ns, hipStream_t stream, int mode,
-                                     double pre) {
-  if (src_f64 && dst_f64) launch_norm_t<double, double>(n, np, A, lda, Ap, ns, acc, mode, pre, stream);
-  else if (src_f64 && !dst_f64) launch_norm_t<double, float>(n, np, A, lda, Ap, ns, acc, mode, pre, stream);
-  else if (!src_f64 && dst_f64) launch_norm_t<float, double>(n, np, A, lda, Ap, ns, acc, mode, pre, stream);
-  else launch_norm_t<float, float>(n, np, A, lda, Ap, ns, acc, mode, pre, stream);
+                                     double pre, int s_max, sincosm_plan* plan_dev) {
+  if (src_f64 && dst_f64)
+    launch_norm_t<double, double>(n, np, A, lda, Ap, ns, acc, mode, pre, s_max, plan_dev, stream);
+  else if (src_f64 && !dst_f64)
+    launch_norm_t<double, float>(n, np, A, lda, Ap, ns, acc, mode, pre, s_max, plan_dev, stream);
+  else if (!src_f64 && dst_f64)
+    launch_norm_t<float, double>(n, np, A, lda, Ap, ns, acc, mode, pre, s_max, plan_dev, stream);
+  else
+    launch_norm_t<float, float>(n, np, A, lda, Ap, ns, acc, mode, pre, s_max, plan_dev, stream);
   SC_HIP(hipGetLastError());
   return SINCOSM_OK;
 }
@@ -253,6 +328,43 @@ __global__ void check_plan_kernel(const unsigned long long* maxbits, int acc, in
 sincosm_status launch_check_plan(int acc, int level, int s, const NormScratch& ns, sincosm_plan* plan_dev,
                                  hipStream_t stream) {
   check_plan_kernel<<<1, 64, 0, stream>>>(ns.maxbits, acc, level, s, ns.plan, plan_dev);
+  SC_HIP(hipGetLastError());
+  return SINCOSM_OK;
+}
+
+// After s double-angle steps the pair (C, S) sits in (q1, q0) for even s and
+// in (q3, q2) for odd s (the scheme writes (q1, q0), step i writes the other
+// pair of the two). Copies rows of both into the caller's matrices, or fills
+// them with NaN when the plan record's status is not SINCOSM_OK.
+template <typename T>
+__global__ __launch_bounds__(256) void copy_result_kernel(const sincosm_plan* plan, int64_t n, int64_t np,
+                                                          const T* q0, const T* q1, const T* q2, const T* q3,
+                                                          T* C, int64_t ldc, T* S, int64_t lds) {
+  const bool ok = plan->status == SINCOSM_OK;
+  const bool odd = (plan->s & 1) != 0;
+  const T* srcC = odd ? q3 : q1;
+  const T* srcS = odd ? q2 : q0;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = blockIdx.y;
+  if (j < n) {
+    const T nan = (T)__longlong_as_double(0x7ff8000000000000ll);
+    C[i * ldc + j] = ok ? srcC[i * np + j] : nan;
+    S[i * lds + j] = ok ? srcS[i * np + j] : nan;
+  }
+}
+
+sincosm_status launch_copy_result(const sincosm_plan* plan, int64_t n, int64_t np, void* const q[4], void* C,
+                                  int64_t ldc, void* S, int64_t lds, bool f64, hipStream_t stream) {
+  if (n <= 0) return SINCOSM_OK;
+  dim3 g((unsigned)((n + 255) / 256), (unsigned)n);
+  if (f64)
+    copy_result_kernel<double><<<g, 256, 0, stream>>>(plan, n, np, (const double*)q[0], (const double*)q[1],
+                                                      (const double*)q[2], (const double*)q[3], (double*)C, ldc,
+                                                      (double*)S, lds);
+  else
+    copy_result_kernel<float><<<g, 256, 0, stream>>>(plan, n, np, (const float*)q[0], (const float*)q[1],
+                                                     (const float*)q[2], (const float*)q[3], (float*)C, ldc,
+                                                     (float*)S, lds);
   SC_HIP(hipGetLastError());
   return SINCOSM_OK;
 }

@@ -177,12 +177,20 @@ bool overlaps(const void* a, int64_t lda, const void* b, int64_t ldb, int64_t n,
 
 Target internal(void* p, const Modes& m, bool f64) { return Target{p, m.np, (int)m.np, f64}; }
 
-sincosm_status gemm(Run& r, Arith ar, const GemmLaunch& g, int kind) {
+sincosm_status gemm(Run& r, Arith ar, const GemmLaunch& g0, int kind) {
   if (r.rec) {
     if (r.rec->count >= 8) return SINCOSM_E_ARG;
-    r.rec->launches[r.rec->count++] = g;
+    r.rec->launches[r.rec->count++] = g0;
     return SINCOSM_OK;
   }
+  GemmLaunch dg;
+  const GemmLaunch* gp = &g0;
+  if (r.cond.plan) {
+    dg = g0;
+    dg.cond = r.cond;
+    gp = &dg;
+  }
+  const GemmLaunch& g = *gp;
   if (!r.timed) return launch_gemm(ar, r.m->tile, g, r.stream);
   if (kind < 0) kind = g.nprob == 2 ? SINCOSM_TIMING_SQUARING : SINCOSM_TIMING_SCHEME;
   const TimingMark t = timing_begin(kind, r.stream);
@@ -191,8 +199,7 @@ sincosm_status gemm(Run& r, Arith ar, const GemmLaunch& g, int kind) {
   return st;
 }
 
-// G1 of every scheme: Y = (sA)(sA) into W0, unless the caller already placed it there.
-static sincosm_status g1(Run& r, double sx) {
+sincosm_status first_product(Run& r, double sx) {
   if (r.y_ready) return SINCOSM_OK;
   const Modes& m = *r.m;
   Problem p = make_problem((int)r.n);
@@ -206,7 +213,7 @@ sincosm_status scheme3(Run& r, double sx) {
   const int64_t np = m.np;
   const int nv = (int)r.n;
   const bool pf = m.poly_f64;
-  SC_TRY(g1(r, sx));
+  SC_TRY(first_product(r, sx));
   Problem p = make_problem(nv);
   add_seg(p, r.W[0], r.W[0], np);
   add_in(p, r.W[0], np);
@@ -224,7 +231,7 @@ sincosm_status scheme4(Run& r, double sx) {
   const int64_t np = m.np;
   const int nv = (int)r.n;
   const bool pf = m.poly_f64;
-  SC_TRY(g1(r, sx));
+  SC_TRY(first_product(r, sx));
   Problem p = make_problem(nv);
   add_seg(p, r.W[0], r.W[0], np);
   add_in(p, r.W[0], np);
@@ -251,7 +258,7 @@ sincosm_status scheme5(Run& r, double sx) {
   const int64_t np = m.np;
   const int nv = (int)r.n;
   const bool pf = m.poly_f64;
-  SC_TRY(g1(r, sx));
+  SC_TRY(first_product(r, sx));
   Problem p = make_problem(nv);
   add_seg(p, r.W[0], r.W[0], np);
   add_in(p, r.W[0], np);
@@ -285,7 +292,7 @@ sincosm_status scheme6(Run& r, double sx) {
   const Coeffs& k = coeffs();
   const double* x = k.x;   // x[1..8]
   const double* z = k.z6;  // z[0..8]
-  SC_TRY(g1(r, sx));
+  SC_TRY(first_product(r, sx));
   // G2: Y2 = Y Y -> Y2, W = x1 Y + x2 Y2
   Problem p = make_problem(nv);
   add_seg(p, r.W[0], r.W[0], np);
@@ -336,7 +343,7 @@ sincosm_status scheme7(Run& r, double sx) {
   const Coeffs& k = coeffs();
   const double(*a)[5] = k.a;  // a[i][j], i = 0..3, j = 1..4
   const double* z = k.z7;     // z[0..11]
-  SC_TRY(g1(r, sx));
+  SC_TRY(first_product(r, sx));
   // G2: Y2 = Y Y
   Problem p = make_problem(nv);
   add_seg(p, r.W[0], r.W[0], np);

@@ -37,6 +37,7 @@ struct Run {
   Recorder* rec = nullptr;
   bool y_ready = false;   // W0 already holds Y = (2^-s A)^2: the schemes skip their first product
   bool timed = true;      // launch timing may record events (off where nothing may be allocated)
+  DevCond cond{};         // copied into every launch (plan == nullptr: launches always run)
 };
 
 // Launch capture used to build the batched path's stage templates from the
@@ -59,6 +60,8 @@ sincosm_status read_plan(const sincosm_plan* dev, sincosm_plan* host, hipStream_
 bool overlaps(const void* a, int64_t lda, const void* b, int64_t ldb, int64_t n, size_t es);
 Target internal(void* p, const Modes& m, bool f64);
 sincosm_status gemm(Run& r, Arith ar, const GemmLaunch& g, int kind = -1);
+// G1 of every scheme: Y = (sx A)(sx A) into W0 (skipped when r.y_ready).
+sincosm_status first_product(Run& r, double sx);
 sincosm_status scheme3(Run& r, double sx);
 sincosm_status scheme4(Run& r, double sx);
 sincosm_status scheme5(Run& r, double sx);

@@ -40,6 +40,58 @@ sincosm_status enqueue_method(Run& r, const Modes& m, const Layout& L, char* bas
   return SINCOSM_OK;
 }
 
+// The schemes' products after the shared first one, for a plan decided on the
+// device: each scheme's launch sequence is recorded, then the sequences are
+// packed into "slot" launches of up to MAX_PROB alternative problems (one per
+// level, each level's products in increasing slots; levels with more products
+// first, each placed in the earliest slots with room), and every slot is
+// launched with select = 1, so the device computes the problem of the plan's
+// level. Without the extended flag this is 6 launches for the 16 products.
+sincosm_status enqueue_schemes_by_slot(Run& r, int acc) {
+  const int levels[5] = {7, 6, 5, 4, 3};   // most products first
+  const bool extended = (acc & SINCOSM_PLAN_EXTENDED) != 0;
+  Recorder rec[5];
+  constexpr int MAX_SLOTS = 12;
+  GemmLaunch slot[MAX_SLOTS];
+  int fill[MAX_SLOTS] = {0};
+  int nslots = 0;
+  for (int li = 0; li < 5; ++li) {
+    if (levels[li] == 5 && !extended) continue;
+    Run rr = r;
+    rr.rec = &rec[li];
+    SC_TRY(run_scheme(rr, levels[li], SCALE_2_POW_MINUS_S));
+    int next = 0;
+    for (int k = 0; k < rec[li].count; ++k) {
+      const GemmLaunch& g = rec[li].launches[k];
+      if (g.nprob != 1) return SINCOSM_E_ARG;   // scheme products are single problems
+      while (next < nslots && fill[next] >= MAX_PROB) ++next;
+      if (next == nslots) {
+        if (nslots == MAX_SLOTS) return SINCOSM_E_ARG;
+        memset(&slot[nslots], 0, sizeof(GemmLaunch));
+        slot[nslots].np = g.np;
+        ++nslots;
+      }
+      GemmLaunch& sl = slot[next];
+      sl.prob[fill[next]] = g.prob[0];
+      sl.cond.prob_level[fill[next]] = levels[li];
+      ++fill[next];
+      sl.nprob = fill[next];
+      ++next;
+    }
+  }
+  for (int k = 0; k < nslots; ++k) {
+    DevCond c = r.cond;
+    c.level = 0;
+    c.step = -1;
+    c.select = 1;
+    for (int q = 0; q < MAX_PROB; ++q) c.prob_level[q] = q < fill[k] ? slot[k].cond.prob_level[q] : 0;
+    Run rr = r;
+    rr.cond = c;
+    SC_TRY(gemm(rr, r.m->poly, slot[k]));
+  }
+  return SINCOSM_OK;
+}
+
 // Argument and workspace checks shared by sincosm_eval and sincosm_eval_planned
 // (n > 0, Modes already derived).
 sincosm_status check_eval_args(int64_t n, int dtype, const void* A, int64_t lda, const void* C, int64_t ldc,
@@ -112,6 +164,7 @@ const char* sincosm_strerror(int status) {
     case SINCOSM_E_HIP: return "HIP runtime error";
     case SINCOSM_E_PLAN: return "the given plan does not cover the matrix 1-norm";
     case SINCOSM_E_TOO_LARGE: return "the matrix needs more workspace than the static scratch holds";
+    case SINCOSM_E_SCALING: return "the plan needs more double-angle steps than the call allowed";
     default: return "unknown status";
   }
 }
@@ -215,6 +268,56 @@ sincosm_status sincosm_eval_planned(int64_t n, int dtype, const void* A, int64_t
                                     void* ws, size_t ws_bytes, sincosm_plan* plan_dev, void* stream_) {
   return eval_planned(n, dtype, A, lda, C, ldc, S, lds, acc, prod, plan_in, ws, ws_bytes, plan_dev,
                       (hipStream_t)stream_, true);
+}
+
+sincosm_status sincosm_eval_async(int64_t n, int dtype, const void* A, int64_t lda, void* C, int64_t ldc, void* S,
+                                  int64_t lds, int acc, int prod, int32_t s_max, void* ws, size_t ws_bytes,
+                                  sincosm_plan* plan_dev, void* stream_) {
+  if (n < 0 || n > (1 << 20) || s_max < 0 || s_max > 1100) return SINCOSM_E_ARG;
+  if (!acc_valid(acc, SINCOSM_PLAN_EXTENDED)) return SINCOSM_E_ARG;
+  Modes m;
+  if (!modes_for(n > 0 ? n : 1, dtype, prod, m)) return SINCOSM_E_ARG;
+  if (n == 0) return SINCOSM_OK;
+  SC_TRY(check_eval_args(n, dtype, A, lda, C, ldc, S, lds, m, ws, ws_bytes));
+  const Layout L = layout_for(m);
+  hipStream_t stream = (hipStream_t)stream_;
+  char* base = (char*)ws;
+  const NormScratch ns = norm_scratch(base + L.norm_off, m.np);
+  void* Ap = base + L.ap_off;
+  void* Q[4];
+  for (int i = 0; i < 4; ++i) Q[i] = base + L.q_off[i];
+  Run r;
+  r.m = &m;
+  r.n = n;
+  r.Ap = Ap;
+  for (int i = 0; i < 9; ++i) r.W[i] = base + L.w_off[i];
+  r.stream = stream;
+  SC_TRY(launch_norm_copy_plan(n, m.np, A, lda, m.user_f64, Ap, m.poly_f64, acc, ns, stream, 0, 1.0, s_max,
+                               plan_dev));
+
+  // Every product launch below reads the plan record. The scheme writes (C, S)
+  // to (Q1, Q0) and the double-angle steps ping-pong between (Q1, Q0) and
+  // (Q3, Q2); a copy kernel then moves the pair that the record's s selects
+  // into the caller's C and S (or NaN, for a non-finite A or s > s_max).
+  r.cond.plan = ns.plan;
+  r.cond.level = 0;
+  r.cond.step = -1;
+  r.cond.select = 0;
+  r.Cout = internal(Q[1], m, m.sq_f64);
+  r.Sout = internal(Q[0], m, m.sq_f64);
+  SC_TRY(first_product(r, SCALE_2_POW_MINUS_S));   // shared by every scheme
+  r.y_ready = true;
+  SC_TRY(enqueue_schemes_by_slot(r, acc));
+  r.cond.level = 0;
+  for (int i = 0; i < s_max; ++i) {
+    r.cond.step = i;
+    void* Sc = Q[(i & 1) ? 2 : 0];
+    void* Cc = Q[(i & 1) ? 3 : 1];
+    const Target Sn = internal(Q[(i & 1) ? 0 : 2], m, m.sq_f64);
+    const Target Cn = internal(Q[(i & 1) ? 1 : 3], m, m.sq_f64);
+    SC_TRY(double_angle(r, Sc, Cc, Cn, Sn));
+  }
+  return launch_copy_result(ns.plan, n, m.np, Q, C, ldc, S, lds, m.user_f64, stream);
 }
 
 size_t sincosm_matmul_workspace_size(int64_t n, int dtype, int prod) {

@@ -280,34 +280,40 @@ sincosm_status sincosm_expi_eval(int64_t n, int dtype, const void* A, int64_t ld
                                  sincosm_plan* plan_host, void* stream);
 
 /* Batched evaluation of many independent matrices of uneven orders
- * (1 <= n <= 256), packed row-major with leading dimension n at element
- * offsets offset_host[i] (the same offsets for A, C and S). Two calls:
+ * (1 <= n <= 256), each with its own plan (as sincosm_eval would choose it:
+ * Tables 1-2 on its own 1-norm), packed row-major with leading dimension n.
  *
- * sincosm_batched_prepare - once per batch shape: copies the orders, the
- *   offsets and a longest-first processing order into the workspace (host ->
- *   device copies, then a stream synchronisation). Host arrays are read only
- *   during the call.
- * sincosm_eval_batched    - cos and sin of every matrix, each with its own
- *   plan (as sincosm_eval would choose it). It enqueues a fixed sequence of
- *   two launches (queue reset, persistent kernel) whose shape depends only on
- *   the prepared batch, so it can be captured in a HIP graph and replayed
- *   with new values in A. A matrix with Inf/NaN gets NaN outputs and status
- *   SINCOSM_E_NONFINITE in its plan; the call still returns SINCOSM_OK.
- *
- * ws: sincosm_batched_workspace_size(...) bytes, 256-byte aligned, prepared
- * for exactly this batch; its size does not grow with the batch beyond the
- * 16 bytes of metadata per matrix (each resident workgroup owns one slot of
- * 10 padded matrices). dtype F64 or F32 with prod NATIVE. plans_dev:
- * optional device array of `batch` sincosm_plan.
- * Calls that overlap on one workspace race. */
+ * sincosm_batched_workspace_size - bytes of workspace for `batch` matrices
+ *   whose orders are at most max(n_host[i]) (n_host: host array of the
+ *   orders, read during the call; NULL sizes for any order up to 256). It
+ *   grows with the batch only by 4 bytes per matrix (the work queue): each
+ *   resident workgroup owns one slot of 10 padded matrices. Returns 0 for
+ *   batch <= 0, an order outside 1..256, a bad dtype or prod other than NATIVE.
+ * sincosm_eval_batched - cos and sin of every matrix. n_dev[i] (int32) and
+ *   offset_dev[i] (int64, in elements; the same offsets for A, C and S) are
+ *   DEVICE arrays of `batch` entries; A, C and S hold at least total_elems
+ *   elements each. Everything is checked on the device: an entry whose order
+ *   lies outside 1..256, or whose n x n elements do not lie inside
+ *   [0, total_elems), is skipped with status SINCOSM_E_ARG in its plan record;
+ *   an order beyond the largest one the workspace's slots hold is skipped with
+ *   SINCOSM_E_WORKSPACE; a matrix with Inf/NaN gets NaN outputs and status
+ *   SINCOSM_E_NONFINITE. The call enqueues a fixed sequence of two launches
+ *   (entry checks and the largest-first work queue in one workgroup, then the
+ *   persistent kernel), reads nothing back and returns SINCOSM_OK for any
+ *   entry values, so it can be captured in a HIP graph and replayed with new
+ *   values in A, n_dev and offset_dev.
+ *   ws / ws_bytes: 256-byte aligned; the size query's value for the batch
+ *   (a smaller workspace holds smaller orders only; none at all:
+ *   SINCOSM_E_WORKSPACE). dtype F64 or F32 with prod NATIVE (other products:
+ *   SINCOSM_E_UNSUPPORTED). plans_dev: optional device array of `batch`
+ *   sincosm_plan. Calls that overlap on one workspace race. */
 size_t sincosm_batched_workspace_size(int64_t batch, const int32_t* n_host, int dtype,
                                       int acc, int prod);
-sincosm_status sincosm_batched_prepare(int64_t batch, const int32_t* n_host,
-                                       const int64_t* offset_host, int dtype, void* ws,
-                                       size_t ws_bytes, void* stream);
-sincosm_status sincosm_eval_batched(int64_t batch, int dtype, const void* A, void* C, void* S,
-                                    int acc, int prod, void* ws, size_t ws_bytes,
-                                    sincosm_plan* plans_dev, void* stream);
+sincosm_status sincosm_eval_batched(int64_t batch, int dtype, const int32_t* n_dev,
+                                    const int64_t* offset_dev, int64_t total_elems,
+                                    const void* A, void* C, void* S, int acc, int prod,
+                                    void* ws, size_t ws_bytes, sincosm_plan* plans_dev,
+                                    void* stream);
 
 /* Bytes of workspace sincosm_backward needs for order n and `s` double-angle
  * steps (s from the forward call's plan; the backward rejects a larger s). */

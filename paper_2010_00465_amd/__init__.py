@@ -328,33 +328,53 @@ def sincosm_backward(A: torch.Tensor, Gc: torch.Tensor | None, Gs: torch.Tensor 
 
 
 class BatchedWorkspace:
-    """A workspace prepared for one packed batch (C-ABI sincosm_batched_prepare).
+    """Device metadata and workspace for one packed batch (C-ABI sincosm_eval_batched).
 
-    ``run`` calls sincosm_eval_batched; it enqueues a fixed launch sequence, so
-    it may be captured in a CUDA/HIP graph once the workspace is prepared.
+    ``ns`` and ``offsets`` (host sequences or int32 / int64 GPU tensors) are kept on the
+    device; ``run`` enqueues the batched call's fixed launch sequence (no read-back), so it
+    may be captured in a CUDA/HIP graph. ``nmax`` bounds the orders when ``ns`` is a device
+    tensor (default 256).
     """
 
-    def __init__(self, ns, offsets, dtype=torch.float64, device="cuda", accuracy="double"):
-        self.batch = len(ns)
+    def __init__(self, ns, offsets, dtype=torch.float64, device="cuda", accuracy="double", nmax=None):
         self.dtype = dtype
         self.accuracy = accuracy
         dt = _lib.F64 if dtype == torch.float64 else _lib.F32
-        n_arr = (ctypes.c_int32 * self.batch)(*[int(v) for v in ns])
-        o_arr = (ctypes.c_int64 * self.batch)(*[int(v) for v in offsets])
-        size = lib.sincosm_batched_workspace_size(self.batch, n_arr, dt, ACC[accuracy], PROD["native"])
+        if isinstance(ns, torch.Tensor):
+            self.n_dev = ns.to(device=device, dtype=torch.int32).contiguous()
+            n_host = None
+            self.batch = int(self.n_dev.numel())
+        else:
+            n_list = [int(v) for v in ns]
+            self.batch = len(n_list)
+            self.n_dev = torch.tensor(n_list, dtype=torch.int32, device=device)
+            n_host = n_list if nmax is None else None
+        if isinstance(offsets, torch.Tensor):
+            self.off_dev = offsets.to(device=device, dtype=torch.int64).contiguous()
+        else:
+            self.off_dev = torch.tensor([int(v) for v in offsets], dtype=torch.int64, device=device)
+        if self.off_dev.numel() != self.batch:
+            raise ValueError("ns and offsets differ in length")
+        if n_host is not None:
+            arr = (ctypes.c_int32 * self.batch)(*n_host)
+        elif nmax is not None:
+            arr = (ctypes.c_int32 * self.batch)(*([int(nmax)] * self.batch))
+        else:
+            arr = None
+        size = lib.sincosm_batched_workspace_size(self.batch, arr, dt, ACC[accuracy], PROD["native"])
         if size == 0:
             raise SincosmError(_lib.E_ARG, "sincosm_batched_workspace_size")
         self.ws = _workspace(size, device)
-        stream = torch.cuda.current_stream(self.ws.device).cuda_stream
-        check(lib.sincosm_batched_prepare(self.batch, n_arr, o_arr, dt, self.ws.data_ptr(), self.ws.numel(),
-                                          stream), "sincosm_batched_prepare")
 
     def run(self, A: torch.Tensor, C: torch.Tensor, S: torch.Tensor, plans: torch.Tensor | None = None):
         _require_cuda(A, C, S)
+        if C.numel() < A.numel() or S.numel() < A.numel():
+            raise ValueError("C and S must hold as many elements as A")
         plans_ptr = plans.data_ptr() if plans is not None else None
-        check(lib.sincosm_eval_batched(self.batch, _dtype_code(A), A.data_ptr(), C.data_ptr(), S.data_ptr(),
-                                       ACC[self.accuracy], PROD["native"], self.ws.data_ptr(), self.ws.numel(),
-                                       plans_ptr, _stream(A)), "sincosm_eval_batched")
+        check(lib.sincosm_eval_batched(self.batch, _dtype_code(A), self.n_dev.data_ptr(), self.off_dev.data_ptr(),
+                                       A.numel(), A.data_ptr(), C.data_ptr(), S.data_ptr(), ACC[self.accuracy],
+                                       PROD["native"], self.ws.data_ptr(), self.ws.numel(), plans_ptr, _stream(A)),
+              "sincosm_eval_batched")
 
 
 def plans_from_bytes(buf: torch.Tensor):
@@ -366,7 +386,8 @@ def plans_from_bytes(buf: torch.Tensor):
 def sincosm_eval_batched(ns, offsets, A: torch.Tensor, C: torch.Tensor, S: torch.Tensor,
                          accuracy: str = "double", products: str = "native",
                          plans: torch.Tensor | None = None) -> BatchedWorkspace:
-    """Prepare a workspace for the packed batch (ns, offsets: host int sequences) and run it once."""
+    """Set up the batch's device metadata and workspace (ns, offsets: host sequences or GPU
+    tensors) and run it once."""
     if products != "native":
         raise SincosmError(_lib.E_UNSUPPORTED, "sincosm_eval_batched")
     w = BatchedWorkspace(ns, offsets, A.dtype, A.device, accuracy)

@@ -72,8 +72,7 @@ SYMBOLS = {
     "sincosm_wave_block_eval": (_int, [_i64, _int, _vp, _i64, _dbl, _vp, _i64, _int, _int, _vp, _sz, _PlanP, _vp]),
     "sincosm_expi_eval": (_int, [_i64, _int, _vp, _i64, _dbl, _vp, _i64, _int, _int, _vp, _sz, _PlanP, _vp]),
     "sincosm_batched_workspace_size": (_sz, [_i64, ctypes.POINTER(_i32), _int, _int, _int]),
-    "sincosm_batched_prepare": (_int, [_i64, ctypes.POINTER(_i32), ctypes.POINTER(_i64), _int, _vp, _sz, _vp]),
-    "sincosm_eval_batched": (_int, [_i64, _int, _vp, _vp, _vp, _int, _int, _vp, _sz, _vp, _vp]),
+    "sincosm_eval_batched": (_int, [_i64, _int, _vp, _vp, _i64, _vp, _vp, _vp, _int, _int, _vp, _sz, _vp, _vp]),
     "sincosm_backward_workspace_size": (_sz, [_i64, _int, _int, _i32]),
     "sincosm_backward": (_int, [_i64, _int, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _int, _vp, _sz,
                                 _PlanP, _vp]),

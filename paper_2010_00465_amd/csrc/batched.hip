@@ -1,8 +1,14 @@
 // Batched path: cos and sin of many independent matrices of uneven order
 // (n <= 256) in one persistent launch.
 //
-// Each workgroup repeatedly takes the next matrix from a device work queue
-// (longest first), and runs that matrix's whole method alone: zero-padded
+// The orders and element offsets are device arrays of the caller. A first
+// one-workgroup launch checks every entry (order within 1..256 and within the
+// workspace's slot size, n x n elements inside the packed arrays), reports
+// rejected entries in their plan record, and sorts the accepted ones by
+// padded order into the work queue (largest first; a counting sort, so no
+// host work and nothing read back). Each workgroup of the persistent launch
+// then repeatedly takes the next matrix from the queue, and runs that
+// matrix's whole method alone: zero-padded
 // copy and 1-norm, plan (Tables 1-2), the scheme's products (Section 2.1) and
 // the s double-angle steps (Section 1), each product as a loop over 64 x 64
 // or 32 x 32 output tiles of the workgroup (per padded order, from the
@@ -18,8 +24,6 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
-#include <numeric>
-#include <vector>
 
 #include "schemes.hpp"
 
@@ -58,9 +62,10 @@ struct BatchArgs {
   int batch;
   int acc;
   int8_t tile32[NMAX / 16 + 1];   // per padded order / 16: 1 = 32 x 32 output tiles, 0 = 64 x 64
-  const int32_t* nmat;
-  const int64_t* off;
-  const int32_t* order;
+  const int32_t* nmat;            // caller's orders (device)
+  const int64_t* off;             // caller's element offsets (device)
+  const int32_t* order;           // work queue: accepted entries, largest padded order first
+  const unsigned int* nqueue;     // its length
   const void* A;
   void* C;
   void* S;
@@ -69,6 +74,64 @@ struct BatchArgs {
   int64_t slot_bytes;
   unsigned int* counter;
 };
+
+// Check every entry and build the work queue (one workgroup). An entry is
+// accepted when 1 <= n <= 256, its padded order fits the workspace's slots
+// (npm) and its n x n elements lie inside the packed arrays (0 <= off,
+// off + n^2 <= total); a rejected entry gets status SINCOSM_E_ARG (or
+// SINCOSM_E_WORKSPACE for an order beyond npm) in its plan record and is not
+// computed. Accepted entries are bucketed by padded order, largest first;
+// the order within a bucket does not matter (each matrix is computed by one
+// workgroup the same way wherever it sits in the queue).
+constexpr int ORDER_THREADS = 1024;
+constexpr int NBUCKET = NMAX / 16;
+
+__device__ inline int entry_status(int n, int64_t o, int64_t total, int npm) {
+  if (n < 1 || n > NMAX) return SINCOSM_E_ARG;
+  if (o < 0 || o > total || (int64_t)n * n > total - o) return SINCOSM_E_ARG;
+  if (((n + 15) & ~15) > npm) return SINCOSM_E_WORKSPACE;
+  return SINCOSM_OK;
+}
+
+__global__ __launch_bounds__(ORDER_THREADS) void batched_order_kernel(int batch, const int32_t* nmat,
+                                                                     const int64_t* off, int64_t total, int npm,
+                                                                     int32_t* order, unsigned int* counter,
+                                                                     unsigned int* nqueue, sincosm_plan* plans) {
+  __shared__ unsigned int hist[NBUCKET];
+  __shared__ unsigned int next[NBUCKET];
+  const int tid = threadIdx.x;
+  for (int b = tid; b < NBUCKET; b += ORDER_THREADS) hist[b] = 0u;
+  __syncthreads();
+  for (int i = tid; i < batch; i += ORDER_THREADS) {
+    const int n = nmat[i];
+    const int st = entry_status(n, off[i], total, npm);
+    if (st != SINCOSM_OK) {
+      if (plans) {
+        sincosm_plan p;
+        p.level = 0; p.s = 0; p.products = 0; p.status = st; p.norm1 = 0.0;
+        plans[i] = p;
+      }
+      continue;
+    }
+    atomicAdd(&hist[NBUCKET - ((n + 15) >> 4)], 1u);   // bucket 0: padded order 256
+  }
+  __syncthreads();
+  if (tid == 0) {
+    unsigned int run = 0u;
+    for (int b = 0; b < NBUCKET; ++b) {
+      next[b] = run;
+      run += hist[b];
+    }
+    *nqueue = run;
+    *counter = 0u;
+  }
+  __syncthreads();
+  for (int i = tid; i < batch; i += ORDER_THREADS) {
+    const int n = nmat[i];
+    if (entry_status(n, off[i], total, npm) != SINCOSM_OK) continue;
+    order[atomicAdd(&next[NBUCKET - ((n + 15) >> 4)], 1u)] = i;
+  }
+}
 
 template <typename T>
 struct Vec;
@@ -310,15 +373,16 @@ __global__ __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(3))) void b
   __shared__ sincosm_plan s_plan;
   const int tid = threadIdx.x;
   T* const slot = (T*)(a.arena + (int64_t)blockIdx.x * a.slot_bytes);
+  const int nq = (int)*a.nqueue;
 
   for (;;) {
     if (tid == 0) s_item = (int)atomicAdd(a.counter, 1u);
     __syncthreads();
     const int item = s_item;
     __syncthreads();
-    if (item >= a.batch) break;
+    if (item >= nq) break;
     const int i = a.order[item];
-    if (i < 0 || i >= a.batch) continue;     // metadata not written by the prepare call
+    if (i < 0 || i >= a.batch) continue;     // the queue holds checked entries only
     const int n = a.nmat[i];
     if (n < 1 || n > NMAX) continue;
     const int64_t off = a.off[i];
@@ -445,10 +509,6 @@ __global__ __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(3))) void b
   }
 }
 
-__global__ void reset_counter_kernel(unsigned int* counter) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
-}
-
 // Templates are recorded once per process and copied to each device on first use.
 std::mutex tmpl_mu;
 bool tmpl_built = false;
@@ -504,8 +564,8 @@ sincosm_status ensure_templates(hipStream_t stream) {
 }
 
 struct BatchLayout {
-  size_t counter_off, n_off, off_off, order_off, arena_off, slot_bytes, total;
-  int slots;
+  size_t counter_off, order_off, arena_off, slot_bytes, total;
+  int slots, npm;
 };
 
 int device_cus() {
@@ -515,27 +575,22 @@ int device_cus() {
   return cus;
 }
 
-bool batch_layout(int64_t batch, int nmax, int dtype, BatchLayout& L) {
+// Workspace: the queue counter and length (256 bytes), the work queue, then one
+// arena slot of 10 padded matrices of order npm per resident workgroup.
+bool batch_layout(int64_t batch, int npm, int dtype, BatchLayout& L) {
   const int cus = device_cus();
   if (cus <= 0) return false;
   const size_t es = dtype == SINCOSM_F64 ? 8 : 4;
-  const int npm = (nmax + 15) & ~15;
+  L.npm = npm;
   L.slots = (int)std::min<int64_t>(batch, (int64_t)cus * WG_PER_CU);
   L.slot_bytes = align_up((size_t)10 * npm * npm * es, 256);
   size_t off = 0;
   L.counter_off = off; off += 256;
-  L.n_off = off; off += align_up((size_t)batch * 4, 256);
-  L.off_off = off; off += align_up((size_t)batch * 8, 256);
   L.order_off = off; off += align_up((size_t)batch * 4, 256);
   L.arena_off = off; off += (size_t)L.slots * L.slot_bytes;
   L.total = off;
   return true;
 }
-
-// Host-side record of each prepared workspace (for argument checks).
-struct Prepared { int64_t batch; int dtype; BatchLayout L; };
-std::mutex prep_mu;
-std::map<const void*, Prepared> prepared;
 
 }  // namespace
 }  // namespace sc
@@ -546,83 +601,73 @@ extern "C" {
 
 size_t sincosm_batched_workspace_size(int64_t batch, const int32_t* n_host, int dtype, int acc, int prod) {
   (void)acc;
-  if (batch <= 0 || !n_host || (dtype != SINCOSM_F64 && dtype != SINCOSM_F32) || prod != SINCOSM_PROD_NATIVE)
+  if (batch <= 0 || batch > INT32_MAX || (dtype != SINCOSM_F64 && dtype != SINCOSM_F32) ||
+      prod != SINCOSM_PROD_NATIVE)
     return 0;
-  int nmax = 1;
-  for (int64_t i = 0; i < batch; ++i) {
-    if (n_host[i] < 1 || n_host[i] > NMAX) return 0;
-    nmax = std::max<int>(nmax, n_host[i]);
+  int nmax = NMAX;
+  if (n_host) {
+    nmax = 1;
+    for (int64_t i = 0; i < batch; ++i) {
+      if (n_host[i] < 1 || n_host[i] > NMAX) return 0;
+      nmax = std::max<int>(nmax, n_host[i]);
+    }
   }
   BatchLayout L;
-  if (!batch_layout(batch, nmax, dtype, L)) return 0;
+  if (!batch_layout(batch, (nmax + 15) & ~15, dtype, L)) return 0;
   return L.total;
 }
 
-sincosm_status sincosm_batched_prepare(int64_t batch, const int32_t* n_host, const int64_t* offset_host, int dtype,
-                                       void* ws, size_t ws_bytes, void* stream_) {
-  if (batch <= 0 || !n_host || !offset_host) return SINCOSM_E_ARG;
-  if (dtype != SINCOSM_F64 && dtype != SINCOSM_F32) return SINCOSM_E_ARG;
-  int nmax = 1;
-  for (int64_t i = 0; i < batch; ++i) {
-    if (n_host[i] < 1 || n_host[i] > NMAX || offset_host[i] < 0) return SINCOSM_E_ARG;
-    nmax = std::max<int>(nmax, n_host[i]);
-  }
-  BatchLayout L;
-  if (!batch_layout(batch, nmax, dtype, L)) return SINCOSM_E_HIP;
-  if (!ws || ws_bytes < L.total || ((uintptr_t)ws & 255u)) return SINCOSM_E_WORKSPACE;
-  hipStream_t stream = (hipStream_t)stream_;
-  SC_TRY(ensure_templates(stream));
-  // longest first: order by n descending, stable
-  std::vector<int32_t> order((size_t)batch);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return n_host[x] > n_host[y]; });
-  char* base = (char*)ws;
-  SC_HIP(hipMemcpyAsync(base + L.n_off, n_host, (size_t)batch * 4, hipMemcpyHostToDevice, stream));
-  SC_HIP(hipMemcpyAsync(base + L.off_off, offset_host, (size_t)batch * 8, hipMemcpyHostToDevice, stream));
-  SC_HIP(hipMemcpyAsync(base + L.order_off, order.data(), (size_t)batch * 4, hipMemcpyHostToDevice, stream));
-  SC_HIP(hipStreamSynchronize(stream));
-  std::lock_guard<std::mutex> g(prep_mu);
-  prepared[ws] = Prepared{batch, dtype, L};
-  return SINCOSM_OK;
-}
-
-sincosm_status sincosm_eval_batched(int64_t batch, int dtype, const void* A, void* C, void* S, int acc, int prod,
+sincosm_status sincosm_eval_batched(int64_t batch, int dtype, const int32_t* n_dev, const int64_t* offset_dev,
+                                    int64_t total_elems, const void* A, void* C, void* S, int acc, int prod,
                                     void* ws, size_t ws_bytes, sincosm_plan* plans_dev, void* stream_) {
-  if (batch < 0) return SINCOSM_E_ARG;
+  if (batch < 0 || batch > INT32_MAX || total_elems < 0) return SINCOSM_E_ARG;
   if (batch == 0) return SINCOSM_OK;
   if (acc != SINCOSM_ACC_DOUBLE && acc != SINCOSM_ACC_SINGLE) return SINCOSM_E_ARG;
   if (dtype != SINCOSM_F64 && dtype != SINCOSM_F32) return SINCOSM_E_ARG;
   if (prod != SINCOSM_PROD_NATIVE) return SINCOSM_E_UNSUPPORTED;
-  if (!A || !C || !S) return SINCOSM_E_ARG;
-  Prepared pr;
-  {
-    std::lock_guard<std::mutex> g(prep_mu);
-    auto it = prepared.find(ws);
-    if (it == prepared.end()) return SINCOSM_E_WORKSPACE;
-    pr = it->second;
+  if (!n_dev || !offset_dev || !A || !C || !S) return SINCOSM_E_ARG;
+  if (!ws || ((uintptr_t)ws & 255u)) return SINCOSM_E_WORKSPACE;
+  // the largest padded order whose slots fit the workspace (orders above it
+  // are rejected on the device with SINCOSM_E_WORKSPACE)
+  BatchLayout L;
+  int npm = 0;
+  for (int cand = NMAX; cand >= 16; cand -= 16) {
+    BatchLayout t;
+    if (!batch_layout(batch, cand, dtype, t)) return SINCOSM_E_HIP;
+    if (t.total <= ws_bytes) {
+      L = t;
+      npm = cand;
+      break;
+    }
   }
-  if (pr.batch != batch || pr.dtype != dtype || ws_bytes < pr.L.total) return SINCOSM_E_WORKSPACE;
+  if (npm == 0) return SINCOSM_E_WORKSPACE;
   hipStream_t stream = (hipStream_t)stream_;
+  SC_TRY(ensure_templates(stream));
   char* base = (char*)ws;
+  unsigned int* counter = (unsigned int*)(base + L.counter_off);
+  unsigned int* nqueue = counter + 1;
+  int32_t* order = (int32_t*)(base + L.order_off);
   BatchArgs a;
   a.batch = (int)batch;
   a.acc = acc;
-  a.nmat = (const int32_t*)(base + pr.L.n_off);
-  a.off = (const int64_t*)(base + pr.L.off_off);
-  a.order = (const int32_t*)(base + pr.L.order_off);
+  a.nmat = n_dev;
+  a.off = offset_dev;
+  a.order = order;
+  a.nqueue = nqueue;
   a.A = A;
   a.C = C;
   a.S = S;
   a.plans = plans_dev;
-  a.arena = base + pr.L.arena_off;
-  a.slot_bytes = (int64_t)pr.L.slot_bytes;
-  a.counter = (unsigned int*)(base + pr.L.counter_off);
+  a.arena = base + L.arena_off;
+  a.slot_bytes = (int64_t)L.slot_bytes;
+  a.counter = counter;
   for (int b = 0; b <= NMAX / 16; ++b)   // product tile per padded order, from the tuning table
     a.tile32[b] = (int8_t)(batched_tile(dtype == SINCOSM_F64 ? Arith::F64 : Arith::F32, 16 * b) == 32);
   const TimingMark t = timing_begin(SINCOSM_TIMING_BATCHED, stream);
-  reset_counter_kernel<<<1, 64, 0, stream>>>(a.counter);
-  if (dtype == SINCOSM_F64) batched_kernel<double><<<pr.L.slots, BNT, 0, stream>>>(a);
-  else batched_kernel<float><<<pr.L.slots, BNT, 0, stream>>>(a);
+  batched_order_kernel<<<1, ORDER_THREADS, 0, stream>>>((int)batch, n_dev, offset_dev, total_elems, npm, order,
+                                                        counter, nqueue, plans_dev);
+  if (dtype == SINCOSM_F64) batched_kernel<double><<<L.slots, BNT, 0, stream>>>(a);
+  else batched_kernel<float><<<L.slots, BNT, 0, stream>>>(a);
   timing_end(t, stream);
   SC_HIP(hipGetLastError());
   return SINCOSM_OK;

@@ -159,28 +159,31 @@ def test_batched_argument_errors_without_gpu(lib):
     ns = (i32 * 3)(4, 17, 256)
     bad_n = (i32 * 2)(4, 257)
     zero_n = (i32 * 2)(0, 5)
-    offs = (ctypes.c_int64 * 3)(0, 16, 16 + 289)
-    neg_offs = (ctypes.c_int64 * 3)(0, -1, 400)
     lib.sincosm_batched_workspace_size.restype = ctypes.c_size_t
     assert lib.sincosm_batched_workspace_size(0, ns, 0, 0, 0) == 0          # empty batch
     assert lib.sincosm_batched_workspace_size(2, bad_n, 0, 0, 0) == 0       # order above 256
     assert lib.sincosm_batched_workspace_size(2, zero_n, 0, 0, 0) == 0      # order 0
     assert lib.sincosm_batched_workspace_size(3, ns, 7, 0, 0) == 0          # bad dtype
     assert lib.sincosm_batched_workspace_size(3, ns, 0, 0, 2) == 0          # products other than native
-    assert lib.sincosm_batched_workspace_size(3, None, 0, 0, 0) == 0
-    assert lib.sincosm_batched_prepare(0, ns, offs, 0, None, 0, None) == -1
-    assert lib.sincosm_batched_prepare(2, bad_n, offs, 0, None, 0, None) == -1
-    assert lib.sincosm_batched_prepare(3, ns, neg_offs, 0, None, 0, None) == -1
-    assert lib.sincosm_batched_prepare(3, ns, None, 0, None, 0, None) == -1
-    assert lib.sincosm_batched_prepare(3, ns, offs, 5, None, 0, None) == -1
-    # sincosm_eval_batched: an empty batch is a no-op; bad enums and unprepared workspaces fail
-    assert lib.sincosm_eval_batched(0, 0, None, None, None, 0, 0, None, 0, None, None) == 0
-    assert lib.sincosm_eval_batched(-1, 0, None, None, None, 0, 0, None, 0, None, None) == -1
-    buf = ctypes.create_string_buffer(64)
-    p = ctypes.cast(buf, ctypes.c_void_p)
-    assert lib.sincosm_eval_batched(3, 0, p, p, p, 9, 0, p, 64, None, None) == -1      # bad accuracy
-    assert lib.sincosm_eval_batched(3, 0, p, p, p, 0, 2, p, 64, None, None) == -2      # unsupported products
-    assert lib.sincosm_eval_batched(3, 0, p, p, p, 0, 0, p, 64, None, None) == -3      # never prepared
+    # sincosm_eval_batched: an empty batch is a no-op; bad sizes, enums and workspaces fail
+    i64 = ctypes.c_int64
+    call = lib.sincosm_eval_batched
+    call.argtypes = [i64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, i64, ctypes.c_void_p, ctypes.c_void_p,
+                     ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
+                     ctypes.c_void_p, ctypes.c_void_p]
+    buf = ctypes.create_string_buffer(1024)
+    p = ctypes.cast(buf, ctypes.c_void_p).value
+    aligned = (p + 255) // 256 * 256
+    assert call(0, 0, None, None, 0, None, None, None, 0, 0, None, 0, None, None) == 0
+    assert call(-1, 0, p, p, 9, p, p, p, 0, 0, p, 64, None, None) == -1         # negative batch
+    assert call(3, 0, p, p, -1, p, p, p, 0, 0, p, 64, None, None) == -1         # negative extent
+    assert call(3, 0, p, p, 9, p, p, p, 9, 0, p, 64, None, None) == -1          # bad accuracy
+    assert call(3, 5, p, p, 9, p, p, p, 0, 0, p, 64, None, None) == -1          # bad dtype
+    assert call(3, 0, p, p, 9, p, p, p, 0, 2, p, 64, None, None) == -2          # unsupported products
+    assert call(3, 0, None, p, 9, p, p, p, 0, 0, p, 64, None, None) == -1       # missing order array
+    assert call(3, 0, p, None, 9, p, p, p, 0, 0, p, 64, None, None) == -1       # missing offsets
+    assert call(3, 0, p, p, 9, p, p, p, 0, 0, None, 64, None, None) == -3      # no workspace
+    assert call(3, 0, p, p, 9, p, p, p, 0, 0, aligned + 8, 64, None, None) == -3   # misaligned
 
 
 def test_python_host_plan_helpers():

@@ -1,11 +1,13 @@
-"""GPU parity of the batched path (sincosm_batched_prepare + sincosm_eval_batched
-through the C ABI) against the CPU oracle.
+"""GPU parity of the batched path (sincosm_eval_batched with device order and offset
+arrays, through the C ABI) against the CPU oracle.
 
 Bars as for the single-matrix path: relative Frobenius error <= 1e-12 per
 matrix (float64, double accuracy), plan integers equal to the oracle's
 (breakpoint neighbours accepted). Bitwise equality with the single-matrix
 path is not expected (different tiles, different rounding order): parity
 unpinned, checked at 1e-13."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -268,3 +270,73 @@ def test_sincosm_batched_list_helper(env):
         assert C.shape == M.shape and S.shape == M.shape
         assert rel_fro(C.cpu().numpy(), Cr) <= 1e-12 and rel_fro(S.cpu().numpy(), Sr) <= 1e-12
     assert sc.sincosm_batched([]) == ([], [])
+
+
+def test_batched_entry_checks_on_device(env):
+    """Entries are checked on the device: orders outside 1..256 and elements outside the packed
+    arrays are skipped with status E_ARG, an order beyond the workspace's slots with
+    E_WORKSPACE; their outputs stay untouched and every accepted entry matches the oracle."""
+    torch, sc = env
+    from paper_2010_00465_amd import _lib
+    good = [W.gaussian(n, 4.0, key=(140, n)) for n in (20, 40, 64)]
+    ns, offs, flat = pack(good)
+    total = len(flat)
+    big = 100                                    # fits the extent, but not 64-order slots
+    flat = np.concatenate([flat, W.gaussian(big, 4.0, key=(141,)).ravel()])
+    ext = len(flat)
+    entries = [(20, offs[0], 0), (0, 0, -1), (300, 0, -1), (40, -5, -1), (64, ext - 10, -1), (8, ext + 1, -1),
+               (40, offs[1], 0), (big, total, -3), (64, offs[2], 0)]
+    n_dev = torch.tensor([e[0] for e in entries], dtype=torch.int32, device="cuda")
+    o_dev = torch.tensor([int(e[1]) for e in entries], dtype=torch.int64, device="cuda")
+    A = torch.from_numpy(flat).cuda()
+    C = torch.full_like(A, 7.0)
+    S = torch.full_like(A, 7.0)
+    nmax = (ctypes.c_int32 * len(entries))(*([64] * len(entries)))
+    size = _lib.lib.sincosm_batched_workspace_size(len(entries), nmax, _lib.F64, 0, 0)
+    ws = torch.empty(size, dtype=torch.uint8, device="cuda")
+    plans = torch.zeros(len(entries) * sc.PLAN_BYTES, dtype=torch.uint8, device="cuda")
+    st = _lib.lib.sincosm_eval_batched(len(entries), _lib.F64, n_dev.data_ptr(), o_dev.data_ptr(), A.numel(),
+                                       A.data_ptr(), C.data_ptr(), S.data_ptr(), 0, 0, ws.data_ptr(), ws.numel(),
+                                       plans.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    assert st == 0
+    torch.cuda.synchronize()
+    pl = sc.plans_from_bytes(plans)
+    assert [p.status for p in pl] == [e[2] for e in entries]
+    Cn, Sn = C.cpu().numpy(), S.cpu().numpy()
+    for (n, o, want), p in zip(entries, pl):
+        if want == 0:
+            Am = flat[o:o + n * n].reshape(n, n)
+            Cr, Sr = R.sincosm(Am)
+            assert rel_fro(Cn[o:o + n * n].reshape(n, n), Cr) <= 1e-12
+            assert rel_fro(Sn[o:o + n * n].reshape(n, n), Sr) <= 1e-12
+    assert (Cn[total:] == 7.0).all() and (Sn[total:] == 7.0).all()   # the rejected order-100 entry
+
+
+def test_batched_graph_replay_new_metadata(env):
+    """Captured once; replayed after the device order and offset arrays change (matrices moved
+    and resized within the same extent): each replay equals the oracle for the new layout."""
+    torch, sc = env
+    layouts = [[30, 90, 7], [90, 7, 30], [64, 64, 12]]
+    total = max(sum(n * n for n in lay) for lay in layouts)
+    A = torch.zeros(total, dtype=torch.float64, device="cuda")
+    C, S = torch.empty_like(A), torch.empty_like(A)
+    w = sc.BatchedWorkspace(layouts[0], pack([np.zeros((n, n)) for n in layouts[0]])[1], nmax=96)
+    w.run(A, C, S)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        w.run(A, C, S)
+    for k, lay in enumerate(layouts):
+        mats = [W.gaussian(n, 2.0 ** (k + 2), key=(142, n, k)) for n in lay]
+        ns, offs, flat = pack(mats)
+        A.zero_()
+        A[:len(flat)].copy_(torch.from_numpy(flat).cuda())
+        w.n_dev.copy_(torch.tensor(ns, dtype=torch.int32))
+        w.off_dev.copy_(torch.tensor(offs, dtype=torch.int64))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for n, o, Am in zip(ns, offs, mats):
+            Cr, Sr = R.sincosm(Am)
+            assert rel_fro(C[o:o + n * n].view(n, n).cpu().numpy(), Cr) <= 1e-12
+            assert rel_fro(S[o:o + n * n].view(n, n).cpu().numpy(), Sr) <= 1e-12

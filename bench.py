@@ -9,8 +9,13 @@ in device memory before the timed region.
 Printed: one JSON line with evaluations/s, algorithmic TFLOP/s
 ((Pi + 2 s) 2 n^3 per evaluation) against the float64 MFMA peak, the
 roofline of the dominant kernel (the double-angle product launch, timed with
-HIP events on its stream), the relative error of the 2^0 anchor against the
-float64 CPU oracle, and the oracle's own throughput on the host cores.
+HIP events on its stream), the relative errors of the anchors against the
+float64 CPU oracle, and the oracle's own throughput on the host cores (all
+threads, and one thread). Beside the step (unless --no-extras): the mean over
+8 seeded draws of ||A||_1 = 2^e, e ~ U(-4, 10); the float32 single-accuracy
+path on the anchors; the float64 oracle's and the GPU's discrepancy against the
+long-double oracle at n = 256; and the secondary workloads (batched, reverse
+pass, precision tiers, wave pair, propagators, other orders).
 """
 from __future__ import annotations
 
@@ -28,6 +33,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP64_MFMA_PEAK_TFLOPS = 78.6
+FP32_MFMA_PEAK_TFLOPS = 157.3
 N = 4096
 ANCHORS = (-4, 0, 4, 10)
 
@@ -274,16 +280,15 @@ def bench_backward(torch, sc, W):
 
 def bench_tiers(torch, sc, W):
     """n = 4096: 2-D 5-point Laplacian on a 64 x 64 grid scaled to ||A||_1 = 64; each product
-    arithmetic with its plan table: time, and relative error against the all-float64
-    double-accuracy path (itself held to 1e-12 of the CPU oracle by the parity tests)."""
+    arithmetic with its plan table: time and relative error against the float64 CPU oracle; for
+    each lowered tier, the float64 path with the error closest to it from below (matched
+    accuracy: the same or better error)."""
+    from oracle import reference as R
     Anp = W.laplacian_2d(64, 64.0)
     A = torch.from_numpy(Anp).cuda()
-    Cref = torch.empty_like(A)
-    Sref = torch.empty_like(A)
-    sc.sincosm_eval(A, Cref, Sref, "double", "native")
-    Cr, Sr = Cref.cpu().numpy(), Sref.cpu().numpy()
+    Cr, Sr = R.sincosm(Anp)
     out = {"workload": "n=4096 2-D Laplacian (64 x 64 grid), ||A||_1 = 64, float64 storage; errors relative "
-                       "to the float64 double-accuracy result"}
+                       "to the float64 CPU oracle"}
     for name, acc, prod in (("fp64_double", "double", "native"), ("fp64_single_plan", "single", "native"),
                             ("fp32_products", "single", "f32"), ("bf16x3_products", "single", "bf16x3")):
         C = torch.empty_like(A)
@@ -295,7 +300,109 @@ def bench_tiers(torch, sc, W):
         es = float(np.linalg.norm(S.cpu().numpy() - Sr) / np.linalg.norm(Sr))
         out[name] = {"ms": 1e3 * t, "plan": [plan.level, plan.s], "products": plan.products,
                      "rel_err_cos": ec, "rel_err_sin": es}
+    fp64 = [k for k in ("fp64_single_plan", "fp64_double")]
+    for tier in ("fp32_products", "bf16x3_products"):
+        err = max(out[tier]["rel_err_cos"], out[tier]["rel_err_sin"])
+        ok = [k for k in fp64 if max(out[k]["rel_err_cos"], out[k]["rel_err_sin"]) <= err]
+        best = min(ok, key=lambda k: out[k]["ms"]) if ok else None
+        out[tier]["matched_accuracy_fp64"] = None if best is None else {
+            "path": best, "ms": out[best]["ms"], "rel_err": max(out[best]["rel_err_cos"], out[best]["rel_err_sin"]),
+            "speedup_of_tier": out[best]["ms"] / out[tier]["ms"]}
+        out[tier]["meets_single_accuracy_5e-6"] = err <= 5e-6
     return out
+
+
+def bench_draws(torch, sc, W, n, ws):
+    """The n = 4096 float64 Gaussian workload at 8 seeded draws e ~ U(-4, 10), ||A||_1 = 2^e:
+    each evaluation timed on its own after a warm-up; mean throughput over the draws."""
+    exps = W.log_uniform_exponents(8, -4.0, 10.0, key=(2, n, 0, 100))
+    A = torch.empty(n, n, dtype=torch.float64, device="cuda")
+    C, S = torch.empty_like(A), torch.empty_like(A)
+    per, t_sum, f_sum = [], 0.0, 0.0
+    for d, e in enumerate(exps):
+        A.copy_(torch.from_numpy(W.gaussian(n, 2.0 ** float(e), key=(2, n, 0, 1000 + d))))
+        p = sc.sincosm_eval(A, C, S, ws=ws)
+        t = _elapsed(torch, lambda: sc.sincosm_eval(A, C, S, ws=ws), 2)
+        flops = p.products * 2.0 * n ** 3
+        per.append({"log2_norm1": float(e), "plan": [p.level, p.s], "products": p.products, "ms": 1e3 * t,
+                    "tflops_algorithmic": flops / t / 1e12})
+        t_sum += t
+        f_sum += flops
+    return {"workload": f"sincosm_eval of 8 dense n={n} float64 Gaussian matrices, ||A||_1 = 2^e with e drawn "
+                        "uniformly in [-4, 10] (seeded), double-accuracy plan",
+            "evals_per_s": len(exps) / t_sum, "tflops_algorithmic": f_sum / t_sum / 1e12,
+            "pct_fp64_mfma_peak": 100.0 * f_sum / t_sum / 1e12 / FP64_MFMA_PEAK_TFLOPS, "draws": per}
+
+
+def bench_fp32_single(torch, sc, W, n, mats, with_oracle):
+    """Float32 storage with the single-accuracy plan (Table 2) on the four anchor matrices cast
+    to float32: throughput against the FP32 MFMA peak and, when asked, the relative error against
+    the float64 oracle run on the float32 values promoted (the single-accuracy bar is 5e-6)."""
+    from oracle import reference as R
+    A = [torch.from_numpy(m.astype(np.float32)).cuda() for m in mats]
+    C = [torch.empty_like(a) for a in A]
+    S = [torch.empty_like(a) for a in A]
+    ws = torch.empty(sc.workspace_size(n, torch.float32, "single"), dtype=torch.uint8, device="cuda")
+    plans = [sc.sincosm_eval(a, c, s_, "single", ws=ws) for a, c, s_ in zip(A, C, S)]
+
+    def step():
+        for a, c, s_ in zip(A, C, S):
+            sc.sincosm_eval(a, c, s_, "single", ws=ws)
+
+    t = _elapsed(torch, step, 3)
+    flops = sum(p.products for p in plans) * 2.0 * n ** 3
+    out = {"workload": f"sincosm_eval of the four n={n} anchor matrices cast to float32, single-accuracy plan",
+           "evals_per_s": len(A) / t, "tflops_algorithmic": flops / t / 1e12,
+           "pct_fp32_mfma_peak": 100.0 * flops / t / 1e12 / FP32_MFMA_PEAK_TFLOPS,
+           "plans": [[p.level, p.s] for p in plans], "products": [p.products for p in plans]}
+    if with_oracle:
+        errs = {}
+        for e, m, c, s_ in zip(ANCHORS, mats, C, S):
+            Cr, Sr = R.sincosm(m.astype(np.float32).astype(np.float64))
+            errs[f"2^{e}"] = {"cos": float(np.linalg.norm(c.double().cpu().numpy() - Cr) / np.linalg.norm(Cr)),
+                              "sin": float(np.linalg.norm(s_.double().cpu().numpy() - Sr) / np.linalg.norm(Sr))}
+        out["rel_err_vs_oracle"] = errs
+        out["rel_err_max"] = max(max(v.values()) for v in errs.values())
+    return out
+
+
+def oracle_vs_long_double(torch, sc, W, n=256):
+    """The float64 oracle's own discrepancy against the 80-bit long-double oracle (the best
+    available reference for a general matrix), and the GPU's, on the four anchors at order n."""
+    from oracle import reference as R
+    out = {"n": n, "reference": "oracle in 80-bit long double (Taylor m=11 + double angle)", "per_anchor": {}}
+    for e in ANCHORS:
+        A = W.gaussian(n, 2.0 ** e, key=(2, n, 0, e + 10))
+        Cl, Sl = (x.astype(np.float64) for x in R.sincosm_ld(A))
+        Co, So = R.sincosm(A)
+        At = torch.from_numpy(A).cuda()
+        Cg, Sg = torch.empty_like(At), torch.empty_like(At)
+        sc.sincosm_eval(At, Cg, Sg)
+        Cg, Sg = Cg.cpu().numpy(), Sg.cpu().numpy()
+
+        def rel(X, Y):
+            return float(np.linalg.norm(X - Y) / np.linalg.norm(Y))
+
+        out["per_anchor"][f"2^{e}"] = {"fp64_oracle": max(rel(Co, Cl), rel(So, Sl)),
+                                       "gpu": max(rel(Cg, Cl), rel(Sg, Sl)),
+                                       "gpu_vs_fp64_oracle": max(rel(Cg, Co), rel(Sg, So))}
+    return out
+
+
+def cpu_baseline_1core(mat):
+    """The float64 oracle on one thread, on the cheapest anchor (||A||_1 = 2^-4)."""
+    from oracle import reference as R
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover - informational only
+        return None
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        R.sincosm(mat)
+        secs = time.perf_counter() - t0
+    return {"value": 1.0 / secs, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"the ||A||_1 = 2^-4 anchor (n={mat.shape[0]}) once through the float64 oracle on one "
+                      f"host thread, {secs:.1f} s"}
 
 
 def bench_wave(torch, sc, W):
@@ -550,9 +657,15 @@ def main():
                    "sincosm_plan_device")
         plan_ms.append((time.perf_counter() - tp) * 1e3)
 
+    draws = bench_draws(torch, sc, W, n, ws) if (n == N and not args.no_extras) else None
+    fp32 = (bench_fp32_single(torch, sc, W, n, mats, not args.no_cpu_baseline)
+            if (n == N and not args.no_extras) else None)
+
     rel = None
     cpu = None
+    cpu1 = None
     host = None
+    ld = None
     if not args.no_cpu_baseline:
         secs, threads, ref = cpu_baseline(mats)
         rel = {"reference": "float64 CPU oracle (Taylor m=9 + double angle), same inputs",
@@ -568,6 +681,9 @@ def main():
                "sample": f"one whole step (the four n={n} anchor matrices once each) through the float64 "
                          f"oracle on the host, {secs:.1f} s"}
         host = cpu_host(n, products)
+        if not args.no_extras:
+            cpu1 = cpu_baseline_1core(mats[0])
+            ld = oracle_vs_long_double(torch, sc, W)
 
     extras = {}
     if not args.no_extras and n == N:
@@ -610,8 +726,12 @@ def main():
                      "avg_ms": (sq_ms / sq_cnt) if sq_cnt else None},
         "scheme_products": {"launches": sch_cnt, "avg_ms": (sch_ms / sch_cnt) if sch_cnt else None,
                             "tflops": (2.0 * n ** 3 / (sch_ms / sch_cnt / 1e3) / 1e12) if sch_cnt else None},
+        "draws": draws,
         "rel_err": rel,
+        "oracle_vs_long_double": ld,
+        "fp32_single": fp32,
         "cpu_baseline": cpu,
+        "cpu_baseline_1core": cpu1,
         "cpu_host": host,
     }
     out.update(extras)

@@ -422,6 +422,9 @@ def sincosm(A: torch.Tensor, accuracy: str = "double", products: str = "native")
         raise ValueError("square matrix expected")
     A = A.contiguous()
     if A.requires_grad and torch.is_grad_enabled():
+        if A.dtype != torch.float64 or products != "native":
+            # the reverse pass (sincosm_backward) is the float64 adjoint of the float64 products
+            raise TypeError("sincosm: gradients are provided for float64 input with native products only")
         return _SinCosM.apply(A, accuracy, products)
     C = torch.empty_like(A)
     S = torch.empty_like(A)

@@ -42,6 +42,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "schemes.hpp"
 #include "coeffs.hpp"
 
@@ -151,16 +153,38 @@ Layout layout_for(const Modes& m) {
   return L;
 }
 
-// Pinned host slot for the plan read-back (one per host thread, kept for the
-// life of the process).
+// Pinned host slots for the plan read-back: one block of PLAN_SLOTS pairs,
+// allocated on first use and kept for the life of the process (a bounded,
+// one-time allocation); a call holds one slot while it copies and waits. When
+// every slot is held (more concurrent callers than slots) the copy goes
+// through a stack buffer instead (pageable memory: the same result, a staged
+// copy).
+constexpr int PLAN_SLOTS = 64;
+std::mutex plan_slot_mu;
+sincosm_plan* plan_slots = nullptr;
+bool plan_slot_busy[PLAN_SLOTS];
+
 sincosm_status read_plan(const sincosm_plan* dev, sincosm_plan* host, hipStream_t stream, int count) {
-  thread_local sincosm_plan* pinned = nullptr;
   if (count < 1 || count > 2) return SINCOSM_E_ARG;
-  if (!pinned) SC_HIP(hipHostMalloc((void**)&pinned, 2 * sizeof(sincosm_plan), hipHostMallocDefault));
-  SC_HIP(hipMemcpyAsync(pinned, dev, count * sizeof(sincosm_plan), hipMemcpyDeviceToHost, stream));
-  SC_HIP(hipStreamSynchronize(stream));
-  for (int i = 0; i < count; ++i) host[i] = pinned[i];
-  return SINCOSM_OK;
+  int slot = -1;
+  {
+    std::lock_guard<std::mutex> g(plan_slot_mu);
+    if (!plan_slots) SC_HIP(hipHostMalloc((void**)&plan_slots, PLAN_SLOTS * 2 * sizeof(sincosm_plan),
+                                          hipHostMallocDefault));
+    for (int i = 0; i < PLAN_SLOTS && slot < 0; ++i)
+      if (!plan_slot_busy[i]) { plan_slot_busy[i] = true; slot = i; }
+  }
+  sincosm_plan local[2];
+  sincosm_plan* buf = slot >= 0 ? plan_slots + 2 * slot : local;
+  hipError_t e = hipMemcpyAsync(buf, dev, count * sizeof(sincosm_plan), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e == hipSuccess)
+    for (int i = 0; i < count; ++i) host[i] = buf[i];
+  if (slot >= 0) {
+    std::lock_guard<std::mutex> g(plan_slot_mu);
+    plan_slot_busy[slot] = false;
+  }
+  return e == hipSuccess ? SINCOSM_OK : SINCOSM_E_HIP;
 }
 
 bool overlaps(const void* a, int64_t lda, const void* b, int64_t ldb, int64_t n, size_t es) {

@@ -197,3 +197,16 @@ def test_python_host_plan_helpers():
             assert (p.level, p.s, p.products, p.status) == (*P.plan(x, acc), 0)
             q = sc.wave_plan_host(x, acc)
             assert (q.level, q.s, q.products, q.status) == (*Wv.wave_plan(x, acc), 0)
+
+
+def test_autograd_rejects_unsupported_gradients_up_front():
+    """The reverse pass is the float64 adjoint of the float64 products: asking sincosm for a
+    gradient of a float32 input, or with lowered products, fails before any device work."""
+    import torch
+    import paper_2010_00465_amd as sc
+    A32 = torch.zeros(4, 4, dtype=torch.float32, requires_grad=True)
+    with pytest.raises(TypeError):
+        sc.sincosm(A32)
+    A64 = torch.zeros(4, 4, dtype=torch.float64, requires_grad=True)
+    with pytest.raises(TypeError):
+        sc.sincosm(A64, "single", "f32")

@@ -273,9 +273,14 @@ def bench_backward(torch, sc, W):
     sc.sincosm_backward(A, Gc, Gs, gA, s=plan.s, ws=ws)
     t = _elapsed(torch, lambda: sc.sincosm_backward(A, Gc, Gs, gA, s=plan.s, ws=ws), 3)
     prods = 3 * plan.level + 6 * plan.s - 2
+    # the same with the plan decided on the device (no read-back), s_max = 8
+    wsa = torch.empty(sc.lib.sincosm_backward_workspace_size(n, 0, 0, 8), dtype=torch.uint8, device="cuda")
+    sc.sincosm_backward_async(A, Gc, Gs, gA, 8, ws=wsa)
+    ta = _elapsed(torch, lambda: sc.sincosm_backward_async(A, Gc, Gs, gA, 8, ws=wsa), 3)
     return {"workload": f"sincosm_backward, n={n} Gaussian, ||A||_1=128, plan (level {plan.level}, s {plan.s})",
             "ms": 1e3 * t, "products": prods, "tflops_algorithmic": prods * 2.0 * n ** 3 / t / 1e12,
-            "forward_products": plan.products}
+            "forward_products": plan.products,
+            "async_s_max8_ms": 1e3 * ta}
 
 
 def bench_tiers(torch, sc, W):

@@ -316,7 +316,8 @@ sincosm_status sincosm_eval_batched(int64_t batch, int dtype, const int32_t* n_d
                                     void* stream);
 
 /* Bytes of workspace sincosm_backward needs for order n and `s` double-angle
- * steps (s from the forward call's plan; the backward rejects a larger s). */
+ * steps (s from the forward call's plan; the backward rejects a larger s), and
+ * that sincosm_backward_async needs for s_max = s. */
 size_t sincosm_backward_workspace_size(int64_t n, int dtype, int acc, int32_t s);
 
 /* Gradient of L(A) = <Gc, cos A> + <Gs, sin A> (Frobenius inner products)
@@ -332,6 +333,26 @@ sincosm_status sincosm_backward(int64_t n, int dtype, const void* A, int64_t lda
                                 const void* Gc, int64_t ldgc, const void* Gs, int64_t ldgs,
                                 void* gA, int64_t ldga, int acc, void* ws, size_t ws_bytes,
                                 sincosm_plan* plan_host, void* stream);
+
+/* sincosm_backward with the plan decided on the device: the call only enqueues
+ * kernels on `stream` (no read-back, no synchronisation), so it can be captured
+ * in a HIP graph without knowing the plan. The forward recomputation and the
+ * reverse pass run as a fixed launch sequence whose launches read the plan
+ * record and return at once where they do not apply (another level; a
+ * double-angle step beyond the plan's s), as in sincosm_eval_async; the
+ * products computed are those of sincosm_backward, so gA is bitwise the same.
+ *  s_max: 0 <= s_max <= 1100, the largest number of double-angle steps the
+ *  call allows; the workspace must hold
+ *  sincosm_backward_workspace_size(n, dtype, acc, s_max) bytes. A plan with
+ *  s > s_max gives status SINCOSM_E_SCALING and gA filled with NaN.
+ *  plan_dev (device, nullable): receives the plan record once the stream
+ *  reaches it (status SINCOSM_OK, SINCOSM_E_NONFINITE or SINCOSM_E_SCALING;
+ *  gA is NaN for the latter two). Other arguments and the synchronous argument
+ *  errors as sincosm_backward. */
+sincosm_status sincosm_backward_async(int64_t n, int dtype, const void* A, int64_t lda,
+                                      const void* Gc, int64_t ldgc, const void* Gs, int64_t ldgs,
+                                      void* gA, int64_t ldga, int acc, int32_t s_max, void* ws,
+                                      size_t ws_bytes, sincosm_plan* plan_dev, void* stream);
 
 /* Building block exposed for tests and measurement: Z = X Y for n x n
  * matrices with the same kernels and padding sincosm_eval uses

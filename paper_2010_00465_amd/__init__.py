@@ -28,7 +28,7 @@ __all__ = ["sincosm", "sincosm_eval", "sincosm_eval_batched", "sincosm_backward"
            "plan_host", "plan_device", "workspace_size", "Plan", "SincosmError", "sincosm_batched",
            "wave_plan_host", "sincosm_wave_eval", "wave", "sincosm_wave_block_eval", "wave_block",
            "sincosm_expi_eval", "expi", "sincosm_eval_planned", "plan_from_device", "PLAN_BYTES",
-           "sincosm_eval_planned_noalloc", "sincosm_eval_async"]
+           "sincosm_eval_planned_noalloc", "sincosm_eval_async", "sincosm_backward_async"]
 
 
 def _dtype_code(t: torch.Tensor) -> int:
@@ -325,6 +325,31 @@ def sincosm_backward(A: torch.Tensor, Gc: torch.Tensor | None, Gs: torch.Tensor 
                                _ld(gA), ACC[accuracy], ws.data_ptr(), ws.numel(), ctypes.byref(plan),
                                _stream(A)), "sincosm_backward")
     return plan
+
+
+def sincosm_backward_async(A: torch.Tensor, Gc: torch.Tensor | None, Gs: torch.Tensor | None, gA: torch.Tensor,
+                           s_max: int = 16, accuracy: str = "double", ws: torch.Tensor | None = None,
+                           plan_dev: torch.Tensor | None = None) -> None:
+    """C-ABI sincosm_backward_async: gA = d/dA (<Gc, cos A> + <Gs, sin A>) with the plan decided on
+    the device (no read-back; graph-capturable when ``ws`` and ``plan_dev`` are given). ``s_max``
+    bounds the double-angle steps and sizes the workspace; beyond it, and for non-finite A, gA
+    becomes NaN and the plan record's status says why."""
+    _require_cuda(A, Gc, Gs, gA)
+    n = A.shape[0]
+    dt = _dtype_code(A)
+    if ws is None:
+        ws = _workspace(lib.sincosm_backward_workspace_size(n, dt, ACC[accuracy], int(s_max)), A.device)
+    pd = None
+    if plan_dev is not None:
+        _require_cuda(plan_dev)
+        if plan_dev.numel() * plan_dev.element_size() < PLAN_BYTES:
+            raise ValueError("plan_dev holds fewer than PLAN_BYTES bytes")
+        pd = plan_dev.data_ptr()
+    gc_ptr, gc_ld = (Gc.data_ptr(), _ld(Gc)) if Gc is not None else (None, n)
+    gs_ptr, gs_ld = (Gs.data_ptr(), _ld(Gs)) if Gs is not None else (None, n)
+    check(lib.sincosm_backward_async(n, dt, A.data_ptr(), _ld(A), gc_ptr, gc_ld, gs_ptr, gs_ld, gA.data_ptr(),
+                                     _ld(gA), ACC[accuracy], int(s_max), ws.data_ptr(), ws.numel(), pd,
+                                     _stream(A)), "sincosm_backward_async")
 
 
 class BatchedWorkspace:

@@ -76,6 +76,8 @@ SYMBOLS = {
     "sincosm_backward_workspace_size": (_sz, [_i64, _int, _int, _i32]),
     "sincosm_backward": (_int, [_i64, _int, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _int, _vp, _sz,
                                 _PlanP, _vp]),
+    "sincosm_backward_async": (_int, [_i64, _int, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _int, _i32, _vp, _sz,
+                                      _vp, _vp]),
     "sincosm_tune_num_configs": (_int, [_int]),
     "sincosm_tune_config_info": (_int, [_int, _int, ctypes.POINTER(_i32)]),
     "sincosm_tune_set": (_int, [_int, _i64, _i64, _int]),

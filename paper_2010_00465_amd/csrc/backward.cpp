@@ -400,4 +400,106 @@ sincosm_status sincosm_backward(int64_t n, int dtype, const void* A, int64_t lda
   }
 }
 
+sincosm_status sincosm_backward_async(int64_t n, int dtype, const void* A, int64_t lda, const void* Gc,
+                                      int64_t ldgc, const void* Gs, int64_t ldgs, void* gA, int64_t ldga, int acc,
+                                      int32_t s_max, void* ws, size_t ws_bytes, sincosm_plan* plan_dev,
+                                      void* stream_) {
+  if (n < 0 || n > (1 << 20) || s_max < 0 || s_max > 1100) return SINCOSM_E_ARG;
+  if (acc != SINCOSM_ACC_DOUBLE && acc != SINCOSM_ACC_SINGLE) return SINCOSM_E_ARG;
+  if (dtype == SINCOSM_F32) return SINCOSM_E_UNSUPPORTED;
+  if (dtype != SINCOSM_F64) return SINCOSM_E_ARG;
+  if (n == 0) return SINCOSM_OK;
+  if (!A || !gA || lda < n || ldga < n) return SINCOSM_E_ARG;
+  if ((Gc && ldgc < n) || (Gs && ldgs < n)) return SINCOSM_E_ARG;
+  if (overlaps(A, lda, gA, ldga, n, 8) || (Gc && overlaps(Gc, ldgc, gA, ldga, n, 8)) ||
+      (Gs && overlaps(Gs, ldgs, gA, ldga, n, 8)))
+    return SINCOSM_E_ARG;
+  Modes m;
+  if (!modes_for(n, SINCOSM_F64, SINCOSM_PROD_NATIVE, m)) return SINCOSM_E_ARG;
+  const BwdLayout L = bwd_layout(m, s_max);
+  if (!ws || ws_bytes < L.total || ((uintptr_t)ws & 255u)) return SINCOSM_E_WORKSPACE;
+  hipStream_t stream = (hipStream_t)stream_;
+  char* base = (char*)ws;
+
+  // plan of A (not of A^T) on the device, capped at s_max
+  const NormScratch ns = norm_scratch(base + L.norm_off, m.np);
+  SC_TRY(launch_norm_copy_plan(n, m.np, A, lda, true, nullptr, true, acc, ns, stream, 0, 1.0, s_max, plan_dev));
+  void* Bp = base + L.bp_off;
+  SC_TRY(launch_transpose_pad(n, m.np, A, lda, true, Bp, true, stream));
+
+  Run r;
+  r.m = &m;
+  r.n = n;
+  r.Ap = Bp;
+  for (int i = 0; i < 9; ++i) r.W[i] = base + L.w_off[i];
+  r.stream = stream;
+  r.cond.plan = ns.plan;
+  r.cond.level = 0;
+  r.cond.step = -1;
+  r.cond.select = 0;
+  void* Rb[9];
+  for (int i = 0; i < 9; ++i) Rb[i] = base + L.rev_off[i];
+  void* cot[4];
+  for (int i = 0; i < 4; ++i) cot[i] = base + L.cot_off[i];
+  const size_t mat = align_up((size_t)m.np * m.np * 8, 256);
+  auto chainS = [&](int i) -> void* { return base + L.chain_off + mat * (size_t)(2 * i); };
+  auto chainC = [&](int i) -> void* { return base + L.chain_off + mat * (size_t)(2 * i + 1); };
+
+  // forward on B as in sincosm_backward, every launch decided on the device:
+  // the scheme's (C, S) go to the first double-angle inputs (or to scratch when
+  // no step can run), forward step i runs while i + 1 < s
+  if (s_max > 0) {
+    r.Cout = internal(chainC(0), m, true);
+    r.Sout = internal(chainS(0), m, true);
+  } else {
+    r.Cout = internal(Rb[0], m, true);
+    r.Sout = internal(Rb[1], m, true);
+  }
+  SC_TRY(first_product(r, SCALE_2_POW_MINUS_S));
+  r.y_ready = true;
+  SC_TRY(enqueue_schemes_by_slot(r, acc));
+  for (int i = 0; i + 1 < s_max; ++i) {
+    r.cond.step = i + 1;
+    SC_TRY(double_angle(r, chainS(i), chainC(i), internal(chainC(i + 1), m, true),
+                        internal(chainS(i + 1), m, true)));
+  }
+
+  // adjoints of the outputs, zero padded, in pair 0; for odd s they move to
+  // pair 1, where reverse step s - 1 reads them: step i reads pair (i + 1) & 1
+  // and writes pair i & 1, so the scheme's adjoints end in pair 0 for every s
+  if (Gc) SC_TRY(launch_convert_pad(n, m.np, Gc, ldgc, true, cot[0], true, stream));
+  else SC_TRY(launch_fill_zero(m.np, cot[0], true, stream));
+  if (Gs) SC_TRY(launch_convert_pad(n, m.np, Gs, ldgs, true, cot[1], true, stream));
+  else SC_TRY(launch_fill_zero(m.np, cot[1], true, stream));
+  SC_TRY(launch_copy_pair_if_odd(ns.plan, m.np, cot[0], cot[1], cot[2], cot[3], stream));
+  for (int i = s_max - 1; i >= 0; --i) {
+    r.cond.step = i;
+    const int rd = (i + 1) & 1, wr = i & 1;
+    SC_TRY(rev_double_angle(r, m, chainS(i), chainC(i), cot[2 * rd], cot[2 * rd + 1], cot[2 * wr],
+                            cot[2 * wr + 1], Rb[0]));
+  }
+  r.cond.step = -1;
+
+  // the reverse of each level's scheme, run only for the plan's level
+  Rev v;
+  v.r = &r;
+  v.m = &m;
+  v.Bp = Bp;
+  v.W = r.W;
+  for (int i = 0; i < 9; ++i) v.R[i] = Rb[i];
+  v.Cbar = cot[0];
+  v.Sbar = cot[1];
+  v.gA = Target{gA, ldga, (int)n, true};
+  v.sx = SCALE_2_POW_MINUS_S;
+  r.cond.level = 3;
+  SC_TRY(rev3(v));
+  r.cond.level = 4;
+  SC_TRY(rev4(v));
+  r.cond.level = 6;
+  SC_TRY(rev6(v));
+  r.cond.level = 7;
+  SC_TRY(rev7(v));
+  return launch_fill_nan_if(ns.plan, n, gA, ldga, true, stream);
+}
+
 }  // extern "C"

@@ -241,7 +241,10 @@ __device__ void wg_gemm(const Problem& P, int np, T* smem, int lt) {
   T* const As0 = smem;
   T* const Bs0 = smem + 2 * BT * LDA;
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the wave index is uniform across a wave: readfirstlane keeps it (and the
+  // per-block validity tests built on it) in scalar registers, so they branch
+  // on scalar conditions rather than through the exec mask
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave >> 1, wn = wave & 1;
   const int lr = lane & 15, lg = lane >> 4;
   const int nseg = P.nseg, nin = P.nin, nout = P.nout, nvalid = P.nvalid;

@@ -277,6 +277,10 @@ sincosm_status launch_check_plan(int acc, int level, int s, const NormScratch& n
 // or fill C and S with NaN when the record's status is not SINCOSM_OK.
 sincosm_status launch_copy_result(const sincosm_plan* plan, int64_t n, int64_t np, void* const q[4], void* C,
                                   int64_t ldc, void* S, int64_t lds, bool f64, hipStream_t stream);
+// Device-planned reverse pass: copy the np x np float64 pair (x0, x1) into
+// (y0, y1) when the plan record's s is odd and its status is SINCOSM_OK.
+sincosm_status launch_copy_pair_if_odd(const sincosm_plan* plan, int64_t np, const void* x0, const void* x1,
+                                       void* y0, void* y1, hipStream_t stream);
 // Fill the n x n matrix X with NaN if the plan record at `plan` has a status
 // other than SINCOSM_OK (decided on the device).
 sincosm_status launch_fill_nan_if(const sincosm_plan* plan, int64_t n, void* X, int64_t ld, bool f64,

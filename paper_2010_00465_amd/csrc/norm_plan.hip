@@ -369,6 +369,30 @@ sincosm_status launch_copy_result(const sincosm_plan* plan, int64_t n, int64_t n
   return SINCOSM_OK;
 }
 
+// Device-planned reverse pass: copy the pair (x0, x1) of np x np float64
+// matrices into (y0, y1) when the plan record's s is odd and its status is
+// SINCOSM_OK (the adjoint pair then starts where the first reverse step reads).
+__global__ __launch_bounds__(256) void copy_pair_if_odd_kernel(const sincosm_plan* plan, int64_t count,
+                                                               const double* x0, const double* x1, double* y0,
+                                                               double* y1) {
+  if (plan->status != SINCOSM_OK || (plan->s & 1) == 0) return;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < count) {
+    y0[e] = x0[e];
+    y1[e] = x1[e];
+  }
+}
+
+sincosm_status launch_copy_pair_if_odd(const sincosm_plan* plan, int64_t np, const void* x0, const void* x1,
+                                       void* y0, void* y1, hipStream_t stream) {
+  const int64_t count = np * np;
+  if (count <= 0) return SINCOSM_OK;
+  copy_pair_if_odd_kernel<<<(unsigned)((count + 255) / 256), 256, 0, stream>>>(
+      plan, count, (const double*)x0, (const double*)x1, (double*)y0, (double*)y1);
+  SC_HIP(hipGetLastError());
+  return SINCOSM_OK;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void fill_nan_if_kernel(const sincosm_plan* plan, int64_t cols, T* X,
                                                           int64_t ld) {

@@ -69,6 +69,10 @@ sincosm_status scheme6(Run& r, double sx);
 sincosm_status scheme7(Run& r, double sx);
 sincosm_status run_scheme(Run& r, int level, double sx);
 sincosm_status double_angle(Run& r, const void* Sc, const void* Cc, const Target& Cn, const Target& Sn);
+// Device-planned calls: the products of the four schemes after the shared
+// first one (r.y_ready set), packed into slot launches whose workgroups
+// compute the problem of the plan's level (r.cond.plan set).
+sincosm_status enqueue_schemes_by_slot(Run& r, int acc);
 // Body of sincosm_eval_planned on a given workspace (timed = false: no launch
 // timing events, so nothing is allocated).
 sincosm_status eval_planned(int64_t n, int dtype, const void* A, int64_t lda, void* C, int64_t ldc, void* S,

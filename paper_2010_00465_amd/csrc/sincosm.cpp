@@ -40,6 +40,10 @@ sincosm_status enqueue_method(Run& r, const Modes& m, const Layout& L, char* bas
   return SINCOSM_OK;
 }
 
+}  // namespace
+
+namespace sc {
+
 // The schemes' products after the shared first one, for a plan decided on the
 // device: each scheme's launch sequence is recorded, then the sequences are
 // packed into "slot" launches of up to MAX_PROB alternative problems (one per
@@ -91,6 +95,10 @@ sincosm_status enqueue_schemes_by_slot(Run& r, int acc) {
   }
   return SINCOSM_OK;
 }
+
+}  // namespace sc
+
+namespace {
 
 // Argument and workspace checks shared by sincosm_eval and sincosm_eval_planned
 // (n > 0, Modes already derived).

@@ -1,6 +1,7 @@
-"""sincosm_eval_async (plan decided on the device, fixed launch sequence, no read-back)
-through the C ABI: bitwise equal to sincosm_eval, whose plan is read back first (the
-launches that do work are the same, with the 2^-s operand scales resolved on the device);
+"""sincosm_eval_async and sincosm_backward_async (plan decided on the device, fixed launch
+sequence, no read-back) through the C ABI: bitwise equal to sincosm_eval and sincosm_backward,
+whose plan is read back first (the launches that do work are the same, with the 2^-s operand
+scales resolved on the device);
 against the oracle at 1e-12 (double plan, Sections 1 and 2.1, Tables 1-2) and 5e-6 (float32
 storage, single plan); the plan record; s_max, non-finite input; HIP-graph capture with no
 plan known at capture, replayed on matrices whose plans differ."""
@@ -166,5 +167,111 @@ def test_async_graph_capture_no_plan(env):
         torch.cuda.synchronize()
         assert (rec.level, rec.s, rec.status) == (pe.level, pe.s, 0)
         assert torch.equal(C, Ce) and torch.equal(S, Se), e
+        seen.add((rec.level, rec.s))
+    assert len(seen) == 5
+
+
+# ---------------------------------------------------------------------------
+# Reverse pass with the plan decided on the device
+# ---------------------------------------------------------------------------
+def _grads(env, A, Gc, Gs, s_max):
+    torch, sc = env
+    At = torch.from_numpy(A).cuda()
+    gc = torch.from_numpy(Gc).cuda() if Gc is not None else None
+    gs = torch.from_numpy(Gs).cuda() if Gs is not None else None
+    g0 = torch.empty_like(At)
+    p0 = sc.sincosm_backward(At, gc, gs, g0)
+    g1 = torch.full_like(At, 9.0)
+    pd = torch.zeros(sc.PLAN_BYTES, dtype=torch.uint8, device="cuda")
+    sc.sincosm_backward_async(At, gc, gs, g1, s_max, plan_dev=pd)
+    torch.cuda.synchronize()
+    return g0, g1, p0, sc.plan_from_device(pd)
+
+
+@pytest.mark.parametrize("n", [16, 70, 130])
+@pytest.mark.parametrize("e", [-9.0, -5.0, -1.0, 1.0, 2.0, 3.0, 7.0])
+def test_backward_async_equals_sync(env, n, e):
+    """Every level and s = 0 .. 7 (odd and even s: the adjoint pair's starting place)."""
+    from oracle import frechet as F
+    say("backward async", n, e)
+    A = W.gaussian(n, 2.0 ** e, key=(110, n, int(e * 2) + 40))
+    g = W.rng(111, n, int(e * 2) + 40)
+    Gc, Gs = g.standard_normal((n, n)), g.standard_normal((n, n))
+    g0, g1, p0, p1 = _grads(env, A, Gc, Gs, 8)
+    assert (p1.level, p1.s, p1.status) == (p0.level, p0.s, 0)
+    import torch
+    assert torch.equal(g0, g1), (n, e, p0)
+    if n <= 70:
+        assert rel_fro(g1.cpu().numpy(), F.dual_gradient(A, Gc, Gs)) <= 1e-12
+
+
+@pytest.mark.parametrize("which", ["cos", "sin"])
+def test_backward_async_one_sided_and_config(env, which):
+    import torch
+    n = 256
+    A = W.gaussian(n, 128.0, key=(4, n, 256))          # the configured n = 256, ||A||_1 = 128 case (s = 7)
+    G = W.rng(112).standard_normal((n, n))
+    Gc, Gs = (G, None) if which == "cos" else (None, G)
+    g0, g1, p0, p1 = _grads(env, A, Gc, Gs, 7)          # exactly enough steps
+    assert p1.s == 7 and p1.status == 0
+    assert torch.equal(g0, g1)
+
+
+def test_backward_async_s_max_and_nonfinite(env):
+    torch, sc = env
+    n = 40
+    A = torch.from_numpy(W.gaussian(n, 2.0 ** 6, key=(113,))).cuda()   # s = 6
+    G = torch.from_numpy(W.rng(114).standard_normal((n, n))).cuda()
+    gA = torch.empty_like(A)
+    pd = torch.zeros(sc.PLAN_BYTES, dtype=torch.uint8, device="cuda")
+    sc.sincosm_backward_async(A, G, G, gA, 5, plan_dev=pd)
+    rec = sc.plan_from_device(pd)
+    assert (rec.s, rec.status) == (6, sc._lib.E_SCALING)
+    assert bool(torch.isnan(gA).all())
+    A[2, 3] = float("nan")
+    sc.sincosm_backward_async(A, G, G, gA, 8, plan_dev=pd)
+    assert sc.plan_from_device(pd).status == sc._lib.E_NONFINITE
+    assert bool(torch.isnan(gA).all())
+    with pytest.raises(sc.SincosmError):
+        sc.sincosm_backward_async(A, G, G, gA, -1)
+    with pytest.raises(sc.SincosmError):
+        sc.sincosm_backward_async(A.float(), G.float(), G.float(), gA.float(), 4)
+
+
+def test_backward_async_graph_capture_no_plan(env):
+    """Captured once with no plan known; replayed on inputs whose plans differ: every replay equals
+    sincosm_backward bitwise."""
+    torch, sc = env
+    n = 200
+    A = torch.zeros(n, n, dtype=torch.float64, device="cuda")
+    Gc = torch.from_numpy(W.rng(115).standard_normal((n, n))).cuda()
+    Gs = torch.from_numpy(W.rng(116).standard_normal((n, n))).cuda()
+    gA = torch.empty_like(A)
+    ws = torch.empty(sc.lib.sincosm_backward_workspace_size(n, 0, 0, 8), dtype=torch.uint8, device="cuda")
+    pd = torch.zeros(sc.PLAN_BYTES, dtype=torch.uint8, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        sc.sincosm_backward_async(A, Gc, Gs, gA, 8, ws=ws, plan_dev=pd)   # warm-up outside capture
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        sc.sincosm_backward_async(A, Gc, Gs, gA, 8, ws=ws, plan_dev=pd)
+    seen = set()
+    for k, e in enumerate([-6.0, -1.0, 1.0, 4.0, 7.0]):
+        say("backward async graph replay", e)
+        A.copy_(torch.from_numpy(W.gaussian(n, 2.0 ** e, key=(117, k))).cuda())
+        junk = torch.randn(128, 128, device="cuda", dtype=torch.float64)
+        junk = junk @ junk
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        rec = sc.plan_from_device(pd)
+        ge = torch.empty_like(A)
+        pe = sc.sincosm_backward(A, Gc, Gs, ge)
+        torch.cuda.synchronize()
+        assert (rec.level, rec.s, rec.status) == (pe.level, pe.s, 0)
+        assert torch.equal(gA, ge), e
         seen.add((rec.level, rec.s))
     assert len(seen) == 5

@@ -191,7 +191,8 @@ def test_backward_nonfinite_and_errors(env):
     assert ei.value.status == -2
 
 
-@pytest.mark.parametrize("n,norm", [(256, 0.5), (256, 8.0), (256, 128.0), (1024, 0.5), (1024, 8.0), (1024, 128.0)])
+@pytest.mark.parametrize("n,norm", [(256, 0.5), (256, 8.0), (256, 128.0), (1024, 0.5), (1024, 8.0), (1024, 128.0),
+                                    (2048, 0.5), (2048, 8.0), (2048, 128.0)])
 def test_backward_finite_differences_config_sizes(env, n, norm):
     """Central differences (h = 1e-6) along 4 seeded directions at the configured sizes.
     The gap is FD's own truncation (h^2) and cancellation (u |L| / h) error, so the bar

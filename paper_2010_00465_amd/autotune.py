@@ -77,8 +77,11 @@ def apply_cache(path: str | None = None) -> int:
         if arith not in ARITH or cls not in CLASS_FLAG:
             continue
         table = arith + "_batched" if cls == "batched" else arith
-        if data.get("configs", {}).get(table) != configs(arith, CLASS_FLAG[cls] & BATCHED):
-            continue   # tuned against another configuration table: its indices mean other kernels
+        tuned, have = data.get("configs", {}).get(table), configs(arith, CLASS_FLAG[cls] & BATCHED)
+        if not tuned or tuned != have[:len(tuned)]:
+            # tuned against another configuration table: its indices mean other kernels (a table
+            # that only appended configurations keeps the indices of the ones the cache knows)
+            continue
         code = ARITH[arith] | CLASS_FLAG[cls]
         for e in entries:
             if lib.sincosm_tune_set(code, int(e["np_lo"]), int(e["np_hi"]), int(e["idx"])) == 0:

@@ -141,7 +141,7 @@ void gemm_kernel(const GemmLaunch g) {
   constexpr int LDE = BN + VEC;
   constexpr int GROUP_ELEMS = 2 * (BM * LDA + BK * LDB);   // the two LDS buffers of a k group
   constexpr int STAGE_ELEMS = KS * GROUP_ELEMS;
-  constexpr int RED_ELEMS = KS > 1 ? BM * BN : 0;
+  constexpr int RED_ELEMS = (KS - 1) * BM * BN;   // one region per group after the first
   constexpr int EPI_ELEMS = WTM * LDE;
   constexpr int SMEM_ELEMS = STAGE_ELEMS > EPI_ELEMS ? (STAGE_ELEMS > RED_ELEMS ? STAGE_ELEMS : RED_ELEMS)
                                                      : (EPI_ELEMS > RED_ELEMS ? EPI_ELEMS : RED_ELEMS);
@@ -162,12 +162,13 @@ void gemm_kernel(const GemmLaunch g) {
                         QB <= 64 && 64 % QB == 0 && A_LOADS * NW * RA == BM && B_LOADS * NW * RB == BK),
                 "direct loads: 64- or 128-byte A rows, B rows that divide 1 KiB");
 
-  static_assert(KS == 1 || KS == 2, "one or two k groups");
+  static_assert(KS == 1 || KS == 2 || KS == 4, "one, two or four k groups");
 
-  // k groups (KS = 2): the waves split into two groups of WGM x WGN waves that
-  // take alternate k steps of the same output tile, each with its own LDS
-  // buffers; at the end the second group's accumulators are added to the
-  // first's through LDS (a fixed order, so results are deterministic).
+  // k groups (KS = 2, 4): the waves split into KS groups of WGM x WGN waves
+  // that take every KS-th k step of the same output tile, each with its own
+  // LDS buffers; at the end the other groups' accumulators are added to the
+  // first's through LDS in group order (a fixed order, so results are
+  // deterministic; KS = 2 gives the sum it always gave).
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int grp = KS > 1 ? __builtin_amdgcn_readfirstlane(wave / NW) : 0;
@@ -451,27 +452,32 @@ void gemm_kernel(const GemmLaunch g) {
   }
 
   if constexpr (KS > 1) {
-    // second group's accumulators -> LDS (element-major, so a wave's 64 lanes
-    // write consecutive slots), then added to the first group's
+    // the other groups' accumulators -> LDS, group g into region g - 1
+    // (element-major, so a wave's 64 lanes write consecutive slots), then
+    // added to the first group's in group order
     constexpr int NACC = FM * FN * 4;
     static_assert(NACC * NT == BM * BN && RED_ELEMS <= SMEM_ELEMS, "reduction buffer");
     __syncthreads();   // every wave is done with the stage buffers
-    if (grp == 1) {
+    if (grp > 0) {
+      T* const red = smem + (grp - 1) * (BM * BN);
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) smem[((i * FN + j) * 4 + r) * NT + tidg] = acc[i][j][r];
+          for (int r = 0; r < 4; ++r) red[((i * FN + j) * 4 + r) * NT + tidg] = acc[i][j][r];
     }
     __syncthreads();
     if (grp == 0) {
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
+      for (int q = 0; q < KS - 1; ++q)
 #pragma unroll
-        for (int j = 0; j < FN; ++j)
+        for (int i = 0; i < FM; ++i)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) acc[i][j][r] += smem[((i * FN + j) * 4 + r) * NT + tidg];
+          for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              acc[i][j][r] += smem[q * (BM * BN) + ((i * FN + j) * 4 + r) * NT + tidg];
     }
     __syncthreads();   // the epilogue reuses the buffer
   }
@@ -555,6 +561,7 @@ static const KernelCfg kF64[] = {
     SC_CFG(double, 64, 128, 16, 2, 2, 2, 1),
     SC_CFG_KS(double, 64, 64, 16, 2, 2, 2, 1, 2), SC_CFG_KS(double, 128, 64, 16, 2, 2, 2, 1, 2),
     SC_CFG_KS(double, 64, 64, 16, 2, 2, 2, 0, 2),
+    SC_CFG_KS(double, 64, 64, 16, 2, 2, 4, 1, 4), SC_CFG_KS(double, 64, 64, 16, 2, 2, 4, 0, 4),
 };
 static const KernelCfg kF32[] = {
     SC_CFG(float, 128, 128, 16, 2, 2, 2, 0), SC_CFG(float, 64, 64, 16, 2, 2, 2, 0),
@@ -564,6 +571,7 @@ static const KernelCfg kF32[] = {
     SC_CFG(float, 256, 128, 16, 4, 2, 2, 1), SC_CFG(float, 128, 128, 16, 2, 2, 2, 1),
     SC_CFG(float, 64, 64, 32, 2, 2, 2, 1),
     SC_CFG_KS(float, 64, 64, 32, 2, 2, 2, 1, 2), SC_CFG_KS(float, 64, 64, 16, 2, 2, 2, 1, 2),
+    SC_CFG_KS(float, 64, 64, 32, 2, 2, 4, 1, 4),
 };
 
 const KernelCfg* cfg_table(Arith ar, int& count) {

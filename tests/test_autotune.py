@@ -24,7 +24,7 @@ def test_config_table(lib):
             assert lib.sincosm_tune_config_info(arith, i, info) == 0
             bm, bn, bk, wgm, wgn, wpe, direct, kgroups = list(info)
             assert bm % (16 * wgm) == 0 and bn % (16 * wgn) == 0 and bk % 4 == 0 and wpe >= 1
-            assert direct in (0, 1) and kgroups in (1, 2)
+            assert direct in (0, 1) and kgroups in (1, 2, 4)
         # the three defaults are the square tiles of the padding granularities
         sizes = []
         for i in range(3):
@@ -69,7 +69,8 @@ def test_shipped_cache_matches_table_and_applies(lib):
     from paper_2010_00465_amd import autotune
     data = json.load(open(autotune.DEFAULT_CACHE))
     for arith in autotune.ARITH:
-        assert data["configs"][arith] == autotune.configs(arith)
+        have = autotune.configs(arith)
+        assert data["configs"][arith] == have[:len(data["configs"][arith])]   # the library may append
         if arith + "_batched" in data["configs"]:
             assert data["configs"][arith + "_batched"] == autotune.configs(arith, autotune.BATCHED)
     expected = sum(len(v) for v in data["entries"].values())
@@ -77,9 +78,11 @@ def test_shipped_cache_matches_table_and_applies(lib):
 
 
 def test_cache_of_another_table_is_skipped(lib, tmp_path):
+    """A cache whose configuration list is not a prefix of the library's table is skipped for
+    that table (a prefix is accepted: appending configurations keeps the earlier indices)."""
     from paper_2010_00465_amd import autotune
     data = json.load(open(autotune.DEFAULT_CACHE))
-    data["configs"]["f64"] = data["configs"]["f64"][:-1]        # a table with one entry less
+    data["configs"]["f64"][0] = dict(data["configs"]["f64"][0], bk=99)   # an entry that means another kernel
     p = tmp_path / "cache.json"
     p.write_text(json.dumps(data))
     try:

@@ -396,23 +396,36 @@ __global__ __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(3))) void b
     T* Si = (T*)a.S + off;
     T* Ap = slot;
 
-    // zero-padded copy and column sums (each thread one column, rows in order)
+    // zero-padded copy and column sums (each thread one column, rows in order;
+    // the loads of 16 rows are issued together, then added in row order)
     for (int c = tid; c < np; c += BNT) {
       double sum = 0.0;
-      for (int r = 0; r < np; ++r) {
-        const double v = (r < n && c < n) ? (double)Ai[(int64_t)r * n + c] : 0.0;
-        Ap[(int64_t)r * np + c] = (T)v;
-        sum += fabs(v);
+      for (int r0 = 0; r0 < np; r0 += 16) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int r = r0 + u;
+          v[u] = (r < n && c < n) ? (double)Ai[(int64_t)r * n + c] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          Ap[(int64_t)(r0 + u) * np + c] = (T)v[u];
+          sum += fabs(v[u]);
+        }
       }
       red[c] = (unsigned long long)__double_as_longlong(sum);
     }
     for (int c = np + tid; c < BNT; c += BNT) red[c] = 0ull;
     __syncthreads();
+    // maximum over the columns (integer compare of the float64 bit patterns:
+    // order-independent, so the same result as a sequential scan)
+    for (int w = BNT / 2; w > 0; w >>= 1) {
+      if (tid < w && red[tid + w] > red[tid]) red[tid] = red[tid + w];
+      __syncthreads();
+    }
     if (tid == 0) {
-      unsigned long long mx = 0ull;
-      for (int c = 0; c < np; ++c) mx = red[c] > mx ? red[c] : mx;
       sincosm_plan p;
-      plan_rule(__longlong_as_double((long long)mx), a.acc, &p);
+      plan_rule(__longlong_as_double((long long)red[0]), a.acc, &p);
       s_plan = p;
       if (a.plans) a.plans[i] = p;
     }

@@ -48,9 +48,10 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the secondary measurements (batched, backward, tiers, wave, propagators, "
                          "5-product scheme, refined norm, other orders)")
-    ap.add_argument("--only", choices=["batched", "backward", "tiers", "wave", "propagators", "level5",
-                                       "refined", "sizes"],
-                    help="run and print only one of the secondary measurements")
+    ap.add_argument("--only", choices=["batched", "batched_call", "backward", "tiers", "wave", "propagators",
+                                       "level5", "refined", "sizes"],
+                    help="run and print only one of the secondary measurements (batched_call: the 20,000-matrix "
+                         "batched calls alone, float64 and float32, without the comparison loops; for counters)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run sincosm_matmul once at --n: its two pad/convert copy kernels read and "
                          "write n*n float64 each, a known byte count for scaling HBM counters")
@@ -258,6 +259,26 @@ def bench_batched(torch, sc, W):
             "float32_single": {"ms_per_batch": 1e3 * t32, "evals_per_s": len(ns) / t32,
                                "tflops_algorithmic": flops32 / t32 / 1e12,
                                "mean_products": float(np.mean([p.products for p in pl32]))}}
+
+
+def bench_batched_call(torch, sc, W):
+    """The 20,000-matrix batched call alone (float64 double plans, then float32 single plans),
+    three timed calls each after one warm-up: the workload of the batched counter passes."""
+    ns, offs, packed, _ = W.batched_gaussian(20000, key=(3,))
+    out = {}
+    for dt, acc in ((torch.float64, "double"), (torch.float32, "single")):
+        A = torch.from_numpy(packed).cuda().to(dt)
+        C, S = torch.empty_like(A), torch.empty_like(A)
+        plans = torch.zeros(len(ns) * sc.PLAN_BYTES, dtype=torch.uint8, device="cuda")
+        w = sc.BatchedWorkspace(ns, offs, dt, A.device, accuracy=acc)
+        w.run(A, C, S, plans)
+        pl = sc.plans_from_bytes(plans)
+        flops = float(sum(p.products * 2.0 * int(n) ** 3 for p, n in zip(pl, ns)))
+        t = _elapsed(torch, lambda: w.run(A, C, S, plans), 3)
+        out["f64_double" if dt == torch.float64 else "f32_single"] = {
+            "ms_per_batch": 1e3 * t, "tflops_algorithmic": flops / t / 1e12}
+        del A, C, S, w
+    return out
 
 
 def bench_backward(torch, sc, W):
@@ -592,7 +613,8 @@ def main():
         import torch
         import paper_2010_00465_amd as sc
         import workloads as W
-        fn = {"batched": bench_batched, "backward": bench_backward, "tiers": bench_tiers,
+        fn = {"batched": bench_batched, "batched_call": bench_batched_call, "backward": bench_backward,
+              "tiers": bench_tiers,
               "wave": bench_wave, "propagators": bench_propagators, "level5": bench_level5,
               "refined": bench_refined, "sizes": bench_sizes}[args.only]
         print(json.dumps({args.only: fn(torch, sc, W)}))

@@ -210,3 +210,39 @@ def test_autograd_rejects_unsupported_gradients_up_front():
     A64 = torch.zeros(4, 4, dtype=torch.float64, requires_grad=True)
     with pytest.raises(TypeError):
         sc.sincosm(A64, "single", "f32")
+
+
+def test_device_planned_and_noalloc_argument_errors_without_gpu(lib):
+    """Synchronous argument checks of sincosm_eval_async, sincosm_backward_async and
+    sincosm_eval_planned_noalloc, all taken before any device work."""
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    buf = ctypes.create_string_buffer(4096)
+    p = ctypes.cast(buf, vp).value
+    aligned = (p + 255) // 256 * 256
+    ea = lib.sincosm_eval_async
+    ea.argtypes = [i64, ctypes.c_int, vp, i64, vp, i64, vp, i64, ctypes.c_int, ctypes.c_int, i32, vp,
+                   ctypes.c_size_t, vp, vp]
+    assert ea(0, 0, None, 0, None, 0, None, 0, 0, 0, 8, None, 0, None, None) == 0       # n = 0: no-op
+    assert ea(-1, 0, p, 4, p, 4, p, 4, 0, 0, 8, p, 64, None, None) == -1                # negative n
+    assert ea(4, 0, p, 4, p, 4, p, 4, 0, 0, -1, p, 64, None, None) == -1                # negative s_max
+    assert ea(4, 0, p, 4, p, 4, p, 4, 0, 0, 1101, p, 64, None, None) == -1              # s_max too large
+    assert ea(4, 0, p, 4, p, 4, p, 4, 32, 0, 8, p, 64, None, None) == -1                # refined flag
+    assert ea(4, 0, None, 4, p, 4, p, 4, 0, 0, 8, p, 64, None, None) == -1              # no A
+    assert ea(4, 0, aligned, 4, aligned + 4096, 4, aligned + 8192, 4, 0, 0, 8, None, 0, None, None) == -3
+    ba = lib.sincosm_backward_async
+    ba.argtypes = [i64, ctypes.c_int, vp, i64, vp, i64, vp, i64, vp, i64, ctypes.c_int, i32, vp,
+                   ctypes.c_size_t, vp, vp]
+    assert ba(0, 0, None, 0, None, 0, None, 0, None, 0, 0, 4, None, 0, None, None) == 0
+    assert ba(4, 0, p, 4, None, 4, None, 4, p, 4, 0, -1, p, 64, None, None) == -1      # negative s_max
+    assert ba(4, 1, p, 4, None, 4, None, 4, p, 4, 0, 4, p, 64, None, None) == -2       # float32
+    assert ba(4, 0, p, 4, None, 4, None, 4, p, 4, 0, 4, p, 64, None, None) == -1       # gA aliases A
+    na = lib.sincosm_eval_planned_noalloc
+    plan = Plan()
+    plan.level, plan.s = 7, 0
+    na.argtypes = [i64, ctypes.c_int, vp, i64, vp, i64, vp, i64, ctypes.c_int, ctypes.c_int,
+                   ctypes.POINTER(Plan), vp, vp]
+    assert na(1024, 0, p, 1024, p, 1024, p, 1024, 0, 0, ctypes.byref(plan), None, None) == -7   # too large
+    assert na(-1, 0, p, 4, p, 4, p, 4, 0, 0, ctypes.byref(plan), None, None) == -1
+    lib.sincosm_strerror.restype = ctypes.c_char_p
+    assert b"scratch" in lib.sincosm_strerror(-7)
+    assert b"double-angle" in lib.sincosm_strerror(-8)

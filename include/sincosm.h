@@ -24,8 +24,9 @@
  *  - `stream` is a hipStream_t passed as void*; NULL means the default
  *    stream. Work is enqueued on it. sincosm_eval and sincosm_backward read
  *    the 24-byte plan back to the host (one stream synchronisation) before
- *    they enqueue the products, so they return after the plan is known;
- *    sincosm_eval_async decides the plan on the device and never waits.
+ *    they enqueue the products, so they return after the plan is known (so
+ *    do sincosm_wave_eval, sincosm_wave_block_eval and sincosm_expi_eval);
+ *    the *_async variants decide the plan on the device and never wait.
  *  - The caller owns every buffer. The library allocates no device memory:
  *    each call takes a workspace whose size the matching *_workspace_size
  *    query returns. Results are deterministic (bitwise) for identical inputs,
@@ -263,6 +264,35 @@ sincosm_status sincosm_wave_block_eval(int64_t n, int dtype, const void* A, int6
                                        void* E, int64_t lde, int acc, int prod, void* ws,
                                        size_t ws_bytes, sincosm_plan* plan_host, void* stream);
 
+/* sincosm_wave_eval and sincosm_wave_block_eval with the plan decided on the
+ * device (the wave plan of ||t^2 A||_1): the calls only enqueue kernels on
+ * `stream` (no read-back, no synchronisation, no allocation; graph-capturable).
+ * Fixed sequence: the 1-norm and plan (2 launches), B_s = 4^-s t^2 A formed in
+ * place (1 launch), the products of the four wave schemes packed into 5 slot
+ * launches whose workgroups compute the product of the plan's level, s_max
+ * double-angle steps that return at once beyond the plan's s, then the copy
+ * into C and S (block form: one launch that moves the pair to fixed buffers,
+ * one padded copy of A, the product A s(t, A) writing E, and a NaN fill that
+ * acts only on a failed plan). The sine is carried as s / t_s through the
+ * steps (t_s = 2^-s t; the step becomes S' = S C) and multiplied by t at the
+ * end, so C is bitwise that of the synchronous call and S agrees with it to
+ * rounding (not bitwise).
+ *  s_max: 0 <= s_max <= 1100; a plan with s > s_max gives status
+ *  SINCOSM_E_SCALING in the plan record and NaN outputs (double table: s_max =
+ *  k covers ||t^2 A||_1 <= 3.6404 * 4^k).
+ *  plan_dev (device, nullable): receives the plan record; status SINCOSM_OK,
+ *  SINCOSM_E_NONFINITE or SINCOSM_E_SCALING (outputs NaN for the last two).
+ *  Other arguments, workspace and synchronous argument errors as the
+ *  synchronous calls. */
+sincosm_status sincosm_wave_eval_async(int64_t n, int dtype, const void* A, int64_t lda, double t,
+                                       void* C, int64_t ldc, void* S, int64_t lds,
+                                       int acc, int prod, int32_t s_max, void* ws, size_t ws_bytes,
+                                       sincosm_plan* plan_dev, void* stream);
+sincosm_status sincosm_wave_block_eval_async(int64_t n, int dtype, const void* A, int64_t lda,
+                                             double t, void* E, int64_t lde, int acc, int prod,
+                                             int32_t s_max, void* ws, size_t ws_bytes,
+                                             sincosm_plan* plan_dev, void* stream);
+
 /* Unitary propagator of i u' = A u for real A (eq:unitary, Section 1):
  *   U = e^{-itA} = cos(tA) - i sin(tA),
  * from the cos/sin method on X = tA (the copy of A is multiplied by t in
@@ -278,6 +308,17 @@ sincosm_status sincosm_wave_block_eval(int64_t n, int dtype, const void* A, int6
 sincosm_status sincosm_expi_eval(int64_t n, int dtype, const void* A, int64_t lda, double t,
                                  void* U, int64_t ldu, int acc, int prod, void* ws, size_t ws_bytes,
                                  sincosm_plan* plan_host, void* stream);
+
+/* sincosm_expi_eval with the plan decided on the device (that of
+ * sincosm_eval_async for ||tA||_1): the same fixed launch sequence as
+ * sincosm_eval_async on the padded copy of tA, ending in one pass that writes
+ * U = C - i S (or NaN) from the ping-pong pair the plan's s selects. The
+ * result is bitwise that of sincosm_expi_eval. s_max, plan_dev and its
+ * statuses as sincosm_eval_async (s_max = k covers ||tA||_1 <= 1.8548 * 2^k
+ * for the double table); other arguments and errors as sincosm_expi_eval. */
+sincosm_status sincosm_expi_eval_async(int64_t n, int dtype, const void* A, int64_t lda, double t,
+                                       void* U, int64_t ldu, int acc, int prod, int32_t s_max,
+                                       void* ws, size_t ws_bytes, sincosm_plan* plan_dev, void* stream);
 
 /* Batched evaluation of many independent matrices of uneven orders
  * (1 <= n <= 256), each with its own plan (as sincosm_eval would choose it:

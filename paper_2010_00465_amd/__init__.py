@@ -221,6 +221,48 @@ def sincosm_wave_eval(A: torch.Tensor, t: float, C: torch.Tensor, S: torch.Tenso
     return plan
 
 
+def _plan_dev_ptr(plan_dev: torch.Tensor | None):
+    if plan_dev is None:
+        return None
+    _require_cuda(plan_dev)
+    if plan_dev.numel() * plan_dev.element_size() < PLAN_BYTES:
+        raise ValueError("plan_dev holds fewer than PLAN_BYTES bytes")
+    return plan_dev.data_ptr()
+
+
+def sincosm_wave_eval_async(A: torch.Tensor, t: float, C: torch.Tensor, S: torch.Tensor, s_max: int = 8,
+                            accuracy: str = "double", products: str = "native", ws: torch.Tensor | None = None,
+                            plan_dev: torch.Tensor | None = None) -> None:
+    """C-ABI sincosm_wave_eval_async: sincosm_wave_eval with the wave plan decided on the device
+    (enqueue only; graph-capturable when ``ws`` and ``plan_dev`` are given). A plan needing more
+    than ``s_max`` steps (double table: ||t^2 A||_1 > 3.6404 * 4^s_max), or non-finite t^2 A,
+    gives NaN in C and S and the reason in the plan record's status."""
+    _require_cuda(A, C, S)
+    n = A.shape[0]
+    if ws is None:
+        ws = _workspace(workspace_size(n, A.dtype, accuracy, products), A.device)
+    check(lib.sincosm_wave_eval_async(n, _dtype_code(A), A.data_ptr(), _ld(A), float(t), C.data_ptr(), _ld(C),
+                                      S.data_ptr(), _ld(S), ACC[accuracy], PROD[products], int(s_max),
+                                      ws.data_ptr(), ws.numel(), _plan_dev_ptr(plan_dev), _stream(A)),
+          "sincosm_wave_eval_async")
+
+
+def sincosm_wave_block_eval_async(A: torch.Tensor, t: float, E: torch.Tensor, s_max: int = 8,
+                                  accuracy: str = "double", products: str = "native",
+                                  ws: torch.Tensor | None = None, plan_dev: torch.Tensor | None = None) -> None:
+    """C-ABI sincosm_wave_block_eval_async: E = e^{tM} (2n x 2n) with the plan decided on the device."""
+    _require_cuda(A, E)
+    n = A.shape[0]
+    if E.dtype != A.dtype or E.shape[0] != 2 * n or E.shape[1] != 2 * n:
+        raise ValueError("E must be 2n x 2n of A's dtype")
+    if ws is None:
+        ws = _workspace(workspace_size(n, A.dtype, accuracy, products), A.device)
+    check(lib.sincosm_wave_block_eval_async(n, _dtype_code(A), A.data_ptr(), _ld(A), float(t), E.data_ptr(),
+                                            _ld(E), ACC[accuracy], PROD[products], int(s_max), ws.data_ptr(),
+                                            ws.numel(), _plan_dev_ptr(plan_dev), _stream(A)),
+          "sincosm_wave_block_eval_async")
+
+
 def wave(A: torch.Tensor, t: float, accuracy: str = "double", products: str = "native"):
     """(c(t^2 A), s(t, A)) for a square float64/float32 GPU tensor: the propagator of y'' + A y = 0."""
     if A.dim() != 2 or A.shape[0] != A.shape[1]:
@@ -284,6 +326,24 @@ def sincosm_expi_eval(A: torch.Tensor, t: float, U: torch.Tensor, accuracy: str 
         return plan
     check(st, "sincosm_expi_eval")
     return plan
+
+
+def sincosm_expi_eval_async(A: torch.Tensor, t: float, U: torch.Tensor, s_max: int = 16,
+                            accuracy: str = "double", products: str = "native", ws: torch.Tensor | None = None,
+                            plan_dev: torch.Tensor | None = None, extended: bool = False) -> None:
+    """C-ABI sincosm_expi_eval_async: U = e^{-itA} with the plan decided on the device (enqueue
+    only; bitwise the result of sincosm_expi_eval). s_max and the plan record as in
+    sincosm_eval_async."""
+    _require_cuda(A, U)
+    n = A.shape[0]
+    if U.dtype != _COMPLEX_OF.get(A.dtype) or U.dim() != 2 or U.stride(1) != 1:
+        raise ValueError("U must be a row-major complex tensor matching A's precision")
+    if ws is None:
+        ws = _workspace(workspace_size(n, A.dtype, accuracy, products), A.device)
+    check(lib.sincosm_expi_eval_async(n, _dtype_code(A), A.data_ptr(), _ld(A), float(t), U.data_ptr(),
+                                      U.stride(0), _acc(accuracy, extended), PROD[products], int(s_max),
+                                      ws.data_ptr(), ws.numel(), _plan_dev_ptr(plan_dev), _stream(A)),
+          "sincosm_expi_eval_async")
 
 
 def expi(A: torch.Tensor, t: float = 1.0, accuracy: str = "double", products: str = "native"):

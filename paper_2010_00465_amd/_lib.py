@@ -71,6 +71,12 @@ SYMBOLS = {
                                  _vp]),
     "sincosm_wave_block_eval": (_int, [_i64, _int, _vp, _i64, _dbl, _vp, _i64, _int, _int, _vp, _sz, _PlanP, _vp]),
     "sincosm_expi_eval": (_int, [_i64, _int, _vp, _i64, _dbl, _vp, _i64, _int, _int, _vp, _sz, _PlanP, _vp]),
+    "sincosm_wave_eval_async": (_int, [_i64, _int, _vp, _i64, _dbl, _vp, _i64, _vp, _i64, _int, _int, _i32, _vp,
+                                       _sz, _vp, _vp]),
+    "sincosm_wave_block_eval_async": (_int, [_i64, _int, _vp, _i64, _dbl, _vp, _i64, _int, _int, _i32, _vp, _sz,
+                                             _vp, _vp]),
+    "sincosm_expi_eval_async": (_int, [_i64, _int, _vp, _i64, _dbl, _vp, _i64, _int, _int, _i32, _vp, _sz, _vp,
+                                       _vp]),
     "sincosm_batched_workspace_size": (_sz, [_i64, ctypes.POINTER(_i32), _int, _int, _int]),
     "sincosm_eval_batched": (_int, [_i64, _int, _vp, _vp, _i64, _vp, _vp, _vp, _int, _int, _vp, _sz, _vp, _vp]),
     "sincosm_backward_workspace_size": (_sz, [_i64, _int, _int, _i32]),

@@ -273,18 +273,30 @@ sincosm_status launch_fill_nan(int64_t n, void* X, int64_t ld, bool f64, hipStre
 sincosm_status launch_check_plan(int acc, int level, int s, const NormScratch& ns, sincosm_plan* plan_dev,
                                  hipStream_t stream);
 // Device-planned calls: copy the n x n result pair from the ping-pong buffers
-// (np x np, the storage type) that hold it for the record's s into C and S,
-// or fill C and S with NaN when the record's status is not SINCOSM_OK.
+// (np x np, the storage type) that hold it for the record's s into C and S
+// (S multiplied by ss), or fill C and S with NaN when the record's status is
+// not SINCOSM_OK.
 sincosm_status launch_copy_result(const sincosm_plan* plan, int64_t n, int64_t np, void* const q[4], void* C,
-                                  int64_t ldc, void* S, int64_t lds, bool f64, hipStream_t stream);
-// Device-planned reverse pass: copy the np x np float64 pair (x0, x1) into
-// (y0, y1) when the plan record's s is odd and its status is SINCOSM_OK.
+                                  int64_t ldc, void* S, int64_t lds, bool f64, hipStream_t stream,
+                                  double ss = 1.0);
+// The same into one interleaved complex matrix U = C + i ss S (leading
+// dimension ldu in complex elements), or NaN.
+sincosm_status launch_copy_result_complex(const sincosm_plan* plan, int64_t n, int64_t np, void* const q[4],
+                                          void* U, int64_t ldu, double ss, bool f64, hipStream_t stream);
+// Copy the np x np pair (x0, x1) of es-byte elements into (y0, y1) when the
+// plan record's s is odd and its status is SINCOSM_OK.
 sincosm_status launch_copy_pair_if_odd(const sincosm_plan* plan, int64_t np, const void* x0, const void* x1,
-                                       void* y0, void* y1, hipStream_t stream);
-// Fill the n x n matrix X with NaN if the plan record at `plan` has a status
-// other than SINCOSM_OK (decided on the device).
+                                       void* y0, void* y1, hipStream_t stream, size_t es = 8);
+// X *= 2^(-k s) over count elements, s from the plan record (nothing when its
+// status is not SINCOSM_OK or s = 0).
+sincosm_status launch_scale_by_plan(const sincosm_plan* plan, int k, void* X, int64_t count, bool f64,
+                                    hipStream_t stream);
+// Fill the n x n (rows x cols) matrix X with NaN if the plan record at `plan`
+// has a status other than SINCOSM_OK (decided on the device).
 sincosm_status launch_fill_nan_if(const sincosm_plan* plan, int64_t n, void* X, int64_t ld, bool f64,
                                   hipStream_t stream);
+sincosm_status launch_fill_nan_if_rect(const sincosm_plan* plan, int64_t rows, int64_t cols, void* X, int64_t ld,
+                                       bool f64, hipStream_t stream);
 sincosm_status launch_fill_nan_rect(int64_t rows, int64_t cols, void* X, int64_t ld, bool f64,
                                     hipStream_t stream);
 // dst (n x n complex, leading dimension ldd in complex elements, pairs of the

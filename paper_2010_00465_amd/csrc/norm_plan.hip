@@ -334,12 +334,15 @@ sincosm_status launch_check_plan(int acc, int level, int s, const NormScratch& n
 
 // After s double-angle steps the pair (C, S) sits in (q1, q0) for even s and
 // in (q3, q2) for odd s (the scheme writes (q1, q0), step i writes the other
-// pair of the two). Copies rows of both into the caller's matrices, or fills
-// them with NaN when the plan record's status is not SINCOSM_OK.
-template <typename T>
+// pair of the two). Copies rows of both into the caller's matrices, S
+// multiplied by ss (1 copies exactly), or fills them with NaN when the plan
+// record's status is not SINCOSM_OK. CPLX: one interleaved complex matrix
+// U = C + i ss S at C (leading dimension ldc in complex elements).
+template <typename T, bool CPLX>
 __global__ __launch_bounds__(256) void copy_result_kernel(const sincosm_plan* plan, int64_t n, int64_t np,
                                                           const T* q0, const T* q1, const T* q2, const T* q3,
-                                                          T* C, int64_t ldc, T* S, int64_t lds) {
+                                                          T* C, int64_t ldc, T* S, int64_t lds, T ss) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
   const bool ok = plan->status == SINCOSM_OK;
   const bool odd = (plan->s & 1) != 0;
   const T* srcC = odd ? q3 : q1;
@@ -348,30 +351,58 @@ __global__ __launch_bounds__(256) void copy_result_kernel(const sincosm_plan* pl
   const int64_t i = blockIdx.y;
   if (j < n) {
     const T nan = (T)__longlong_as_double(0x7ff8000000000000ll);
-    C[i * ldc + j] = ok ? srcC[i * np + j] : nan;
-    S[i * lds + j] = ok ? srcS[i * np + j] : nan;
+    const T c = ok ? srcC[i * np + j] : nan;
+    const T sv = ok ? ss * srcS[i * np + j] : nan;
+    if (CPLX) {
+      v2 v;
+      v.x = c;
+      v.y = sv;
+      *(v2*)(C + 2 * (i * ldc + j)) = v;
+    } else {
+      C[i * ldc + j] = c;
+      S[i * lds + j] = sv;
+    }
   }
 }
 
 sincosm_status launch_copy_result(const sincosm_plan* plan, int64_t n, int64_t np, void* const q[4], void* C,
-                                  int64_t ldc, void* S, int64_t lds, bool f64, hipStream_t stream) {
+                                  int64_t ldc, void* S, int64_t lds, bool f64, hipStream_t stream, double ss) {
   if (n <= 0) return SINCOSM_OK;
   dim3 g((unsigned)((n + 255) / 256), (unsigned)n);
   if (f64)
-    copy_result_kernel<double><<<g, 256, 0, stream>>>(plan, n, np, (const double*)q[0], (const double*)q[1],
-                                                      (const double*)q[2], (const double*)q[3], (double*)C, ldc,
-                                                      (double*)S, lds);
+    copy_result_kernel<double, false><<<g, 256, 0, stream>>>(plan, n, np, (const double*)q[0],
+                                                             (const double*)q[1], (const double*)q[2],
+                                                             (const double*)q[3], (double*)C, ldc, (double*)S,
+                                                             lds, ss);
   else
-    copy_result_kernel<float><<<g, 256, 0, stream>>>(plan, n, np, (const float*)q[0], (const float*)q[1],
-                                                     (const float*)q[2], (const float*)q[3], (float*)C, ldc,
-                                                     (float*)S, lds);
+    copy_result_kernel<float, false><<<g, 256, 0, stream>>>(plan, n, np, (const float*)q[0], (const float*)q[1],
+                                                            (const float*)q[2], (const float*)q[3], (float*)C,
+                                                            ldc, (float*)S, lds, (float)ss);
   SC_HIP(hipGetLastError());
   return SINCOSM_OK;
 }
 
-// Device-planned reverse pass: copy the pair (x0, x1) of np x np float64
-// matrices into (y0, y1) when the plan record's s is odd and its status is
-// SINCOSM_OK (the adjoint pair then starts where the first reverse step reads).
+sincosm_status launch_copy_result_complex(const sincosm_plan* plan, int64_t n, int64_t np, void* const q[4],
+                                          void* U, int64_t ldu, double ss, bool f64, hipStream_t stream) {
+  if (n <= 0) return SINCOSM_OK;
+  dim3 g((unsigned)((n + 255) / 256), (unsigned)n);
+  if (f64)
+    copy_result_kernel<double, true><<<g, 256, 0, stream>>>(plan, n, np, (const double*)q[0],
+                                                            (const double*)q[1], (const double*)q[2],
+                                                            (const double*)q[3], (double*)U, ldu, nullptr, 0,
+                                                            ss);
+  else
+    copy_result_kernel<float, true><<<g, 256, 0, stream>>>(plan, n, np, (const float*)q[0], (const float*)q[1],
+                                                           (const float*)q[2], (const float*)q[3], (float*)U,
+                                                           ldu, nullptr, 0, (float)ss);
+  SC_HIP(hipGetLastError());
+  return SINCOSM_OK;
+}
+
+// Device-planned reverse pass and block propagator: copy the pair (x0, x1) of
+// np x np matrices (count 8-byte words each) into (y0, y1) when the plan
+// record's s is odd and its status is SINCOSM_OK, so that the pair a
+// ping-pong sequence ends on is found at (y0, y1) whatever the parity of s.
 __global__ __launch_bounds__(256) void copy_pair_if_odd_kernel(const sincosm_plan* plan, int64_t count,
                                                                const double* x0, const double* x1, double* y0,
                                                                double* y1) {
@@ -384,11 +415,34 @@ __global__ __launch_bounds__(256) void copy_pair_if_odd_kernel(const sincosm_pla
 }
 
 sincosm_status launch_copy_pair_if_odd(const sincosm_plan* plan, int64_t np, const void* x0, const void* x1,
-                                       void* y0, void* y1, hipStream_t stream) {
-  const int64_t count = np * np;
-  if (count <= 0) return SINCOSM_OK;
+                                       void* y0, void* y1, hipStream_t stream, size_t es) {
+  const int64_t bytes = np * np * (int64_t)es;
+  if (bytes <= 0) return SINCOSM_OK;
+  if (bytes % 8) return SINCOSM_E_ARG;
+  const int64_t count = bytes / 8;
   copy_pair_if_odd_kernel<<<(unsigned)((count + 255) / 256), 256, 0, stream>>>(
       plan, count, (const double*)x0, (const double*)x1, (double*)y0, (double*)y1);
+  SC_HIP(hipGetLastError());
+  return SINCOSM_OK;
+}
+
+// X *= 2^(-k s) for the plan record's s, in place over count elements, when
+// the record's status is SINCOSM_OK (an exact scaling for normal results).
+template <typename T>
+__global__ __launch_bounds__(256) void scale_by_plan_kernel(const sincosm_plan* plan, int k, int64_t count,
+                                                            T* X) {
+  if (plan->status != SINCOSM_OK || plan->s == 0) return;
+  const int e2 = -k * plan->s;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < count) X[e] = ldexp(X[e], e2);
+}
+
+sincosm_status launch_scale_by_plan(const sincosm_plan* plan, int k, void* X, int64_t count, bool f64,
+                                    hipStream_t stream) {
+  if (count <= 0) return SINCOSM_OK;
+  const unsigned g = (unsigned)((count + 255) / 256);
+  if (f64) scale_by_plan_kernel<double><<<g, 256, 0, stream>>>(plan, k, count, (double*)X);
+  else scale_by_plan_kernel<float><<<g, 256, 0, stream>>>(plan, k, count, (float*)X);
   SC_HIP(hipGetLastError());
   return SINCOSM_OK;
 }
@@ -402,14 +456,19 @@ __global__ __launch_bounds__(256) void fill_nan_if_kernel(const sincosm_plan* pl
   if (j < cols) X[i * ld + j] = (T)__longlong_as_double(0x7ff8000000000000ll);
 }
 
-sincosm_status launch_fill_nan_if(const sincosm_plan* plan, int64_t n, void* X, int64_t ld, bool f64,
-                                  hipStream_t stream) {
-  if (n <= 0) return SINCOSM_OK;
-  dim3 g((unsigned)((n + 255) / 256), (unsigned)n);
-  if (f64) fill_nan_if_kernel<double><<<g, 256, 0, stream>>>(plan, n, (double*)X, ld);
-  else fill_nan_if_kernel<float><<<g, 256, 0, stream>>>(plan, n, (float*)X, ld);
+sincosm_status launch_fill_nan_if_rect(const sincosm_plan* plan, int64_t rows, int64_t cols, void* X, int64_t ld,
+                                       bool f64, hipStream_t stream) {
+  if (rows <= 0 || cols <= 0) return SINCOSM_OK;
+  dim3 g((unsigned)((cols + 255) / 256), (unsigned)rows);
+  if (f64) fill_nan_if_kernel<double><<<g, 256, 0, stream>>>(plan, cols, (double*)X, ld);
+  else fill_nan_if_kernel<float><<<g, 256, 0, stream>>>(plan, cols, (float*)X, ld);
   SC_HIP(hipGetLastError());
   return SINCOSM_OK;
+}
+
+sincosm_status launch_fill_nan_if(const sincosm_plan* plan, int64_t n, void* X, int64_t ld, bool f64,
+                                  hipStream_t stream) {
+  return launch_fill_nan_if_rect(plan, n, n, X, ld, f64, stream);
 }
 
 // dst[i][j] = (re[i][j], sgn * im[i][j]) for i, j < n: interleaved complex

@@ -81,4 +81,38 @@ sincosm_status sincosm_expi_eval(int64_t n, int dtype, const void* A, int64_t ld
   return launch_interleave(n, m.np, Cf, Sf, true, U, ldu, m.sq_f64, stream);
 }
 
+sincosm_status sincosm_expi_eval_async(int64_t n, int dtype, const void* A, int64_t lda, double t, void* U,
+                                       int64_t ldu, int acc, int prod, int32_t s_max, void* ws, size_t ws_bytes,
+                                       sincosm_plan* plan_dev, void* stream_) {
+  if (n < 0 || n > (1 << 20) || s_max < 0 || s_max > 1100) return SINCOSM_E_ARG;
+  if (!acc_valid(acc, SINCOSM_PLAN_EXTENDED)) return SINCOSM_E_ARG;
+  if (!isfinite(t)) return SINCOSM_E_ARG;
+  Modes m;
+  if (!modes_for(n > 0 ? n : 1, dtype, prod, m)) return SINCOSM_E_ARG;
+  if (n == 0) return SINCOSM_OK;
+  if (!A || !U || lda < n || ldu < n) return SINCOSM_E_ARG;
+  const size_t es = dtype == SINCOSM_F64 ? 8 : 4;
+  {
+    const char* a0 = (const char*)A;
+    const char* a1 = a0 + ((size_t)(n - 1) * lda + n) * es;
+    const char* u0 = (const char*)U;
+    const char* u1 = u0 + ((size_t)(n - 1) * ldu + n) * 2 * es;
+    if (a0 < u1 && u0 < a1) return SINCOSM_E_ARG;
+  }
+  if (((uintptr_t)U) & (2 * es - 1)) return SINCOSM_E_ARG;
+  if (m.poly == Arith::BF16X3 && !bf16x3_available()) return SINCOSM_E_UNSUPPORTED;
+  const Layout L = layout_for(m);
+  if (!ws || ws_bytes < L.total || ((uintptr_t)ws & 255u)) return SINCOSM_E_WORKSPACE;
+  Run r;
+  r.m = &m;
+  r.n = n;
+  r.stream = (hipStream_t)stream_;
+  char* base = (char*)ws;
+  const sincosm_plan* rec = nullptr;
+  SC_TRY(enqueue_async_pair(r, L, base, A, lda, acc, t, s_max, plan_dev, &rec));
+  void* Q[4];
+  for (int i = 0; i < 4; ++i) Q[i] = base + L.q_off[i];
+  return launch_copy_result_complex(rec, n, m.np, Q, U, ldu, -1.0, m.user_f64, r.stream);
+}
+
 }  // extern "C"

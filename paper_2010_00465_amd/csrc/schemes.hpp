@@ -69,10 +69,19 @@ sincosm_status scheme6(Run& r, double sx);
 sincosm_status scheme7(Run& r, double sx);
 sincosm_status run_scheme(Run& r, int level, double sx);
 sincosm_status double_angle(Run& r, const void* Sc, const void* Cc, const Target& Cn, const Target& Sn);
-// Device-planned calls: the products of the four schemes after the shared
-// first one (r.y_ready set), packed into slot launches whose workgroups
-// compute the problem of the plan's level (r.cond.plan set).
+// Device-planned calls: the launch sequences of several schemes (fn(r, level)
+// for each of `levels`) packed into slot launches whose workgroups compute
+// the problem of the plan's level (r.cond.plan set).
+typedef sincosm_status (*SchemeFn)(Run& r, int level);
+sincosm_status enqueue_by_slot(Run& r, const int* levels, int nlev, SchemeFn fn);
+// The products of the cos/sin schemes after the shared first one (r.y_ready set).
 sincosm_status enqueue_schemes_by_slot(Run& r, int acc);
+// Shared by sincosm_eval_async and sincosm_expi_eval_async: the padded copy of
+// pre * A with its device plan (s capped by s_max), the schemes and s_max
+// guarded double-angle steps, leaving the pair in the ping-pong buffers
+// (q1, q0) for even s and (q3, q2) for odd s. Returns the plan record.
+sincosm_status enqueue_async_pair(Run& r, const Layout& L, char* base, const void* A, int64_t lda, int acc,
+                                  double pre, int s_max, sincosm_plan* plan_dev, const sincosm_plan** plan_rec);
 // Body of sincosm_eval_planned on a given workspace (timed = false: no launch
 // timing events, so nothing is allocated).
 sincosm_status eval_planned(int64_t n, int dtype, const void* A, int64_t lda, void* C, int64_t ldc, void* S,

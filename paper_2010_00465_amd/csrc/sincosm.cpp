@@ -44,26 +44,24 @@ sincosm_status enqueue_method(Run& r, const Modes& m, const Layout& L, char* bas
 
 namespace sc {
 
-// The schemes' products after the shared first one, for a plan decided on the
-// device: each scheme's launch sequence is recorded, then the sequences are
-// packed into "slot" launches of up to MAX_PROB alternative problems (one per
-// level, each level's products in increasing slots; levels with more products
-// first, each placed in the earliest slots with room), and every slot is
-// launched with select = 1, so the device computes the problem of the plan's
-// level. Without the extended flag this is 6 launches for the 16 products.
-sincosm_status enqueue_schemes_by_slot(Run& r, int acc) {
-  const int levels[5] = {7, 6, 5, 4, 3};   // most products first
-  const bool extended = (acc & SINCOSM_PLAN_EXTENDED) != 0;
-  Recorder rec[5];
+// Launch sequences of several schemes, for a plan decided on the device: each
+// level's sequence is recorded (fn(r, level)), then the sequences are packed
+// into "slot" launches of up to MAX_PROB alternative problems (one per level,
+// each level's products in increasing slots; levels listed first are placed
+// first, each in the earliest slots with room), and every slot is launched
+// with select = 1, so the device computes the problem of the plan's level.
+sincosm_status enqueue_by_slot(Run& r, const int* levels, int nlev, SchemeFn fn) {
+  constexpr int MAX_LEVELS = 8;
   constexpr int MAX_SLOTS = 12;
+  if (nlev < 1 || nlev > MAX_LEVELS) return SINCOSM_E_ARG;
+  Recorder rec[MAX_LEVELS];
   GemmLaunch slot[MAX_SLOTS];
   int fill[MAX_SLOTS] = {0};
   int nslots = 0;
-  for (int li = 0; li < 5; ++li) {
-    if (levels[li] == 5 && !extended) continue;
+  for (int li = 0; li < nlev; ++li) {
     Run rr = r;
     rr.rec = &rec[li];
-    SC_TRY(run_scheme(rr, levels[li], SCALE_2_POW_MINUS_S));
+    SC_TRY(fn(rr, levels[li]));
     int next = 0;
     for (int k = 0; k < rec[li].count; ++k) {
       const GemmLaunch& g = rec[li].launches[k];
@@ -93,6 +91,52 @@ sincosm_status enqueue_schemes_by_slot(Run& r, int acc) {
     rr.cond = c;
     SC_TRY(gemm(rr, r.m->poly, slot[k]));
   }
+  return SINCOSM_OK;
+}
+
+// The cos/sin schemes' products after the shared first one (r.y_ready set):
+// without the extended flag, 6 launches for the 16 products of levels 7, 6, 4
+// and 3.
+sincosm_status enqueue_schemes_by_slot(Run& r, int acc) {
+  const bool extended = (acc & SINCOSM_PLAN_EXTENDED) != 0;
+  const int all[5] = {7, 6, 5, 4, 3};   // most products first
+  const int base[4] = {7, 6, 4, 3};
+  return enqueue_by_slot(r, extended ? all : base, extended ? 5 : 4,
+                         [](Run& rr, int level) { return run_scheme(rr, level, SCALE_2_POW_MINUS_S); });
+}
+
+sincosm_status enqueue_async_pair(Run& r, const Layout& L, char* base, const void* A, int64_t lda, int acc,
+                                  double pre, int s_max, sincosm_plan* plan_dev, const sincosm_plan** plan_rec) {
+  const Modes& m = *r.m;
+  const NormScratch ns = norm_scratch(base + L.norm_off, m.np);
+  void* Q[4];
+  for (int i = 0; i < 4; ++i) Q[i] = base + L.q_off[i];
+  r.Ap = base + L.ap_off;
+  for (int i = 0; i < 9; ++i) r.W[i] = base + L.w_off[i];
+  SC_TRY(launch_norm_copy_plan(r.n, m.np, A, lda, m.user_f64, base + L.ap_off, m.poly_f64, acc, ns, r.stream, 0,
+                               pre, s_max, plan_dev));
+  // Every product launch below reads the plan record. The scheme writes (C, S)
+  // to (Q1, Q0) and the double-angle steps ping-pong between (Q1, Q0) and
+  // (Q3, Q2); the caller then takes the pair that the record's s selects.
+  r.cond.plan = ns.plan;
+  r.cond.level = 0;
+  r.cond.step = -1;
+  r.cond.select = 0;
+  r.Cout = internal(Q[1], m, m.sq_f64);
+  r.Sout = internal(Q[0], m, m.sq_f64);
+  SC_TRY(first_product(r, SCALE_2_POW_MINUS_S));   // shared by every scheme
+  r.y_ready = true;
+  SC_TRY(enqueue_schemes_by_slot(r, acc));
+  r.cond.level = 0;
+  for (int i = 0; i < s_max; ++i) {
+    r.cond.step = i;
+    void* Sc = Q[(i & 1) ? 2 : 0];
+    void* Cc = Q[(i & 1) ? 3 : 1];
+    const Target Sn = internal(Q[(i & 1) ? 0 : 2], m, m.sq_f64);
+    const Target Cn = internal(Q[(i & 1) ? 1 : 3], m, m.sq_f64);
+    SC_TRY(double_angle(r, Sc, Cc, Cn, Sn));
+  }
+  *plan_rec = ns.plan;
   return SINCOSM_OK;
 }
 
@@ -288,44 +332,16 @@ sincosm_status sincosm_eval_async(int64_t n, int dtype, const void* A, int64_t l
   if (n == 0) return SINCOSM_OK;
   SC_TRY(check_eval_args(n, dtype, A, lda, C, ldc, S, lds, m, ws, ws_bytes));
   const Layout L = layout_for(m);
-  hipStream_t stream = (hipStream_t)stream_;
-  char* base = (char*)ws;
-  const NormScratch ns = norm_scratch(base + L.norm_off, m.np);
-  void* Ap = base + L.ap_off;
-  void* Q[4];
-  for (int i = 0; i < 4; ++i) Q[i] = base + L.q_off[i];
   Run r;
   r.m = &m;
   r.n = n;
-  r.Ap = Ap;
-  for (int i = 0; i < 9; ++i) r.W[i] = base + L.w_off[i];
-  r.stream = stream;
-  SC_TRY(launch_norm_copy_plan(n, m.np, A, lda, m.user_f64, Ap, m.poly_f64, acc, ns, stream, 0, 1.0, s_max,
-                               plan_dev));
-
-  // Every product launch below reads the plan record. The scheme writes (C, S)
-  // to (Q1, Q0) and the double-angle steps ping-pong between (Q1, Q0) and
-  // (Q3, Q2); a copy kernel then moves the pair that the record's s selects
-  // into the caller's C and S (or NaN, for a non-finite A or s > s_max).
-  r.cond.plan = ns.plan;
-  r.cond.level = 0;
-  r.cond.step = -1;
-  r.cond.select = 0;
-  r.Cout = internal(Q[1], m, m.sq_f64);
-  r.Sout = internal(Q[0], m, m.sq_f64);
-  SC_TRY(first_product(r, SCALE_2_POW_MINUS_S));   // shared by every scheme
-  r.y_ready = true;
-  SC_TRY(enqueue_schemes_by_slot(r, acc));
-  r.cond.level = 0;
-  for (int i = 0; i < s_max; ++i) {
-    r.cond.step = i;
-    void* Sc = Q[(i & 1) ? 2 : 0];
-    void* Cc = Q[(i & 1) ? 3 : 1];
-    const Target Sn = internal(Q[(i & 1) ? 0 : 2], m, m.sq_f64);
-    const Target Cn = internal(Q[(i & 1) ? 1 : 3], m, m.sq_f64);
-    SC_TRY(double_angle(r, Sc, Cc, Cn, Sn));
-  }
-  return launch_copy_result(ns.plan, n, m.np, Q, C, ldc, S, lds, m.user_f64, stream);
+  r.stream = (hipStream_t)stream_;
+  char* base = (char*)ws;
+  const sincosm_plan* rec = nullptr;
+  SC_TRY(enqueue_async_pair(r, L, base, A, lda, acc, 1.0, s_max, plan_dev, &rec));
+  void* Q[4];
+  for (int i = 0; i < 4; ++i) Q[i] = base + L.q_off[i];
+  return launch_copy_result(rec, n, m.np, Q, C, ldc, S, lds, m.user_f64, r.stream);
 }
 
 size_t sincosm_matmul_workspace_size(int64_t n, int dtype, int prod) {

@@ -177,16 +177,17 @@ static sincosm_status run_wave_scheme(Run& r, int level, double bs, double ts) {
   }
 }
 
-// One wave double-angle step: C' = 2 Cc Cc - I, S' = 2 Sc Cc.
+// One wave double-angle step: C' = 2 Cc Cc - I, S' = ks Sc Cc (ks = 2; 1 for
+// S carried in units of t_s, see sincosm_wave_eval_async).
 static sincosm_status wave_double_angle(Run& r, const void* Cc, const void* Sc, const Target& Cn,
-                                        const Target& Sn) {
+                                        const Target& Sn, double ks = 2.0) {
   const Modes& m = *r.m;
   Problem p0 = make_problem((int)r.n);
   add_seg(p0, Cc, Cc, m.np);
   add_out(p0, Cn, 2.0, -1.0, {});
   Problem p1 = make_problem((int)r.n);
   add_seg(p1, Sc, Cc, m.np);
-  add_out(p1, Sn, 2.0, 0.0, {});
+  add_out(p1, Sn, ks, 0.0, {});
   return gemm(r, m.sq, two(p0, p1, (int)m.np));
 }
 
@@ -265,6 +266,51 @@ static sincosm_status wave_body(WaveCall& c, int64_t n, double t, const Target* 
   }
   if (Cf) *Cf = Cl;
   if (Sf) *Sf = Sl;
+  return SINCOSM_OK;
+}
+
+// Device-planned wave pair. The plan is decided on the device, so no scale
+// that depends on s can reach a host-built epilogue coefficient; instead
+//  - Ap is multiplied in place by 4^-s once the plan exists (B_s formed
+//    explicitly: the same values the operand scales give), and
+//  - the sine is carried in units of t_s: S~ = S / t_s. The scheme then
+//    runs with t_s = 1, and since t_{j+1} = 2 t_j the step S' = 2 S C becomes
+//    S~' = S~ C. The caller's S is t S~ after the last step.
+// Schemes of levels 5, 4, 3, 2 packed into slot launches, s_max guarded
+// steps; the pair ends in (Q1, Q0) for even s and (Q3, Q2) for odd s.
+static sincosm_status wave_async_pair(WaveCall& c, int64_t n, const void* A, int64_t lda, double t, int acc,
+                                      int s_max, sincosm_plan* plan_dev, const sincosm_plan** plan_rec) {
+  const Modes& m = c.m;
+  const NormScratch ns = norm_scratch(c.base + c.L.norm_off, m.np);
+  void* Ap = c.base + c.L.ap_off;
+  SC_TRY(launch_norm_copy_plan(n, m.np, A, lda, m.user_f64, Ap, m.poly_f64, acc, ns, c.stream, 1, t * t, s_max,
+                               plan_dev));
+  SC_TRY(launch_scale_by_plan(ns.plan, 2, Ap, m.np * m.np, m.poly_f64, c.stream));
+  Run r;
+  r.m = &m;
+  r.n = n;
+  r.Ap = Ap;
+  for (int i = 0; i < 9; ++i) r.W[i] = c.base + c.L.w_off[i];
+  r.stream = c.stream;
+  void* Q[4];
+  for (int i = 0; i < 4; ++i) Q[i] = c.base + c.L.q_off[i];
+  r.cond.plan = ns.plan;
+  r.cond.level = 0;
+  r.cond.step = -1;
+  r.cond.select = 0;
+  r.Cout = internal(Q[1], m, m.sq_f64);
+  r.Sout = internal(Q[0], m, m.sq_f64);
+  const int levels[4] = {5, 4, 3, 2};   // most products first
+  SC_TRY(enqueue_by_slot(r, levels, 4, [](Run& rr, int level) { return run_wave_scheme(rr, level, 1.0, 1.0); }));
+  for (int i = 0; i < s_max; ++i) {
+    r.cond.step = i;
+    void* Sc = Q[(i & 1) ? 2 : 0];
+    void* Cc = Q[(i & 1) ? 3 : 1];
+    const Target Sn = internal(Q[(i & 1) ? 0 : 2], m, m.sq_f64);
+    const Target Cn = internal(Q[(i & 1) ? 1 : 3], m, m.sq_f64);
+    SC_TRY(wave_double_angle(r, Cc, Sc, Cn, Sn, 1.0));
+  }
+  *plan_rec = ns.plan;
   return SINCOSM_OK;
 }
 
@@ -354,6 +400,80 @@ sincosm_status sincosm_wave_block_eval(int64_t n, int dtype, const void* A, int6
   const sincosm_status st = launch_gemm(m.sq, m.tile, one(p, (int)m.np), c.stream);
   timing_end(tm, c.stream);
   return st;
+}
+
+sincosm_status sincosm_wave_eval_async(int64_t n, int dtype, const void* A, int64_t lda, double t, void* C,
+                                       int64_t ldc, void* S, int64_t lds, int acc, int prod, int32_t s_max,
+                                       void* ws, size_t ws_bytes, sincosm_plan* plan_dev, void* stream) {
+  if (s_max < 0 || s_max > 1100) return SINCOSM_E_ARG;
+  WaveCall c;
+  SC_TRY(wave_check(n, dtype, A, lda, t, acc, prod, c.m));
+  if (n == 0) return SINCOSM_OK;
+  if (!C || !S || ldc < n || lds < n) return SINCOSM_E_ARG;
+  const size_t es = dtype == SINCOSM_F64 ? 8 : 4;
+  if (overlaps(A, lda, C, ldc, n, es) || overlaps(A, lda, S, lds, n, es) || overlaps(C, ldc, S, lds, n, es))
+    return SINCOSM_E_ARG;
+  c.L = layout_for(c.m);
+  if (!ws || ws_bytes < c.L.total || ((uintptr_t)ws & 255u)) return SINCOSM_E_WORKSPACE;
+  c.stream = (hipStream_t)stream;
+  c.base = (char*)ws;
+  const sincosm_plan* rec = nullptr;
+  SC_TRY(wave_async_pair(c, n, A, lda, t, acc, s_max, plan_dev, &rec));
+  void* Q[4];
+  for (int i = 0; i < 4; ++i) Q[i] = c.base + c.L.q_off[i];
+  return launch_copy_result(rec, n, c.m.np, Q, C, ldc, S, lds, c.m.user_f64, c.stream, t);
+}
+
+sincosm_status sincosm_wave_block_eval_async(int64_t n, int dtype, const void* A, int64_t lda, double t, void* E,
+                                             int64_t lde, int acc, int prod, int32_t s_max, void* ws,
+                                             size_t ws_bytes, sincosm_plan* plan_dev, void* stream) {
+  if (s_max < 0 || s_max > 1100) return SINCOSM_E_ARG;
+  WaveCall c;
+  SC_TRY(wave_check(n, dtype, A, lda, t, acc, prod, c.m));
+  if (n == 0) return SINCOSM_OK;
+  if (!E || lde < 2 * n) return SINCOSM_E_ARG;
+  const size_t es = dtype == SINCOSM_F64 ? 8 : 4;
+  {
+    const char* a0 = (const char*)A;
+    const char* a1 = a0 + ((size_t)(n - 1) * lda + n) * es;
+    const char* e0 = (const char*)E;
+    const char* e1 = e0 + ((size_t)(2 * n - 1) * lde + 2 * n) * es;
+    if (a0 < e1 && e0 < a1) return SINCOSM_E_ARG;
+  }
+  c.L = layout_for(c.m);
+  if (!ws || ws_bytes < c.L.total || ((uintptr_t)ws & 255u)) return SINCOSM_E_WORKSPACE;
+  c.stream = (hipStream_t)stream;
+  c.base = (char*)ws;
+  const sincosm_plan* rec = nullptr;
+  SC_TRY(wave_async_pair(c, n, A, lda, t, acc, s_max, plan_dev, &rec));
+  const Modes& m = c.m;
+  void* Q[4];
+  for (int i = 0; i < 4; ++i) Q[i] = c.base + c.L.q_off[i];
+  // the pair (C, S~) into (Q1, Q0) whatever the parity of s, then A padded into Q2
+  SC_TRY(launch_copy_pair_if_odd(rec, m.np, Q[3], Q[2], Q[1], Q[0], c.stream, m.sq_f64 ? 8 : 4));
+  SC_TRY(launch_convert_pad(n, m.np, A, lda, m.user_f64, Q[2], m.sq_f64, c.stream));
+  // one launch: D = A S~; E21 = -t D, E11 = E22 = C, E12 = t S~ (skipped when
+  // the record's status is not SINCOSM_OK; E is then filled with NaN)
+  char* e = (char*)E;
+  const Target E11{e, lde, (int)n, m.user_f64};
+  const Target E12{e + (size_t)n * es, lde, (int)n, m.user_f64};
+  const Target E21{e + (size_t)n * lde * es, lde, (int)n, m.user_f64};
+  const Target E22{e + ((size_t)n * lde + n) * es, lde, (int)n, m.user_f64};
+  Problem p = make_problem((int)n);
+  add_seg(p, Q[2], Q[0], m.np);
+  add_in(p, Q[1], m.np);
+  add_in(p, Q[0], m.np);
+  add_out(p, E21, -t, 0.0, {});
+  add_out(p, E11, 0.0, 0.0, {1.0, 0.0});
+  add_out(p, E22, 0.0, 0.0, {1.0, 0.0});
+  add_out(p, E12, 0.0, 0.0, {0.0, t});
+  GemmLaunch g = one(p, (int)m.np);
+  g.cond.plan = rec;
+  g.cond.level = 0;
+  g.cond.step = -1;
+  g.cond.select = 0;
+  SC_TRY(launch_gemm(m.sq, m.tile, g, c.stream));
+  return launch_fill_nan_if_rect(rec, 2 * n, 2 * n, E, lde, m.user_f64, c.stream);
 }
 
 }  // extern "C"

@@ -246,3 +246,33 @@ def test_device_planned_and_noalloc_argument_errors_without_gpu(lib):
     lib.sincosm_strerror.restype = ctypes.c_char_p
     assert b"scratch" in lib.sincosm_strerror(-7)
     assert b"double-angle" in lib.sincosm_strerror(-8)
+
+
+def test_async_propagator_argument_errors_without_gpu(lib):
+    """Synchronous argument checks of the device-planned wave, block and expi entry points."""
+    vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    buf = ctypes.create_string_buffer(4096)
+    p = ctypes.cast(buf, vp).value
+    we = lib.sincosm_wave_eval_async
+    we.argtypes = [i64, ctypes.c_int, vp, i64, dbl, vp, i64, vp, i64, ctypes.c_int, ctypes.c_int, i32, vp,
+                   ctypes.c_size_t, vp, vp]
+    assert we(0, 0, None, 0, 1.0, None, 0, None, 0, 0, 0, 4, None, 0, None, None) == 0
+    assert we(4, 0, p, 4, 1.0, p + 1024, 4, p + 2048, 4, 0, 0, -1, p, 64, None, None) == -1   # s_max < 0
+    assert we(4, 0, p, 4, float("inf"), p + 1024, 4, p + 2048, 4, 0, 0, 4, p, 64, None, None) == -1
+    assert we(4, 0, p, 4, 1.0, p, 4, p + 2048, 4, 0, 0, 4, p, 64, None, None) == -1           # C aliases A
+    assert we(4, 0, p, 4, 1.0, p + 1024, 4, p + 2048, 4, 0, 0, 4, None, 0, None, None) == -3  # no workspace
+    wb = lib.sincosm_wave_block_eval_async
+    wb.argtypes = [i64, ctypes.c_int, vp, i64, dbl, vp, i64, ctypes.c_int, ctypes.c_int, i32, vp,
+                   ctypes.c_size_t, vp, vp]
+    assert wb(0, 0, None, 0, 1.0, None, 0, 0, 0, 4, None, 0, None, None) == 0
+    assert wb(4, 0, p, 4, 1.0, p + 1024, 7, 0, 0, 4, p, 64, None, None) == -1                # lde < 2n
+    assert wb(4, 0, p, 4, 1.0, p + 1024, 8, 0, 0, 1101, p, 64, None, None) == -1             # s_max too large
+    ex = lib.sincosm_expi_eval_async
+    ex.argtypes = [i64, ctypes.c_int, vp, i64, dbl, vp, i64, ctypes.c_int, ctypes.c_int, i32, vp,
+                   ctypes.c_size_t, vp, vp]
+    assert ex(0, 0, None, 0, 1.0, None, 0, 0, 0, 4, None, 0, None, None) == 0
+    assert ex(4, 0, p, 4, float("nan"), p + 1024, 4, 0, 0, 4, p, 64, None, None) == -1
+    u_odd = (p + 1024) // 16 * 16 + 8                                                      # not 16-byte aligned
+    assert ex(4, 0, p, 4, 1.0, u_odd, 4, 0, 0, 4, p, 64, None, None) == -1
+    assert ex(4, 0, p, 4, 1.0, p + 1024, 4, 32, 0, 4, p, 64, None, None) == -1               # refined flag
+    assert ex(4, 0, p, 4, 1.0, p + 1024, 4, 0, 0, 4, None, 0, None, None) == -3

@@ -340,7 +340,9 @@ sincosm_status sincosm_expi_eval_async(int64_t n, int dtype, const void* A, int6
  *   SINCOSM_E_WORKSPACE; a matrix with Inf/NaN gets NaN outputs and status
  *   SINCOSM_E_NONFINITE. The call enqueues a fixed sequence of two launches
  *   (entry checks and the largest-first work queue in one workgroup, then the
- *   persistent kernel), reads nothing back and returns SINCOSM_OK for any
+ *   persistent kernel; three when the tuning table routes padded orders 16 or
+ *   32 to the LDS-resident kernel, which then runs before the persistent one
+ *   on the smallest orders), reads nothing back and returns SINCOSM_OK for any
  *   entry values, so it can be captured in a HIP graph and replayed with new
  *   values in A, n_dev and offset_dev.
  *   ws / ws_bytes: 256-byte aligned; the size query's value for the batch
@@ -433,11 +435,14 @@ sincosm_status sincosm_timing_read(int kind, double* total_ms, int64_t* count);
  * double-angle steps); with SINCOSM_TUNE_UNEVEN, the table of the remaining
  * launches: problems of unequal k-work or one problem with several k-segments
  * (the reverse pass). Such launches use the plain table where their own has
- * no entry. With SINCOSM_TUNE_BATCHED, the entries choose the output tile of
- * sincosm_eval_batched's per-matrix products by padded order: configuration 0
- * is 64 x 64 (the default), 1 is 32 x 32; the choice is read when
- * sincosm_eval_batched is called (a captured graph keeps the choice made at
- * capture). More than one flag is an error. Host-side state shared by all
+ * no entry. With SINCOSM_TUNE_BATCHED, the entries choose how
+ * sincosm_eval_batched runs a matrix's products by padded order: configuration
+ * 0 is 64 x 64 output tiles (the default), 1 is 32 x 32 (both with the
+ * per-matrix workspace in the caller's workspace), 2 keeps the whole
+ * per-matrix workspace in LDS (a kernel of its own for padded orders up to
+ * 32; larger orders given 2 use 64 x 64); all three give bitwise the same
+ * results. The choice is read when sincosm_eval_batched is called (a captured
+ * graph keeps the choice made at capture). More than one flag is an error. Host-side state shared by all
  * devices, thread-safe; results do not depend on it beyond rounding order. */
 enum { SINCOSM_TUNE_MULTI = 16, SINCOSM_TUNE_UNEVEN = 32, SINCOSM_TUNE_BATCHED = 64 };
 int sincosm_tune_num_configs(int arith);

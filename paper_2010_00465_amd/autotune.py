@@ -12,8 +12,9 @@ steps): it forces each configuration for that class only
 tunes the launches of unequal problems or several k-segments, which only the
 reverse pass makes (``SINCOSM_TUNE_UNEVEN``): it times whole
 ``sincosm_backward`` calls with each configuration forced for that class. A
-fourth pass picks the output tile of the batched kernel's per-matrix products
-(``SINCOSM_TUNE_BATCHED``: 64 x 64 or 32 x 32) per padded order, timing
+fourth pass picks the product mode of the batched kernel's per-matrix products
+(``SINCOSM_TUNE_BATCHED``: 64 x 64 or 32 x 32 output tiles, or for padded
+orders up to 32 the LDS-resident kernel) per padded order, timing
 ``sincosm_eval_batched`` on batches of one order. The fastest
 configuration per probe and class is written to a JSON cache with the range of
 padded orders it covers (midpoints between probes); for the single-product and
@@ -197,13 +198,17 @@ def tune_batched(torch, sc, arith: str, reps: int, log):
         best = None
         timings[str(np_)] = {}
         for c in configs(arith, BATCHED):
+            if c["direct"] == 2 and np_ > c["bm"]:
+                continue   # the LDS-resident mode takes padded orders up to its size only
             ms = time_config_batched(torch, sc, arith, np_, c["idx"], reps)
             timings[str(np_)][str(c["idx"])] = ms
             if best is None or ms < best[1]:
                 best = (c["idx"], ms)
         lo, hi = _ranges(nps, k)
         entries.append({"np_lo": lo, "np_hi": hi, "idx": best[0], "probe_np": np_, "ms": best[1]})
-        log(f"{arith} batched np={np_}: best tile {configs(arith, BATCHED)[best[0]]['bm']} {best[1]:.3f} ms")
+        cb = configs(arith, BATCHED)[best[0]]
+        mode = "LDS-resident" if cb["direct"] == 2 else f"tile {cb['bm']}"
+        log(f"{arith} batched np={np_}: best {mode} {best[1]:.3f} ms")
     return entries, timings
 
 

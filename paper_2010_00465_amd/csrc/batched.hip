@@ -35,6 +35,13 @@ constexpr int BBK = 16;       // k step
 constexpr int BNT = 256;      // threads (4 waves in a 2 x 2 grid)
 constexpr int WG_PER_CU = 4;  // resident workgroups per CU the arena is sized for
 constexpr int NMAX = 256;     // largest order of the batched path
+// Per padded order: how its products run. TILE_64 / TILE_32: the arena in
+// global memory, output tiles of 64 x 64 or 32 x 32 (batched_kernel);
+// LDS_RESIDENT: the whole per-matrix workspace in LDS (batched_small_kernel,
+// padded orders up to SNP only).
+constexpr int TILE_64 = 0, TILE_32 = 1, LDS_RESIDENT = 2;
+constexpr int SNP = 32;       // largest padded order of the LDS-resident kernel
+constexpr int SMALL_WG_PER_CU = 2;   // resident LDS-resident workgroups per CU (76 KB of LDS each in float64)
 
 // symbolic buffer ids of the recorded templates
 constexpr int ID_AP = 0;      // 1..9: W0..W8
@@ -61,11 +68,12 @@ __host__ __device__ inline int level_index(int level) { return level == 3 ? 0 : 
 struct BatchArgs {
   int batch;
   int acc;
-  int8_t tile32[NMAX / 16 + 1];   // per padded order / 16: 1 = 32 x 32 output tiles, 0 = 64 x 64
+  int8_t tile32[NMAX / 16 + 1];   // per padded order / 16: product mode (TILE_64, TILE_32 or LDS_RESIDENT)
   const int32_t* nmat;            // caller's orders (device)
   const int64_t* off;             // caller's element offsets (device)
   const int32_t* order;           // work queue: accepted entries, largest padded order first
   const unsigned int* nqueue;     // its length
+  const unsigned int* nlarge;     // queue entries [0, nlarge) go to batched_kernel, the rest to the LDS kernel
   const void* A;
   void* C;
   void* S;
@@ -80,11 +88,20 @@ struct BatchArgs {
 // (npm) and its n x n elements lie inside the packed arrays (0 <= off,
 // off + n^2 <= total); a rejected entry gets status SINCOSM_E_ARG (or
 // SINCOSM_E_WORKSPACE for an order beyond npm) in its plan record and is not
-// computed. Accepted entries are bucketed by padded order, largest first;
-// the order within a bucket does not matter (each matrix is computed by one
-// workgroup the same way wherever it sits in the queue).
+// computed. Accepted entries are bucketed by padded order, largest first.
+// The padded orders whose bit is set in lds_mask (bit k: order 16 k, k <=
+// SNP / 16) go to the LDS-resident kernel, after all others in the queue, when
+// the other entries number fewer than `fill` (the persistent kernel's
+// workgroups): with more, those small matrices are worth more to the
+// persistent kernel as the short work that fills the end of its run, and the
+// whole queue stays its own. The queue's first *nlarge entries are
+// batched_kernel's, the rest batched_small_kernel's. The order within a
+// bucket does not matter (each matrix is computed by one workgroup the same
+// way wherever it sits in the queue, and both kernels give the same bits).
 constexpr int ORDER_THREADS = 1024;
 constexpr int NBUCKET = NMAX / 16;
+constexpr int NSB = SNP / 16;             // padded orders the LDS-resident kernel can take
+constexpr int NB2 = NBUCKET + NSB;        // buckets of the queue
 
 __device__ inline int entry_status(int n, int64_t o, int64_t total, int npm) {
   if (n < 1 || n > NMAX) return SINCOSM_E_ARG;
@@ -93,12 +110,22 @@ __device__ inline int entry_status(int n, int64_t o, int64_t total, int npm) {
   return SINCOSM_OK;
 }
 
+// Queue bucket of an accepted order: padded order 256 first ... 16 last, then
+// the LDS-resident orders (32 before 16).
+__device__ inline int queue_bucket(int n, unsigned int lds_mask) {
+  const int k = (n + 15) >> 4;
+  if (k <= NSB && ((lds_mask >> k) & 1u)) return NBUCKET + NSB - k;
+  return NBUCKET - k;
+}
+
 __global__ __launch_bounds__(ORDER_THREADS) void batched_order_kernel(int batch, const int32_t* nmat,
                                                                      const int64_t* off, int64_t total, int npm,
+                                                                     unsigned int lds_mask, int fill,
                                                                      int32_t* order, unsigned int* counter,
-                                                                     unsigned int* nqueue, sincosm_plan* plans) {
+                                                                     sincosm_plan* plans) {
   __shared__ unsigned int hist[NBUCKET];
-  __shared__ unsigned int next[NBUCKET];
+  __shared__ unsigned int next[NB2];
+  __shared__ unsigned int mask;
   const int tid = threadIdx.x;
   for (int b = tid; b < NBUCKET; b += ORDER_THREADS) hist[b] = 0u;
   __syncthreads();
@@ -113,23 +140,36 @@ __global__ __launch_bounds__(ORDER_THREADS) void batched_order_kernel(int batch,
       }
       continue;
     }
-    atomicAdd(&hist[NBUCKET - ((n + 15) >> 4)], 1u);   // bucket 0: padded order 256
+    atomicAdd(&hist[queue_bucket(n, 0u)], 1u);   // by padded order: bucket 0 is order 256
   }
   __syncthreads();
   if (tid == 0) {
-    unsigned int run = 0u;
+    unsigned int others = 0u;
+    for (int k = 1; k <= NBUCKET; ++k)
+      if (!(k <= NSB && ((lds_mask >> k) & 1u))) others += hist[NBUCKET - k];
+    const unsigned int m = others < (unsigned int)fill ? lds_mask : 0u;
+    mask = m;
+    for (int b = 0; b < NB2; ++b) next[b] = 0u;
     for (int b = 0; b < NBUCKET; ++b) {
-      next[b] = run;
-      run += hist[b];
+      const int k = NBUCKET - b;
+      next[queue_bucket(16 * k, m)] = hist[b];
     }
-    *nqueue = run;
-    *counter = 0u;
+    unsigned int run = 0u;
+    for (int b = 0; b < NB2; ++b) {
+      const unsigned int h = next[b];
+      next[b] = run;
+      run += h;
+    }
+    counter[0] = 0u;            // next entry of batched_kernel
+    counter[1] = run;           // queue length
+    counter[2] = next[NBUCKET]; // first entry of the LDS-resident kernel
   }
   __syncthreads();
+  const unsigned int m = mask;
   for (int i = tid; i < batch; i += ORDER_THREADS) {
     const int n = nmat[i];
     if (entry_status(n, off[i], total, npm) != SINCOSM_OK) continue;
-    order[atomicAdd(&next[NBUCKET - ((n + 15) >> 4)], 1u)] = i;
+    order[atomicAdd(&next[queue_bucket(n, m)], 1u)] = i;
   }
 }
 
@@ -376,7 +416,7 @@ __global__ __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(3))) void b
   __shared__ sincosm_plan s_plan;
   const int tid = threadIdx.x;
   T* const slot = (T*)(a.arena + (int64_t)blockIdx.x * a.slot_bytes);
-  const int nq = (int)*a.nqueue;
+  const int nq = (int)*a.nlarge;   // the queue's entries for this kernel
 
   for (;;) {
     if (tid == 0) s_item = (int)atomicAdd(a.counter, 1u);
@@ -390,7 +430,9 @@ __global__ __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(3))) void b
     if (n < 1 || n > NMAX) continue;
     const int64_t off = a.off[i];
     const int np = (n + 15) & ~15;
-    const int lt = a.tile32[np >> 4] ? 5 : 6;   // log2 of the product tile
+    // log2 of the product tile (orders routed to the LDS-resident kernel that
+    // this kernel takes instead, see batched_order_kernel, use 32 x 32)
+    const int lt = a.tile32[np >> 4] == TILE_64 ? 6 : 5;
     const T* Ai = (const T*)a.A + off;
     T* Ci = (T*)a.C + off;
     T* Si = (T*)a.S + off;
@@ -525,10 +567,272 @@ __global__ __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(3))) void b
   }
 }
 
+// ----------------------------------------------------------------------------
+// LDS-resident kernel for padded orders up to SNP = 32. A matrix's whole
+// workspace stays on chip: W0 .. W8 in LDS (row stride SLD = SNP + 1, so the
+// rows an MFMA operand read touches start in different banks), and the padded
+// copy of A, which the schemes use only as a product operand, as the MFMA
+// operand fragments of each wave in registers. Only A is read from memory and
+// only C and S are written. Each wave owns one 16 x 16 output block (one wave
+// at padded order 16, four at 32) and applies the epilogue straight from its
+// accumulators. The k order of every product, the operand scaling and the
+// epilogue's fused multiply-adds are those of batched_kernel, so the results
+// are bitwise the same; the two products of a double-angle step run in one
+// pass (they share no output).
+//
+// At these orders a matrix's arithmetic takes a few microseconds, so the
+// kernel is laid out against memory latency: the workgroups take the queue's
+// entries round robin (entry w + k G for workgroup w of G: no queue atomic),
+// the entry's index, then its order and offset, then its elements are loaded
+// three, two and one matrices ahead, and the scheme's products read a compact
+// copy of the level's recorded stages that the workgroup stages in LDS per
+// matrix (one round trip instead of a chain of dependent loads per product).
+// ----------------------------------------------------------------------------
+constexpr int SLD = SNP + 1;
+constexpr int SSLOT = SNP * SLD;          // elements per LDS slot
+constexpr int SPF = SNP * SNP / BNT;      // prefetched input elements per thread
+constexpr int SKK = SNP / 4;              // MFMA k steps at the largest order
+
+// One recorded product in the form the LDS-resident kernel reads: operand and
+// output ids as in the templates (0: padded copy of A, k + 1: W_k, ID_COUT,
+// ID_SOUT), epilogue inputs as W slots, scales with SX_SENTINEL for 2^-s.
+struct SmallOp {
+  int8_t nseg, nin, nout, pad;
+  int8_t L[MAX_SEG], R[MAX_SEG];
+  int8_t in[MAX_IN];
+  int8_t out[MAX_OUT];
+  int8_t pad2[2];
+  double lsc[MAX_SEG], rsc[MAX_SEG];
+  double e[MAX_OUT], d[MAX_OUT];
+  double c[MAX_OUT][MAX_IN];
+};
+static_assert(sizeof(SmallOp) % 8 == 0, "SmallOp copies as 8-byte words");
+__device__ SmallOp g_small[4][8];
+
+template <typename T>
+__device__ inline void small_load_a(const BatchArgs& a, int n, int64_t off, int tid, T (&v)[SPF]) {
+  const int np = (n + 15) & ~15;
+  const T* Ai = (const T*)a.A + off;
+#pragma unroll
+  for (int u = 0; u < SPF; ++u) {
+    const int e = tid + u * BNT;
+    const int r = np > 0 ? e / np : 0, c = np > 0 ? e - r * np : 0;
+    v[u] = (n > 0 && e < np * np && r < n && c < n) ? Ai[r * n + c] : (T)0;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BNT) void batched_small_kernel(BatchArgs a) {
+  using M = BMma<T>;
+  using acc_t = typename M::acc_t;
+  __shared__ __attribute__((aligned(16))) T W[9 * SSLOT];
+  __shared__ SmallOp ops[8];
+  __shared__ unsigned long long colbits[SNP];
+  __shared__ sincosm_plan s_plan;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lr = lane & 15, lg = lane >> 4;
+  const int bm = wave >> 1, bn = wave & 1;   // this wave's output block
+  const int nl = (int)*a.nlarge, nq = (int)*a.nqueue;
+  const int G = (int)gridDim.x;
+  T* const TMP = W + 8 * SSLOT;               // the padded copy of A passes through W8's slot
+
+  // entry q of this workgroup's share: queue position nl + blockIdx.x + q G.
+  // Loaded values are checked only when the next iteration uses them, so no
+  // load issued for the entries ahead is waited for before this matrix's work.
+  auto pos_of = [&](int q) { return nl + (int)blockIdx.x + q * G; };
+  auto valid_i = [&](int i) { return i >= 0 && i < a.batch ? i : -1; };
+  auto valid_n = [&](int n) { return n >= 1 && n <= SNP ? n : 0; };
+  int i0 = pos_of(0) < nq ? valid_i(a.order[pos_of(0)]) : -1;
+  int n0 = i0 >= 0 ? valid_n(a.nmat[i0]) : 0;
+  int64_t off0 = n0 > 0 ? a.off[i0] : 0;
+  int i1 = pos_of(1) < nq ? valid_i(a.order[pos_of(1)]) : -1;
+  int n1 = i1 >= 0 ? valid_n(a.nmat[i1]) : 0;
+  int64_t off1 = n1 > 0 ? a.off[i1] : 0;
+  int i2 = pos_of(2) < nq ? valid_i(a.order[pos_of(2)]) : -1;
+  T cur[SPF], nxt[SPF];
+  small_load_a<T>(a, n0, off0, tid, cur);
+  for (int q = 0; pos_of(q) < nq; ++q) {
+    small_load_a<T>(a, n1, off1, tid, nxt);                      // elements of entry q + 1
+    const int i3raw = pos_of(q + 3) < nq ? a.order[pos_of(q + 3)] : -1;   // index of entry q + 3
+    const int n2raw = i2 >= 0 ? a.nmat[i2] : 0;                  // order and offset of entry q + 2
+    const int64_t off2raw = i2 >= 0 ? a.off[i2] : 0;
+
+    const int n = __builtin_amdgcn_readfirstlane(n0), i = __builtin_amdgcn_readfirstlane(i0);
+    if (n > 0) {
+      const int np = (n + 15) & ~15;
+      const int nkk = np >> 2;
+      const bool mine = bm * 16 < np && bn * 16 < np;   // wave-uniform
+      T* Ci = (T*)a.C + off0;
+      T* Si = (T*)a.S + off0;
+      // padded copy through LDS: the column sums (rows in order, in float64)
+      // and each wave's operand fragments of A
+#pragma unroll
+      for (int u = 0; u < SPF; ++u) {
+        const int e = tid + u * BNT;
+        if (e < np * np) {
+          const int r = e / np, c = e - r * np;
+          TMP[r * SLD + c] = cur[u];
+        }
+      }
+      __syncthreads();
+      T La[SKK], Rb[SKK];
+#pragma unroll
+      for (int kk = 0; kk < SKK; ++kk) {
+        La[kk] = (T)0;
+        Rb[kk] = (T)0;
+        if (mine && kk < nkk) {
+          La[kk] = TMP[(bm * 16 + lr) * SLD + kk * 4 + lg];
+          Rb[kk] = TMP[(kk * 4 + lg) * SLD + bn * 16 + lr];
+        }
+      }
+      if (tid < 64) {
+        // column sums on lanes 0 .. np - 1 of wave 0, then their maximum (an
+        // integer compare of the float64 bit patterns, as batched_kernel's tree)
+        unsigned long long bits = 0ull;
+        if (tid < np) {
+          double sum = 0.0;
+          for (int r = 0; r < np; ++r) sum += fabs((double)TMP[r * SLD + tid]);
+          bits = (unsigned long long)__double_as_longlong(sum);
+        }
+#pragma unroll
+        for (int w = 32; w > 0; w >>= 1) {
+          const unsigned long long o = __shfl_xor(bits, w);
+          bits = o > bits ? o : bits;
+        }
+        if (tid == 0) {
+          sincosm_plan p;
+          plan_rule(__longlong_as_double((long long)bits), a.acc, &p);
+          s_plan = p;
+          if (a.plans) a.plans[i] = p;
+        }
+      }
+      __syncthreads();
+      const sincosm_plan plan = s_plan;
+      if (plan.status != SINCOSM_OK) {
+        const T nanv = (T)__longlong_as_double(0x7ff8000000000000ll);
+        for (int e = tid; e < n * n; e += BNT) { Ci[e] = nanv; Si[e] = nanv; }
+      } else {
+        const int li = __builtin_amdgcn_readfirstlane(level_index(plan.level));
+        const int s = __builtin_amdgcn_readfirstlane(plan.s);
+        const double sx = ldexp(1.0, -s);
+        int c0, s0, c1, s1;
+        squaring_slots(li, c0, s0, c1, s1);
+        c0 -= 1; s0 -= 1; c1 -= 1; s1 -= 1;    // ids -> LDS slots
+        const int nst = g_tmpl_count[li];
+        {  // the level's stages into LDS, one 8-byte word per thread
+          const unsigned long long* src = (const unsigned long long*)&g_small[li][0];
+          unsigned long long* dst = (unsigned long long*)&ops[0];
+          const int words = nst * (int)(sizeof(SmallOp) / 8);
+          for (int w = tid; w < words; w += BNT) dst[w] = src[w];
+        }
+        __syncthreads();
+        for (int t = 0; t < nst; ++t) {
+          const SmallOp& P = ops[t];
+          if (mine) {
+            acc_t acc;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[r] = (T)0;
+            const int nseg = P.nseg;
+            for (int g = 0; g < nseg; ++g) {
+              const int idl = P.L[g], idr = P.R[g];
+              const T ls = (T)(P.lsc[g] == SX_SENTINEL ? sx : P.lsc[g]);
+              const T rs = (T)(P.rsc[g] == SX_SENTINEL ? sx : P.rsc[g]);
+              // (the padded copy of A comes from the fragments; its slot is never read)
+              const T* L = W + (idl == ID_AP ? 0 : idl - 1) * SSLOT + (bm * 16 + lr) * SLD + lg;
+              const T* R = W + (idr == ID_AP ? 0 : idr - 1) * SSLOT + lg * SLD + bn * 16 + lr;
+#pragma unroll
+              for (int kk = 0; kk < SKK; ++kk) {
+                if (kk < nkk) {
+                  const T av = idl == ID_AP ? La[kk] : L[kk * 4];
+                  const T bv = idr == ID_AP ? Rb[kk] : R[kk * 4 * SLD];
+                  acc = M::mma(av * ls, bv * rs, acc);
+                }
+              }
+            }
+            const int nin = P.nin, nout = P.nout;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = bm * 16 + M::row_in_block(lg, r), col = bn * 16 + lr;
+              T x[MAX_IN];
+#pragma unroll
+              for (int qi = 0; qi < MAX_IN; ++qi)
+                if (qi < nin) x[qi] = W[P.in[qi] * SSLOT + row * SLD + col];
+              for (int o = 0; o < nout; ++o) {
+                T y = (row == col && row < n) ? (T)P.d[o] : (T)0;
+                y = __builtin_fma((T)P.e[o], acc[r], y);
+#pragma unroll
+                for (int qi = 0; qi < MAX_IN; ++qi)
+                  if (qi < nin) y = __builtin_fma((T)P.c[o][qi], x[qi], y);
+                const int id = P.out[o];
+                if (id == ID_COUT || id == ID_SOUT) {
+                  if (s == 0) {
+                    if (row < n && col < n) (id == ID_COUT ? Ci : Si)[row * n + col] = y;
+                  } else {
+                    W[(id == ID_COUT ? c0 : s0) * SSLOT + row * SLD + col] = y;
+                  }
+                } else {
+                  W[(id - 1) * SSLOT + row * SLD + col] = y;
+                }
+              }
+            }
+          }
+          __syncthreads();
+        }
+        // double-angle steps: P = S S -> C' = I - 2 P, Q = S C -> S' = 2 Q
+        for (int j = 0; j < s; ++j) {
+          const bool last = j == s - 1;
+          const int sc = (j & 1) ? s1 : s0, cc = (j & 1) ? c1 : c0;
+          const int sn = (j & 1) ? s0 : s1, cn = (j & 1) ? c0 : c1;
+          if (mine) {
+            acc_t pa, qa;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) { pa[r] = (T)0; qa[r] = (T)0; }
+            const T* L = W + sc * SSLOT + (bm * 16 + lr) * SLD + lg;
+            const T* RS = W + sc * SSLOT + lg * SLD + bn * 16 + lr;
+            const T* RC = W + cc * SSLOT + lg * SLD + bn * 16 + lr;
+#pragma unroll
+            for (int kk = 0; kk < SKK; ++kk) {
+              if (kk < nkk) {
+                const T av = L[kk * 4];
+                pa = M::mma(av, RS[kk * 4 * SLD], pa);
+                qa = M::mma(av, RC[kk * 4 * SLD], qa);
+              }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = bm * 16 + M::row_in_block(lg, r), col = bn * 16 + lr;
+              T yc = (row == col && row < n) ? (T)1.0 : (T)0;
+              yc = __builtin_fma((T)-2.0, pa[r], yc);
+              const T ys = __builtin_fma((T)2.0, qa[r], (T)0);
+              if (last) {
+                if (row < n && col < n) {
+                  Ci[row * n + col] = yc;
+                  Si[row * n + col] = ys;
+                }
+              } else {
+                W[cn * SSLOT + row * SLD + col] = yc;
+                W[sn * SSLOT + row * SLD + col] = ys;
+              }
+            }
+          }
+          __syncthreads();
+        }
+      }
+    }
+    // advance the pipeline
+    i0 = i1; n0 = n1; off0 = off1;
+    i1 = i2; n1 = i2 >= 0 ? valid_n(n2raw) : 0; off1 = n1 > 0 ? off2raw : 0;
+    i2 = valid_i(i3raw);
+#pragma unroll
+    for (int u = 0; u < SPF; ++u) cur[u] = nxt[u];
+  }
+}
+
 // Templates are recorded once per process and copied to each device on first use.
 std::mutex tmpl_mu;
 bool tmpl_built = false;
 Problem tmpl_host[4][8];
+SmallOp small_host[4][8];
 int tmpl_count_host[4];
 std::map<int, bool> tmpl_uploaded;
 
@@ -560,6 +864,36 @@ sincosm_status build_templates() {
     }
     tmpl_count_host[li] = rec.count;
   }
+  // the same stages in the LDS-resident kernel's compact form
+  memset(small_host, 0, sizeof(small_host));
+  for (int li = 0; li < 4; ++li)
+    for (int t = 0; t < tmpl_count_host[li]; ++t) {
+      const Problem& P = tmpl_host[li][t];
+      SmallOp& o = small_host[li][t];
+      if (P.nseg > MAX_SEG || P.nin > MAX_IN || P.nout > MAX_OUT) return SINCOSM_E_ARG;
+      o.nseg = (int8_t)P.nseg;
+      o.nin = (int8_t)P.nin;
+      o.nout = (int8_t)P.nout;
+      for (int q = 0; q < P.nseg; ++q) {
+        o.L[q] = (int8_t)((intptr_t)P.seg[q].L - 1);
+        o.R[q] = (int8_t)((intptr_t)P.seg[q].R - 1);
+        o.lsc[q] = P.seg[q].lscale;
+        o.rsc[q] = P.seg[q].rscale;
+      }
+      for (int q = 0; q < P.nin; ++q) {
+        const intptr_t id = (intptr_t)P.in[q].p - 1;
+        if (id < 1 || id > 9) return SINCOSM_E_ARG;   // epilogue inputs are W slots
+        o.in[q] = (int8_t)(id - 1);
+      }
+      for (int q = 0; q < P.nout; ++q) {
+        const intptr_t id = (intptr_t)P.out[q].p - 1;
+        if (id < 1 || id > ID_SOUT) return SINCOSM_E_ARG;
+        o.out[q] = (int8_t)id;
+        o.e[q] = P.out[q].e;
+        o.d[q] = P.out[q].d;
+        for (int k = 0; k < MAX_IN; ++k) o.c[q][k] = P.out[q].c[k];
+      }
+    }
   tmpl_built = true;
   return SINCOSM_OK;
 }
@@ -574,6 +908,8 @@ sincosm_status ensure_templates(hipStream_t stream) {
                                 stream));
   SC_HIP(hipMemcpyToSymbolAsync(HIP_SYMBOL(g_tmpl_count), tmpl_count_host, sizeof(tmpl_count_host), 0,
                                 hipMemcpyHostToDevice, stream));
+  SC_HIP(hipMemcpyToSymbolAsync(HIP_SYMBOL(g_small), small_host, sizeof(small_host), 0, hipMemcpyHostToDevice,
+                                stream));
   SC_HIP(hipStreamSynchronize(stream));
   tmpl_uploaded[dev] = true;
   return SINCOSM_OK;
@@ -591,8 +927,9 @@ int device_cus() {
   return cus;
 }
 
-// Workspace: the queue counter and length (256 bytes), the work queue, then one
-// arena slot of 10 padded matrices of order npm per resident workgroup.
+// Workspace: the queue counters (256 bytes: next entry, length, first entry
+// of the LDS-resident kernel), the work queue, then one arena
+// slot of 10 padded matrices of order npm per resident workgroup.
 bool batch_layout(int64_t batch, int npm, int dtype, BatchLayout& L) {
   const int cus = device_cus();
   if (cus <= 0) return false;
@@ -662,6 +999,7 @@ sincosm_status sincosm_eval_batched(int64_t batch, int dtype, const int32_t* n_d
   char* base = (char*)ws;
   unsigned int* counter = (unsigned int*)(base + L.counter_off);
   unsigned int* nqueue = counter + 1;
+  unsigned int* nlarge = counter + 2;
   int32_t* order = (int32_t*)(base + L.order_off);
   BatchArgs a;
   a.batch = (int)batch;
@@ -677,11 +1015,25 @@ sincosm_status sincosm_eval_batched(int64_t batch, int dtype, const int32_t* n_d
   a.arena = base + L.arena_off;
   a.slot_bytes = (int64_t)L.slot_bytes;
   a.counter = counter;
-  for (int b = 0; b <= NMAX / 16; ++b)   // product tile per padded order, from the tuning table
-    a.tile32[b] = (int8_t)(batched_tile(dtype == SINCOSM_F64 ? Arith::F64 : Arith::F32, 16 * b) == 32);
+  a.nlarge = nlarge;
+  // product mode per padded order, from the tuning table
+  const Arith ar = dtype == SINCOSM_F64 ? Arith::F64 : Arith::F32;
+  unsigned int lds_mask = 0u;
+  for (int b = 0; b <= NMAX / 16; ++b) {
+    const int tile = batched_tile(ar, 16 * b);
+    a.tile32[b] = (int8_t)(tile == 32 ? TILE_32 : tile == 0 ? LDS_RESIDENT : TILE_64);
+    if (tile == 0 && b >= 1 && b <= NSB) lds_mask |= 1u << b;
+  }
   const TimingMark t = timing_begin(SINCOSM_TIMING_BATCHED, stream);
-  batched_order_kernel<<<1, ORDER_THREADS, 0, stream>>>((int)batch, n_dev, offset_dev, total_elems, npm, order,
-                                                        counter, nqueue, plans_dev);
+  batched_order_kernel<<<1, ORDER_THREADS, 0, stream>>>((int)batch, n_dev, offset_dev, total_elems, npm,
+                                                        lds_mask, L.slots, order, counter, plans_dev);
+  if (lds_mask) {
+    // the smallest orders first: their workgroups are short, and the large
+    // orders then end the call with the queue's usual largest-first tail
+    const int g = (int)std::min<int64_t>(batch, (int64_t)device_cus() * SMALL_WG_PER_CU);
+    if (dtype == SINCOSM_F64) batched_small_kernel<double><<<g, BNT, 0, stream>>>(a);
+    else batched_small_kernel<float><<<g, BNT, 0, stream>>>(a);
+  }
   if (dtype == SINCOSM_F64) batched_kernel<double><<<L.slots, BNT, 0, stream>>>(a);
   else batched_kernel<float><<<L.slots, BNT, 0, stream>>>(a);
   timing_end(t, stream);

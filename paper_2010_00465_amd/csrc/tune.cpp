@@ -19,16 +19,20 @@ namespace {
 //      equal problems can leave CUs idle here, so this class is tuned on its
 //      own and falls back to the single-product entries.
 // Classes 1 and 2 use class 0 entries when none of their own matches.
-// Class 3 holds the batched kernel's output tile per padded order instead of
-// a configuration of the product kernel (0: 64 x 64, the default; 1: 32 x 32).
+// Class 3 holds the batched kernel's product mode per padded order instead of
+// a configuration of the product kernel (0: 64 x 64 output tiles, the
+// default; 1: 32 x 32; 2: the LDS-resident kernel, padded orders up to 32
+// only, 64 x 64 above).
 struct TuneEntry { int ar; int cls; int64_t lo, hi; int idx; };
 std::mutex tune_mu;
 std::vector<TuneEntry> tune_table;
 
 constexpr int TUNE_FLAGS = SINCOSM_TUNE_MULTI | SINCOSM_TUNE_UNEVEN | SINCOSM_TUNE_BATCHED;
 constexpr int BATCHED_CLASS = 3;
-// Output tiles of the batched kernel, by configuration index.
-const int kBatchedTile[] = {64, 32};
+// Output tiles of the batched kernel, by configuration index (0: the whole
+// matrix in LDS).
+const int kBatchedTile[] = {64, 32, 0};
+constexpr int kLdsMaxOrder = 32;
 
 }  // namespace
 
@@ -45,7 +49,9 @@ int tuned_cfg(Arith ar, int cls, int64_t np) {
 int batched_tile(Arith ar, int64_t np) {
   const int idx = tuned_cfg(ar, BATCHED_CLASS, np);
   const int count = (int)(sizeof(kBatchedTile) / sizeof(kBatchedTile[0]));
-  return idx < 0 || idx >= count ? 64 : kBatchedTile[idx];
+  if (idx < 0 || idx >= count) return 64;
+  if (kBatchedTile[idx] == 0 && np > kLdsMaxOrder) return 64;
+  return kBatchedTile[idx];
 }
 
 }  // namespace sc
@@ -65,6 +71,13 @@ sincosm_status sincosm_tune_config_info(int arith, int idx, int32_t* info) {
   if (t && info && (arith & SINCOSM_TUNE_BATCHED)) {
     if (idx < 0 || idx >= sincosm_tune_num_configs(arith)) return SINCOSM_E_ARG;
     const int tb = sc::kBatchedTile[idx];   // four waves of tb/2 x tb/2, k depth 16, staged
+    if (tb == 0) {
+      // LDS-resident: four waves of 16 x 16 blocks over orders up to 32,
+      // k depth 4, 2 workgroups per CU, "direct" = 2 marks the mode
+      info[0] = sc::kLdsMaxOrder; info[1] = sc::kLdsMaxOrder; info[2] = 4; info[3] = 2; info[4] = 2;
+      info[5] = 2; info[6] = 2; info[7] = 1;
+      return SINCOSM_OK;
+    }
     info[0] = tb; info[1] = tb; info[2] = 16; info[3] = 2; info[4] = 2; info[5] = 3;
     info[6] = 0; info[7] = 1;
     return SINCOSM_OK;

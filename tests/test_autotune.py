@@ -72,7 +72,8 @@ def test_shipped_cache_matches_table_and_applies(lib):
         have = autotune.configs(arith)
         assert data["configs"][arith] == have[:len(data["configs"][arith])]   # the library may append
         if arith + "_batched" in data["configs"]:
-            assert data["configs"][arith + "_batched"] == autotune.configs(arith, autotune.BATCHED)
+            tuned = data["configs"][arith + "_batched"]
+            assert tuned == autotune.configs(arith, autotune.BATCHED)[:len(tuned)]
     expected = sum(len(v) for v in data["entries"].values())
     assert autotune.apply_cache() == expected
 
@@ -121,21 +122,22 @@ def test_uneven_class_flag(lib):
 
 
 def test_batched_class_flag(lib):
-    """SINCOSM_TUNE_BATCHED addresses the batched kernel's tile table: two configurations
-    (64 x 64 and 32 x 32 output tiles); no other class flag may accompany it."""
+    """SINCOSM_TUNE_BATCHED addresses the batched kernel's mode table: three configurations
+    (64 x 64 and 32 x 32 output tiles, and the LDS-resident kernel, which reports order 32 as
+    its size and 2 as its "direct" field); no other class flag may accompany it."""
     from paper_2010_00465_amd import autotune
     info = (ctypes.c_int32 * 8)()
     for arith in (0, 1):
         code = arith | autotune.BATCHED
-        assert lib.sincosm_tune_num_configs(code) == 2
-        tiles = []
-        for i in range(2):
+        assert lib.sincosm_tune_num_configs(code) == 3
+        modes = []
+        for i in range(3):
             assert lib.sincosm_tune_config_info(code, i, info) == 0
-            tiles.append((info[0], info[1], info[3], info[4]))
-        assert tiles == [(64, 64, 2, 2), (32, 32, 2, 2)]
-        assert lib.sincosm_tune_config_info(code, 2, info) == -1
-        assert lib.sincosm_tune_set(code, 1 << 40, 1 << 41, 2) == -1
-        assert lib.sincosm_tune_set(code, 1 << 40, 1 << 41, 1) == 0
+            modes.append((info[0], info[1], info[3], info[4], info[6]))
+        assert modes == [(64, 64, 2, 2, 0), (32, 32, 2, 2, 0), (32, 32, 2, 2, 2)]
+        assert lib.sincosm_tune_config_info(code, 3, info) == -1
+        assert lib.sincosm_tune_set(code, 1 << 40, 1 << 41, 3) == -1
+        assert lib.sincosm_tune_set(code, 1 << 40, 1 << 41, 2) == 0
         assert lib.sincosm_tune_set(code, 1 << 40, 1 << 41, -1) == 0
         for other in (autotune.MULTI, autotune.UNEVEN):
             assert lib.sincosm_tune_set(code | other, 1 << 40, 1 << 41, 0) == -1

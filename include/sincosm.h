@@ -33,6 +33,10 @@
  *    settings and device.
  *  - Errors in arguments are returned synchronously and leave outputs
  *    untouched. n = 0 is a no-op returning SINCOSM_OK.
+ *  - Environment: SINCOSM_LOG set to a value other than "" or "0" prints
+ *    one line to stderr for every plan read back to the host (the calls that
+ *    wait for their plan: entry name, n, level, s, products, norm1, status);
+ *    it is read once, at the first such call.
  */
 #ifndef SINCOSM_H
 #define SINCOSM_H

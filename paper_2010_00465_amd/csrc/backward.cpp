@@ -328,7 +328,7 @@ sincosm_status sincosm_backward(int64_t n, int dtype, const void* A, int64_t lda
   const NormScratch ns = norm_scratch(base + L0.norm_off, m.np);
   SC_TRY(launch_norm_copy_plan(n, m.np, A, lda, true, nullptr, true, acc, ns, stream));
   sincosm_plan plan;
-  SC_TRY(read_plan(ns.plan, &plan, stream));
+  SC_TRY(read_plan(ns.plan, &plan, stream, 1, "sincosm_backward", n));
   if (plan_host) *plan_host = plan;
   if (plan.status != SINCOSM_OK) {
     SC_TRY(launch_fill_nan(n, gA, ldga, true, stream));

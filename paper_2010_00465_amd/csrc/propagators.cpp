@@ -48,7 +48,7 @@ sincosm_status sincosm_expi_eval(int64_t n, int dtype, const void* A, int64_t ld
   void* Xp = base + L.ap_off;
   SC_TRY(launch_norm_copy_plan(n, m.np, A, lda, m.user_f64, Xp, m.poly_f64, acc, ns, stream, 0, t));
   sincosm_plan plan;
-  SC_TRY(read_plan(ns.plan, &plan, stream));
+  SC_TRY(read_plan(ns.plan, &plan, stream, 1, "sincosm_expi_eval", n));
   if (plan_host) *plan_host = plan;
   if (plan.status != SINCOSM_OK) {
     SC_TRY(launch_fill_nan_rect(n, 2 * n, U, 2 * ldu, m.user_f64, stream));

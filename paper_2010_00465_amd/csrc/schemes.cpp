@@ -44,6 +44,9 @@
 
 #include <mutex>
 
+#include <cstdio>
+#include <cstdlib>
+
 #include "schemes.hpp"
 #include "coeffs.hpp"
 
@@ -164,7 +167,18 @@ std::mutex plan_slot_mu;
 sincosm_plan* plan_slots = nullptr;
 bool plan_slot_busy[PLAN_SLOTS];
 
-sincosm_status read_plan(const sincosm_plan* dev, sincosm_plan* host, hipStream_t stream, int count) {
+// SINCOSM_LOG set to a non-empty value other than "0": every plan read back
+// to the host is printed to stderr, one line per call (read once).
+static bool plan_log_on() {
+  static const bool on = [] {
+    const char* v = std::getenv("SINCOSM_LOG");
+    return v && v[0] && !(v[0] == '0' && v[1] == 0);
+  }();
+  return on;
+}
+
+sincosm_status read_plan(const sincosm_plan* dev, sincosm_plan* host, hipStream_t stream, int count,
+                         const char* who, int64_t n) {
   if (count < 1 || count > 2) return SINCOSM_E_ARG;
   int slot = -1;
   {
@@ -184,6 +198,10 @@ sincosm_status read_plan(const sincosm_plan* dev, sincosm_plan* host, hipStream_
     std::lock_guard<std::mutex> g(plan_slot_mu);
     plan_slot_busy[slot] = false;
   }
+  if (e == hipSuccess && plan_log_on())
+    std::fprintf(stderr, "[sincosm] %s n=%lld: level %d s %d products %d norm1 %.6e status %d\n",
+                 who ? who : "plan", (long long)n, host[0].level, host[0].s, host[0].products, host[0].norm1,
+                 host[0].status);
   return e == hipSuccess ? SINCOSM_OK : SINCOSM_E_HIP;
 }
 

@@ -56,7 +56,10 @@ GemmLaunch two(const Problem& p0, const Problem& p1, int np);
 GemmLaunch three(const Problem& p0, const Problem& p1, const Problem& p2, int np);
 bool modes_for(int64_t n, int dtype, int prod, Modes& m);
 Layout layout_for(const Modes& m);
-sincosm_status read_plan(const sincosm_plan* dev, sincosm_plan* host, hipStream_t stream, int count = 1);
+// Copy `count` plan records from the device and wait for them; with SINCOSM_LOG
+// set, the first is printed to stderr tagged with `who` and n.
+sincosm_status read_plan(const sincosm_plan* dev, sincosm_plan* host, hipStream_t stream, int count = 1,
+                         const char* who = nullptr, int64_t n = 0);
 bool overlaps(const void* a, int64_t lda, const void* b, int64_t ldb, int64_t n, size_t es);
 Target internal(void* p, const Modes& m, bool f64);
 sincosm_status gemm(Run& r, Arith ar, const GemmLaunch& g, int kind = -1);

@@ -243,7 +243,7 @@ sincosm_status sincosm_plan_device(int64_t n, int dtype, const void* A, int64_t 
   hipStream_t stream = (hipStream_t)stream_;
   const NormScratch ns = norm_scratch(ws, n);
   SC_TRY(launch_norm_copy_plan(n, n, A, lda, dtype == SINCOSM_F64, nullptr, true, acc, ns, stream));
-  return read_plan(ns.plan, plan_host, stream);
+  return read_plan(ns.plan, plan_host, stream, 1, "sincosm_plan_device", n);
 }
 
 size_t sincosm_workspace_size(int64_t n, int dtype, int acc, int prod) {
@@ -289,9 +289,9 @@ sincosm_status sincosm_eval(int64_t n, int dtype, const void* A, int64_t lda, vo
     add_out(p, internal(r.W[0], m, m.poly_f64), 1.0, 0.0, {});
     SC_TRY(gemm(r, m.poly, one(p, (int)m.np)));
     SC_TRY(launch_norm_sq_plan(n, m.np, r.W[0], m.poly_f64, acc, ns, stream));
-    SC_TRY(read_plan(ns.plan, plans, stream, 2));
+    SC_TRY(read_plan(ns.plan, plans, stream, 2, "sincosm_eval", n));
   } else {
-    SC_TRY(read_plan(ns.plan, plans, stream));
+    SC_TRY(read_plan(ns.plan, plans, stream, 1, "sincosm_eval", n));
   }
   const sincosm_plan plan = plans[0];
   if (plan_host) *plan_host = plan;

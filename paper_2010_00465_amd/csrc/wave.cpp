@@ -223,7 +223,7 @@ static sincosm_status wave_prologue(int64_t n, const void* A, int64_t lda, doubl
   const NormScratch ns = norm_scratch(c.base + c.L.norm_off, c.m.np);
   SC_TRY(launch_norm_copy_plan(n, c.m.np, A, lda, c.m.user_f64, c.base + c.L.ap_off, c.m.poly_f64, acc, ns,
                                c.stream, 1, t * t));
-  return read_plan(ns.plan, &c.plan, c.stream);
+  return read_plan(ns.plan, &c.plan, c.stream, 1, "wave", n);
 }
 
 // The wave scheme and the s double-angle steps. With user targets the last

@@ -562,3 +562,25 @@ def test_refined_edge_cases(env):
     # same launches, so they agree bit for bit, NaN and Inf included)
     same = lambda X, Y: torch.equal(torch.nan_to_num(X), torch.nan_to_num(Y))
     assert same(C, C0) and same(S, S0)
+
+
+def test_plan_log_env(env):
+    """SINCOSM_LOG=1: each plan read back to the host is printed to stderr (a child process,
+    since the variable is read once per process)."""
+    import os
+    import subprocess
+    import sys as _sys
+    code = ("import torch, numpy as np, paper_2010_00465_amd as sc, workloads as W\n"
+            "A = torch.from_numpy(W.gaussian(64, 8.0, key=(5,))).cuda()\n"
+            "C, S = torch.empty_like(A), torch.empty_like(A)\n"
+            "sc.sincosm_eval(A, C, S)\n"
+            "sc.sincosm_wave_eval(A, 0.5, C, S)\n"
+            "torch.cuda.synchronize()\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    envv = dict(os.environ, SINCOSM_LOG="1", PYTHONPATH=root)
+    r = subprocess.run([_sys.executable, "-c", code], cwd=root, env=envv, capture_output=True, text=True,
+                       timeout=240)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [l for l in r.stderr.splitlines() if l.startswith("[sincosm]")]
+    assert any(l.startswith("[sincosm] sincosm_eval n=64: level 7 s 3 products 13") for l in lines), lines
+    assert any(l.startswith("[sincosm] wave n=64: level") for l in lines), lines

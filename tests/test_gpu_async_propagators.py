@@ -340,3 +340,51 @@ def test_expi_async_graph_capture_no_plan(env):
         assert torch.equal(U, Ue), e
         seen.add((rec.level, rec.s))
     assert len(seen) == 4
+
+
+@pytest.mark.parametrize("products", ["f32", "bf16x3"])
+def test_expi_async_tiers_bitwise(env, products):
+    """Lowered-product tiers on float64 data: the device-planned e^{-itA} equals the synchronous
+    call bitwise (same launches, plan decided on the device)."""
+    torch, sc = env
+    say("expi async tier", products)
+    A = torch.from_numpy(W.gaussian(300, 2.0 ** 5, key=(174,))).cuda()
+    (U0, p0), (U1, p1) = expi_both(env, A, 0.8, "single", products)
+    assert (p1.level, p1.s) == (p0.level, p0.s)
+    assert torch.equal(U0, U1)
+
+
+@pytest.mark.parametrize("norm", [0.1, 0.81])
+def test_expi_async_extended_plan(env, norm):
+    """With the 5-product scheme among the candidates (it wins on (theta_4, theta_5])."""
+    torch, sc = env
+    A = torch.from_numpy(W.gaussian(150, norm, key=(175, int(norm * 10)))).cuda()
+    acc = "double" if norm < 0.5 else "single"
+    U0 = torch.empty(A.shape, dtype=torch.complex128, device="cuda")
+    p0 = sc.sincosm_expi_eval(A, 1.0, U0, acc, extended=True)
+    U1 = torch.empty_like(U0)
+    pd = torch.zeros(sc.PLAN_BYTES, dtype=torch.uint8, device="cuda")
+    sc.sincosm_expi_eval_async(A, 1.0, U1, 8, acc, plan_dev=pd, extended=True)
+    torch.cuda.synchronize()
+    p1 = sc.plan_from_device(pd)
+    assert (p1.level, p1.s) == (p0.level, p0.s) and p0.level == 5
+    assert torch.equal(U0, U1)
+
+
+@pytest.mark.parametrize("n", [64, 257])
+def test_wave_block_async_float32(env, n):
+    """Float32 storage, single plan: the device-planned block propagator against the synchronous
+    one (C blocks bitwise, the s blocks to float32 rounding) and against the oracle at 5e-6."""
+    torch, sc = env
+    say("block async f32", n)
+    t = 0.9
+    A32 = W.gaussian(n, 2.0 ** 4 / (t * t), key=(176, n)).astype(np.float32)
+    A = torch.from_numpy(A32).cuda()
+    E0 = torch.empty(2 * n, 2 * n, dtype=torch.float32, device="cuda")
+    sc.sincosm_wave_block_eval(A, t, E0, "single")
+    E1 = torch.empty_like(E0)
+    sc.sincosm_wave_block_eval_async(A, t, E1, 8, "single")
+    torch.cuda.synchronize()
+    assert torch.equal(E1[:n, :n], E0[:n, :n]) and torch.equal(E1[n:, n:], E0[n:, n:])
+    assert rel_fro(np64(E1), np64(E0)) <= 1e-6
+    assert rel_fro(np64(E1), Pr.symplectic_paper(A32.astype(np.float64), t, "single")) <= 5e-6

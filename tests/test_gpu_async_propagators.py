@@ -388,3 +388,30 @@ def test_wave_block_async_float32(env, n):
     assert torch.equal(E1[:n, :n], E0[:n, :n]) and torch.equal(E1[n:, n:], E0[n:, n:])
     assert rel_fro(np64(E1), np64(E0)) <= 1e-6
     assert rel_fro(np64(E1), Pr.symplectic_paper(A32.astype(np.float64), t, "single")) <= 5e-6
+
+
+def test_wave_async_n4096(env):
+    """The headline order (tuned 256 x 128 double-angle launches): ||t^2 A||_1 = 2^10, s = 4;
+    C bitwise equal to the synchronous call, S to 1e-13, both against the closed form of the
+    1-D Laplacian family on sampled rows."""
+    torch, sc = env
+    say("wave async n=4096")
+    n, t = 4096, 1.0
+    A_np = W.laplacian_1d(n, 2.0 ** 10)
+    A = torch.from_numpy(A_np).cuda()
+    (C0, S0, p0), (C1, S1, p1) = wave_both(env, A, t)
+    assert (p1.level, p1.s, p1.status) == (p0.level, p0.s, 0) and p1.s >= 3
+    assert torch.equal(C0, C1)
+    assert rel_fro(np64(S1), np64(S0)) <= 1e-13
+    del C0, S0
+    # A = c tridiag(-1, 2, -1): its eigenpairs are known in closed form
+    rows = [0, 1, 2047, 4095]
+    c = 2.0 ** 10 / 4.0
+    k = np.arange(1, n + 1)
+    mu = 2.0 * c * (1.0 - np.cos(k * np.pi / (n + 1)))        # eigenvalues of A
+    V = np.sqrt(2.0 / (n + 1)) * np.sin(np.outer(np.arange(1, n + 1), k) * np.pi / (n + 1))
+    r = np.sqrt(mu)
+    Cr = (V[rows] * np.cos(t * r)) @ V.T
+    Sr = (V[rows] * (np.sin(t * r) / r)) @ V.T
+    C1r, S1r = np64(C1[rows]), np64(S1[rows])
+    assert rel_fro(C1r, Cr) <= 1e-12 and rel_fro(S1r, Sr) <= 1e-12

@@ -68,7 +68,7 @@ __host__ __device__ inline int level_index(int level) { return level == 3 ? 0 : 
 struct BatchArgs {
   int batch;
   int acc;
-  int8_t tile32[NMAX / 16 + 1];   // per padded order / 16: product mode (TILE_64, TILE_32 or LDS_RESIDENT)
+  int8_t mode[NMAX / 16 + 1];   // per padded order / 16: product mode (TILE_64, TILE_32 or LDS_RESIDENT)
   const int32_t* nmat;            // caller's orders (device)
   const int64_t* off;             // caller's element offsets (device)
   const int32_t* order;           // work queue: accepted entries, largest padded order first
@@ -432,7 +432,7 @@ __global__ __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(3))) void b
     const int np = (n + 15) & ~15;
     // log2 of the product tile (orders routed to the LDS-resident kernel that
     // this kernel takes instead, see batched_order_kernel, use 32 x 32)
-    const int lt = a.tile32[np >> 4] == TILE_64 ? 6 : 5;
+    const int lt = a.mode[np >> 4] == TILE_64 ? 6 : 5;
     const T* Ai = (const T*)a.A + off;
     T* Ci = (T*)a.C + off;
     T* Si = (T*)a.S + off;
@@ -1021,7 +1021,7 @@ sincosm_status sincosm_eval_batched(int64_t batch, int dtype, const int32_t* n_d
   unsigned int lds_mask = 0u;
   for (int b = 0; b <= NMAX / 16; ++b) {
     const int tile = batched_tile(ar, 16 * b);
-    a.tile32[b] = (int8_t)(tile == 32 ? TILE_32 : tile == 0 ? LDS_RESIDENT : TILE_64);
+    a.mode[b] = (int8_t)(tile == 32 ? TILE_32 : tile == 0 ? LDS_RESIDENT : TILE_64);
     if (tile == 0 && b >= 1 && b <= NSB) lds_mask |= 1u << b;
   }
   const TimingMark t = timing_begin(SINCOSM_TIMING_BATCHED, stream);

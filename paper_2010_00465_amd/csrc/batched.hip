@@ -18,6 +18,12 @@
 // batch. The stage descriptors of the four schemes are recorded once from the
 // same builders the single-matrix path launches (schemes.cpp), with symbolic
 // buffer ids resolved per matrix on the device.
+//
+// Padded orders 16 and 32 can instead run in a second kernel that keeps the
+// whole per-matrix workspace in LDS (batched_small_kernel, chosen per order
+// by the tuning table); the queue kernel routes them there only when few
+// larger matrices are queued, and then launches it before the persistent one.
+// All product modes give bitwise the same results.
 #include <math.h>
 #include <string.h>
 

@@ -344,9 +344,9 @@ sincosm_status sincosm_expi_eval_async(int64_t n, int dtype, const void* A, int6
  *   SINCOSM_E_WORKSPACE; a matrix with Inf/NaN gets NaN outputs and status
  *   SINCOSM_E_NONFINITE. The call enqueues a fixed sequence of two launches
  *   (entry checks and the largest-first work queue in one workgroup, then the
- *   persistent kernel; three when the tuning table routes padded orders 16 or
- *   32 to the LDS-resident kernel, which then runs before the persistent one
- *   on the smallest orders), reads nothing back and returns SINCOSM_OK for any
+ *   persistent kernel; one or two more when the tuning table routes small
+ *   padded orders to the LDS-resident kernels, which run before the persistent
+ *   one), reads nothing back and returns SINCOSM_OK for any
  *   entry values, so it can be captured in a HIP graph and replayed with new
  *   values in A, n_dev and offset_dev.
  *   ws / ws_bytes: 256-byte aligned; the size query's value for the batch
@@ -443,9 +443,9 @@ sincosm_status sincosm_timing_read(int kind, double* total_ms, int64_t* count);
  * sincosm_eval_batched runs a matrix's products by padded order: configuration
  * 0 is 64 x 64 output tiles (the default), 1 is 32 x 32 (both with the
  * per-matrix workspace in the caller's workspace), 2 keeps the whole
- * per-matrix workspace in LDS (a kernel of its own for padded orders up to
- * 32; larger orders given 2 use 64 x 64); all three give bitwise the same
- * results. The choice is read when sincosm_eval_batched is called (a captured
+ * per-matrix workspace in LDS (kernels of their own for padded orders up to
+ * 32 in float64 and 64 in float32; larger orders given 2 use 64 x 64); all
+ * three give bitwise the same results. The choice is read when sincosm_eval_batched is called (a captured
  * graph keeps the choice made at capture). More than one flag is an error. Host-side state shared by all
  * devices, thread-safe; results do not depend on it beyond rounding order. */
 enum { SINCOSM_TUNE_MULTI = 16, SINCOSM_TUNE_UNEVEN = 32, SINCOSM_TUNE_BATCHED = 64 };

@@ -19,11 +19,11 @@
 // same builders the single-matrix path launches (schemes.cpp), with symbolic
 // buffer ids resolved per matrix on the device.
 //
-// Padded orders 16 and 32 can instead run in a second kernel that keeps the
-// whole per-matrix workspace in LDS (batched_small_kernel, chosen per order
-// by the tuning table); the queue kernel routes them there only when few
-// larger matrices are queued, and then launches it before the persistent one.
-// All product modes give bitwise the same results.
+// Padded orders up to 32 (float64) or 64 (float32) can instead run in kernels
+// that keep the whole per-matrix workspace in LDS (batched_small_kernel,
+// chosen per order by the tuning table); the queue kernel routes them there
+// only when few larger matrices are queued, and they run before the
+// persistent one. All product modes give bitwise the same results.
 #include <math.h>
 #include <string.h>
 
@@ -43,11 +43,10 @@ constexpr int WG_PER_CU = 4;  // resident workgroups per CU the arena is sized f
 constexpr int NMAX = 256;     // largest order of the batched path
 // Per padded order: how its products run. TILE_64 / TILE_32: the arena in
 // global memory, output tiles of 64 x 64 or 32 x 32 (batched_kernel);
-// LDS_RESIDENT: the whole per-matrix workspace in LDS (batched_small_kernel,
-// padded orders up to SNP only).
+// LDS_RESIDENT: the whole per-matrix workspace in LDS (batched_small_kernel:
+// padded orders up to 32 in float64, up to 64 in float32).
 constexpr int TILE_64 = 0, TILE_32 = 1, LDS_RESIDENT = 2;
-constexpr int SNP = 32;       // largest padded order of the LDS-resident kernel
-constexpr int SMALL_WG_PER_CU = 2;   // resident LDS-resident workgroups per CU (76 KB of LDS each in float64)
+constexpr int SNP = 64;       // largest padded order of any LDS-resident kernel
 
 // symbolic buffer ids of the recorded templates
 constexpr int ID_AP = 0;      // 1..9: W0..W8
@@ -79,7 +78,8 @@ struct BatchArgs {
   const int64_t* off;             // caller's element offsets (device)
   const int32_t* order;           // work queue: accepted entries, largest padded order first
   const unsigned int* nqueue;     // its length
-  const unsigned int* nlarge;     // queue entries [0, nlarge) go to batched_kernel, the rest to the LDS kernel
+  const unsigned int* nlarge;     // queue entries [0, nlarge) go to batched_kernel, the rest to the LDS kernels
+  const unsigned int* nmid;       // [nlarge, nmid): LDS-resident, padded order 48 or 64; [nmid, nqueue): 16 or 32
   const void* A;
   void* C;
   void* S;
@@ -96,12 +96,14 @@ struct BatchArgs {
 // SINCOSM_E_WORKSPACE for an order beyond npm) in its plan record and is not
 // computed. Accepted entries are bucketed by padded order, largest first.
 // The padded orders whose bit is set in lds_mask (bit k: order 16 k, k <=
-// SNP / 16) go to the LDS-resident kernel, after all others in the queue, when
+// SNP / 16) go to the LDS-resident kernels, after all others in the queue, when
 // the other entries number fewer than `fill` (the persistent kernel's
 // workgroups): with more, those small matrices are worth more to the
 // persistent kernel as the short work that fills the end of its run, and the
 // whole queue stays its own. The queue's first *nlarge entries are
-// batched_kernel's, the rest batched_small_kernel's. The order within a
+// batched_kernel's; of the rest, those of padded orders 48 and 64 (float32
+// only) come first, up to *nmid, for the 64-order LDS-resident kernel, then
+// those of orders 16 and 32 for the 32-order one. The order within a
 // bucket does not matter (each matrix is computed by one workgroup the same
 // way wherever it sits in the queue, and both kernels give the same bits).
 constexpr int ORDER_THREADS = 1024;
@@ -117,7 +119,7 @@ __device__ inline int entry_status(int n, int64_t o, int64_t total, int npm) {
 }
 
 // Queue bucket of an accepted order: padded order 256 first ... 16 last, then
-// the LDS-resident orders (32 before 16).
+// the LDS-resident orders (64, 48, 32, 16).
 __device__ inline int queue_bucket(int n, unsigned int lds_mask) {
   const int k = (n + 15) >> 4;
   if (k <= NSB && ((lds_mask >> k) & 1u)) return NBUCKET + NSB - k;
@@ -168,7 +170,8 @@ __global__ __launch_bounds__(ORDER_THREADS) void batched_order_kernel(int batch,
     }
     counter[0] = 0u;            // next entry of batched_kernel
     counter[1] = run;           // queue length
-    counter[2] = next[NBUCKET]; // first entry of the LDS-resident kernel
+    counter[2] = next[NBUCKET]; // first entry of the LDS-resident kernels
+    counter[3] = next[NBUCKET + NSB - 2];   // first LDS-resident entry of padded order <= 32
   }
   __syncthreads();
   const unsigned int m = mask;
@@ -436,9 +439,11 @@ __global__ __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(3))) void b
     if (n < 1 || n > NMAX) continue;
     const int64_t off = a.off[i];
     const int np = (n + 15) & ~15;
-    // log2 of the product tile (orders routed to the LDS-resident kernel that
-    // this kernel takes instead, see batched_order_kernel, use 32 x 32)
-    const int lt = a.mode[np >> 4] == TILE_64 ? 6 : 5;
+    // log2 of the product tile (orders routed to an LDS-resident kernel that
+    // this kernel takes instead, see batched_order_kernel: 32 x 32 up to order
+    // 32, 64 x 64 above)
+    const int md = a.mode[np >> 4];
+    const int lt = (md == TILE_64 || (md == LDS_RESIDENT && np > 32)) ? 6 : 5;
     const T* Ai = (const T*)a.A + off;
     T* Ci = (T*)a.C + off;
     T* Si = (T*)a.S + off;
@@ -574,14 +579,17 @@ __global__ __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(3))) void b
 }
 
 // ----------------------------------------------------------------------------
-// LDS-resident kernel for padded orders up to SNP = 32. A matrix's whole
-// workspace stays on chip: W0 .. W8 in LDS (row stride SLD = SNP + 1, so the
-// rows an MFMA operand read touches start in different banks), and the padded
+// LDS-resident kernels for padded orders up to SN (32: float64, and float32
+// orders 16 and 32; 64: float32 orders 48 and 64). A matrix's whole workspace
+// stays on chip: W0 .. W8 in LDS (row stride SN + 1, so the rows an MFMA
+// operand read touches start in different banks; 76 KB for float64 at SN = 32,
+// two workgroups per CU; 150 KB for float32 at SN = 64, one), and the padded
 // copy of A, which the schemes use only as a product operand, as the MFMA
 // operand fragments of each wave in registers. Only A is read from memory and
-// only C and S are written. Each wave owns one 16 x 16 output block (one wave
-// at padded order 16, four at 32) and applies the epilogue straight from its
-// accumulators. The k order of every product, the operand scaling and the
+// only C and S are written. The workgroup has one wave per 16 x 16 output
+// block at order SN (4 or 16 waves); at a smaller padded order the waves whose
+// block lies outside it sit out the products. Each wave applies the epilogue
+// straight from its accumulators. The k order of every product, the operand scaling and the
 // epilogue's fused multiply-adds are those of batched_kernel, so the results
 // are bitwise the same; the two products of a double-angle step run in one
 // pass (they share no output).
@@ -594,10 +602,15 @@ __global__ __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(3))) void b
 // copy of the level's recorded stages that the workgroup stages in LDS per
 // matrix (one round trip instead of a chain of dependent loads per product).
 // ----------------------------------------------------------------------------
-constexpr int SLD = SNP + 1;
-constexpr int SSLOT = SNP * SLD;          // elements per LDS slot
-constexpr int SPF = SNP * SNP / BNT;      // prefetched input elements per thread
-constexpr int SKK = SNP / 4;              // MFMA k steps at the largest order
+template <int SN>
+struct SmallGeom {
+  static constexpr int NT = (SN / 16) * (SN / 16) * 64;   // threads: one wave per 16 x 16 block
+  static constexpr int LD = SN + 1;                       // LDS row stride
+  static constexpr int SLOT = SN * LD;                    // elements per LDS slot
+  static constexpr int PF = SN * SN / NT;                 // prefetched input elements per thread
+  static constexpr int KK = SN / 4;                       // MFMA k steps at order SN
+  static_assert(PF * NT == SN * SN, "prefetch covers the matrix");
+};
 
 // One recorded product in the form the LDS-resident kernel reads: operand and
 // output ids as in the templates (0: padded copy of A, k + 1: W_k, ID_COUT,
@@ -615,30 +628,35 @@ struct SmallOp {
 static_assert(sizeof(SmallOp) % 8 == 0, "SmallOp copies as 8-byte words");
 __device__ SmallOp g_small[4][8];
 
-template <typename T>
-__device__ inline void small_load_a(const BatchArgs& a, int n, int64_t off, int tid, T (&v)[SPF]) {
+template <typename T, int SN>
+__device__ inline void small_load_a(const BatchArgs& a, int n, int64_t off, int tid,
+                                    T (&v)[SmallGeom<SN>::PF]) {
+  using G = SmallGeom<SN>;
   const int np = (n + 15) & ~15;
   const T* Ai = (const T*)a.A + off;
 #pragma unroll
-  for (int u = 0; u < SPF; ++u) {
-    const int e = tid + u * BNT;
+  for (int u = 0; u < G::PF; ++u) {
+    const int e = tid + u * G::NT;
     const int r = np > 0 ? e / np : 0, c = np > 0 ? e - r * np : 0;
     v[u] = (n > 0 && e < np * np && r < n && c < n) ? Ai[r * n + c] : (T)0;
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(BNT) void batched_small_kernel(BatchArgs a) {
+template <typename T, int SN>
+__global__ __launch_bounds__(SmallGeom<SN>::NT) void batched_small_kernel(BatchArgs a) {
   using M = BMma<T>;
   using acc_t = typename M::acc_t;
+  using Gm = SmallGeom<SN>;
+  constexpr int NT = Gm::NT, SLD = Gm::LD, SSLOT = Gm::SLOT, SPF = Gm::PF, SKK = Gm::KK;
+  constexpr int NB = SN / 16;                 // blocks per side at order SN
   __shared__ __attribute__((aligned(16))) T W[9 * SSLOT];
   __shared__ SmallOp ops[8];
-  __shared__ unsigned long long colbits[SNP];
   __shared__ sincosm_plan s_plan;
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lr = lane & 15, lg = lane >> 4;
-  const int bm = wave >> 1, bn = wave & 1;   // this wave's output block
-  const int nl = (int)*a.nlarge, nq = (int)*a.nqueue;
+  const int bm = wave / NB, bn = wave % NB;   // this wave's output block
+  // this kernel's part of the queue (see batched_order_kernel)
+  const int nl = (int)(SN > 32 ? *a.nlarge : *a.nmid), nq = (int)(SN > 32 ? *a.nmid : *a.nqueue);
   const int G = (int)gridDim.x;
   T* const TMP = W + 8 * SSLOT;               // the padded copy of A passes through W8's slot
 
@@ -647,7 +665,7 @@ __global__ __launch_bounds__(BNT) void batched_small_kernel(BatchArgs a) {
   // load issued for the entries ahead is waited for before this matrix's work.
   auto pos_of = [&](int q) { return nl + (int)blockIdx.x + q * G; };
   auto valid_i = [&](int i) { return i >= 0 && i < a.batch ? i : -1; };
-  auto valid_n = [&](int n) { return n >= 1 && n <= SNP ? n : 0; };
+  auto valid_n = [&](int n) { return n >= 1 && n <= SN ? n : 0; };
   int i0 = pos_of(0) < nq ? valid_i(a.order[pos_of(0)]) : -1;
   int n0 = i0 >= 0 ? valid_n(a.nmat[i0]) : 0;
   int64_t off0 = n0 > 0 ? a.off[i0] : 0;
@@ -656,9 +674,9 @@ __global__ __launch_bounds__(BNT) void batched_small_kernel(BatchArgs a) {
   int64_t off1 = n1 > 0 ? a.off[i1] : 0;
   int i2 = pos_of(2) < nq ? valid_i(a.order[pos_of(2)]) : -1;
   T cur[SPF], nxt[SPF];
-  small_load_a<T>(a, n0, off0, tid, cur);
+  small_load_a<T, SN>(a, n0, off0, tid, cur);
   for (int q = 0; pos_of(q) < nq; ++q) {
-    small_load_a<T>(a, n1, off1, tid, nxt);                      // elements of entry q + 1
+    small_load_a<T, SN>(a, n1, off1, tid, nxt);                  // elements of entry q + 1
     const int i3raw = pos_of(q + 3) < nq ? a.order[pos_of(q + 3)] : -1;   // index of entry q + 3
     const int n2raw = i2 >= 0 ? a.nmat[i2] : 0;                  // order and offset of entry q + 2
     const int64_t off2raw = i2 >= 0 ? a.off[i2] : 0;
@@ -674,7 +692,7 @@ __global__ __launch_bounds__(BNT) void batched_small_kernel(BatchArgs a) {
       // and each wave's operand fragments of A
 #pragma unroll
       for (int u = 0; u < SPF; ++u) {
-        const int e = tid + u * BNT;
+        const int e = tid + u * NT;
         if (e < np * np) {
           const int r = e / np, c = e - r * np;
           TMP[r * SLD + c] = cur[u];
@@ -716,7 +734,7 @@ __global__ __launch_bounds__(BNT) void batched_small_kernel(BatchArgs a) {
       const sincosm_plan plan = s_plan;
       if (plan.status != SINCOSM_OK) {
         const T nanv = (T)__longlong_as_double(0x7ff8000000000000ll);
-        for (int e = tid; e < n * n; e += BNT) { Ci[e] = nanv; Si[e] = nanv; }
+        for (int e = tid; e < n * n; e += NT) { Ci[e] = nanv; Si[e] = nanv; }
       } else {
         const int li = __builtin_amdgcn_readfirstlane(level_index(plan.level));
         const int s = __builtin_amdgcn_readfirstlane(plan.s);
@@ -729,7 +747,7 @@ __global__ __launch_bounds__(BNT) void batched_small_kernel(BatchArgs a) {
           const unsigned long long* src = (const unsigned long long*)&g_small[li][0];
           unsigned long long* dst = (unsigned long long*)&ops[0];
           const int words = nst * (int)(sizeof(SmallOp) / 8);
-          for (int w = tid; w < words; w += BNT) dst[w] = src[w];
+          for (int w = tid; w < words; w += NT) dst[w] = src[w];
         }
         __syncthreads();
         for (int t = 0; t < nst; ++t) {
@@ -933,8 +951,8 @@ int device_cus() {
   return cus;
 }
 
-// Workspace: the queue counters (256 bytes: next entry, length, first entry
-// of the LDS-resident kernel), the work queue, then one arena
+// Workspace: the queue counters (256 bytes: next entry, length, first entries
+// of the LDS-resident kernels), the work queue, then one arena
 // slot of 10 padded matrices of order npm per resident workgroup.
 bool batch_layout(int64_t batch, int npm, int dtype, BatchLayout& L) {
   const int cus = device_cus();
@@ -1022,23 +1040,29 @@ sincosm_status sincosm_eval_batched(int64_t batch, int dtype, const int32_t* n_d
   a.slot_bytes = (int64_t)L.slot_bytes;
   a.counter = counter;
   a.nlarge = nlarge;
+  a.nmid = counter + 3;
   // product mode per padded order, from the tuning table
   const Arith ar = dtype == SINCOSM_F64 ? Arith::F64 : Arith::F32;
   unsigned int lds_mask = 0u;
   for (int b = 0; b <= NMAX / 16; ++b) {
-    const int tile = batched_tile(ar, 16 * b);
+    const int tile = batched_tile(ar, 16 * b);   // 0: LDS-resident (only offered where it fits)
     a.mode[b] = (int8_t)(tile == 32 ? TILE_32 : tile == 0 ? LDS_RESIDENT : TILE_64);
     if (tile == 0 && b >= 1 && b <= NSB) lds_mask |= 1u << b;
   }
   const TimingMark t = timing_begin(SINCOSM_TIMING_BATCHED, stream);
   batched_order_kernel<<<1, ORDER_THREADS, 0, stream>>>((int)batch, n_dev, offset_dev, total_elems, npm,
                                                         lds_mask, L.slots, order, counter, plans_dev);
-  if (lds_mask) {
-    // the smallest orders first: their workgroups are short, and the large
-    // orders then end the call with the queue's usual largest-first tail
-    const int g = (int)std::min<int64_t>(batch, (int64_t)device_cus() * SMALL_WG_PER_CU);
-    if (dtype == SINCOSM_F64) batched_small_kernel<double><<<g, BNT, 0, stream>>>(a);
-    else batched_small_kernel<float><<<g, BNT, 0, stream>>>(a);
+  // the smallest orders first: their workgroups are short, and the large
+  // orders then end the call with the queue's usual largest-first tail
+  const int64_t cus = device_cus();
+  if (lds_mask & ((1u << 3) | (1u << 4))) {   // float32 padded orders 48, 64: one 16-wave workgroup per CU
+    const int g = (int)std::min<int64_t>(batch, cus);
+    batched_small_kernel<float, 64><<<g, SmallGeom<64>::NT, 0, stream>>>(a);
+  }
+  if (lds_mask & ((1u << 1) | (1u << 2))) {   // padded orders 16, 32: 2 (float64) or 3 (float32) per CU
+    const int g = (int)std::min<int64_t>(batch, cus * (dtype == SINCOSM_F64 ? 2 : 3));
+    if (dtype == SINCOSM_F64) batched_small_kernel<double, 32><<<g, SmallGeom<32>::NT, 0, stream>>>(a);
+    else batched_small_kernel<float, 32><<<g, SmallGeom<32>::NT, 0, stream>>>(a);
   }
   if (dtype == SINCOSM_F64) batched_kernel<double><<<L.slots, BNT, 0, stream>>>(a);
   else batched_kernel<float><<<L.slots, BNT, 0, stream>>>(a);

@@ -21,8 +21,8 @@ namespace {
 // Classes 1 and 2 use class 0 entries when none of their own matches.
 // Class 3 holds the batched kernel's product mode per padded order instead of
 // a configuration of the product kernel (0: 64 x 64 output tiles, the
-// default; 1: 32 x 32; 2: the LDS-resident kernel, padded orders up to 32
-// only, 64 x 64 above).
+// default; 1: 32 x 32; 2: the LDS-resident kernel, padded orders up to 32 in
+// float64 and 64 in float32 only, 64 x 64 above).
 struct TuneEntry { int ar; int cls; int64_t lo, hi; int idx; };
 std::mutex tune_mu;
 std::vector<TuneEntry> tune_table;
@@ -32,7 +32,9 @@ constexpr int BATCHED_CLASS = 3;
 // Output tiles of the batched kernel, by configuration index (0: the whole
 // matrix in LDS).
 const int kBatchedTile[] = {64, 32, 0};
-constexpr int kLdsMaxOrder = 32;
+// Largest padded order the LDS-resident kernel holds: nine matrices of order
+// + 1 row stride in 160 KB of LDS.
+inline int lds_max_order(int ar) { return ar == (int)Arith::F64 ? 32 : 64; }
 
 }  // namespace
 
@@ -50,7 +52,7 @@ int batched_tile(Arith ar, int64_t np) {
   const int idx = tuned_cfg(ar, BATCHED_CLASS, np);
   const int count = (int)(sizeof(kBatchedTile) / sizeof(kBatchedTile[0]));
   if (idx < 0 || idx >= count) return 64;
-  if (kBatchedTile[idx] == 0 && np > kLdsMaxOrder) return 64;
+  if (kBatchedTile[idx] == 0 && np > lds_max_order((int)ar)) return 64;
   return kBatchedTile[idx];
 }
 
@@ -72,10 +74,12 @@ sincosm_status sincosm_tune_config_info(int arith, int idx, int32_t* info) {
     if (idx < 0 || idx >= sincosm_tune_num_configs(arith)) return SINCOSM_E_ARG;
     const int tb = sc::kBatchedTile[idx];   // four waves of tb/2 x tb/2, k depth 16, staged
     if (tb == 0) {
-      // LDS-resident: four waves of 16 x 16 blocks over orders up to 32,
-      // k depth 4, 2 workgroups per CU, "direct" = 2 marks the mode
-      info[0] = sc::kLdsMaxOrder; info[1] = sc::kLdsMaxOrder; info[2] = 4; info[3] = 2; info[4] = 2;
-      info[5] = 2; info[6] = 2; info[7] = 1;
+      // LDS-resident: one wave per 16 x 16 block up to the largest order it
+      // holds (32 in float64, 64 in float32), k depth 4; "direct" = 2 marks
+      // the mode, the wave grid is that of the largest order
+      const int mo = sc::lds_max_order(arith & ~sc::TUNE_FLAGS);
+      info[0] = mo; info[1] = mo; info[2] = 4; info[3] = mo / 16; info[4] = mo / 16;
+      info[5] = mo / 16 == 2 ? 2 : 4; info[6] = 2; info[7] = 1;
       return SINCOSM_OK;
     }
     info[0] = tb; info[1] = tb; info[2] = 16; info[3] = 2; info[4] = 2; info[5] = 3;

@@ -123,18 +123,19 @@ def test_uneven_class_flag(lib):
 
 def test_batched_class_flag(lib):
     """SINCOSM_TUNE_BATCHED addresses the batched kernel's mode table: three configurations
-    (64 x 64 and 32 x 32 output tiles, and the LDS-resident kernel, which reports order 32 as
-    its size and 2 as its "direct" field); no other class flag may accompany it."""
+    (64 x 64 and 32 x 32 output tiles, and the LDS-resident kernel, which reports the largest
+    order it holds, 32 in float64 and 64 in float32, as its size and 2 as its "direct" field);
+    no other class flag may accompany it."""
     from paper_2010_00465_amd import autotune
     info = (ctypes.c_int32 * 8)()
-    for arith in (0, 1):
+    for arith, lds in ((0, 32), (1, 64)):
         code = arith | autotune.BATCHED
         assert lib.sincosm_tune_num_configs(code) == 3
         modes = []
         for i in range(3):
             assert lib.sincosm_tune_config_info(code, i, info) == 0
             modes.append((info[0], info[1], info[3], info[4], info[6]))
-        assert modes == [(64, 64, 2, 2, 0), (32, 32, 2, 2, 0), (32, 32, 2, 2, 2)]
+        assert modes == [(64, 64, 2, 2, 0), (32, 32, 2, 2, 0), (lds, lds, lds // 16, lds // 16, 2)]
         assert lib.sincosm_tune_config_info(code, 3, info) == -1
         assert lib.sincosm_tune_set(code, 1 << 40, 1 << 41, 3) == -1
         assert lib.sincosm_tune_set(code, 1 << 40, 1 << 41, 2) == 0

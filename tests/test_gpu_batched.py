@@ -347,8 +347,9 @@ def test_batched_graph_replay_new_metadata(env):
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_batched_lds_resident_small_orders(env, dt):
-    """The LDS-resident kernel on many matrices of orders 1 .. 32 (every level, s = 0 .. 8),
-    among a few larger ones, with the order-16 and order-32 buckets routed to it separately and
+    """The LDS-resident kernels on many matrices of small order (1 .. 32 in float64, 1 .. 64 in
+    float32, where padded orders 48 and 64 have a kernel of their own; every level, s = 0 .. 8),
+    among a few larger ones, with the padded-order buckets routed to them separately and
     together: bitwise equality with the 32 x 32-tile kernel for every matrix, plans equal to
     the oracle's, non-finite entries isolated, and oracle parity: float64 at 1e-12 for every
     matrix; float32 at 5e-6 for orders >= 8 with ||A||_1 <= 2^5. Below order 8 and at larger
@@ -358,8 +359,9 @@ def test_batched_lds_resident_small_orders(env, dt):
     torch, sc = env
     from paper_2010_00465_amd import _lib, autotune
     lib = _lib.lib
+    top = 32 if dt == "f64" else 64
     rng = W.rng(89, 0 if dt == "f64" else 1)
-    sizes = [int(x) for x in rng.integers(1, 33, size=300)] + [33, 48, 64, 100]
+    sizes = [int(x) for x in rng.integers(1, top + 1, size=300)] + [top + 1, top + 16, 100, 129]
     exps = rng.uniform(-9.0, 8.0, size=len(sizes))
     mats = [W.gaussian(n, 2.0 ** e, key=(89, k)) for k, (n, e) in enumerate(zip(sizes, exps))]
     mats[7] = mats[7].copy()
@@ -368,13 +370,17 @@ def test_batched_lds_resident_small_orders(env, dt):
     if dt == "f32":
         mats = [m.astype(np.float32).astype(np.float64) for m in mats]
     arith = autotune.ARITH[dt] | autotune.BATCHED
+    buckets = [(1, 16), (17, 32)] + ([(33, 48), (49, 64)] if dt == "f32" else [])
+    # modes per bucket: 1 = 32 x 32 tiles (the reference), 2 = LDS-resident
+    combos = [tuple(1 for _ in buckets), tuple(2 for _ in buckets), tuple(2 - (i % 2) for i in range(len(buckets))),
+              tuple(1 + (i % 2) for i in range(len(buckets)))]
     results = []
     try:
-        for modes in ((1, 1), (2, 2), (2, 1), (1, 2)):       # (np = 16, np = 32): 1 = 32 x 32 tiles, 2 = LDS
+        for modes in combos:
             print("[case] batched LDS modes", dt, modes, flush=True)
-            assert lib.sincosm_tune_set(arith, 1, 16, modes[0]) == 0
-            assert lib.sincosm_tune_set(arith, 17, 32, modes[1]) == 0
-            assert lib.sincosm_tune_set(arith, 33, 1 << 30, 0) == 0
+            for (lo, hi), md in zip(buckets, modes):
+                assert lib.sincosm_tune_set(arith, lo, hi, md) == 0
+            assert lib.sincosm_tune_set(arith, buckets[-1][1] + 1, 1 << 30, 0) == 0
             out, plans = run_batch(env, mats, accuracy=acc, dtype=dtype)
             results.append(out)
             for k, (A, (C, S), p) in enumerate(zip(mats, out, plans)):
@@ -385,7 +391,7 @@ def test_batched_lds_resident_small_orders(env, dt):
                 assert p.status == 0
                 assert plan_ok(p, A, acc), (k, A.shape, p)
                 stated = dt == "f64" or (A.shape[0] >= 8 and exps[k] <= 5.0)
-                if stated and (modes == (2, 2) or k % 5 == 0):
+                if stated and (modes == combos[1] or k % 5 == 0):
                     Cr, Sr = R.sincosm(A)
                     tol = 1e-12 if dt == "f64" else 5e-6
                     assert rel_fro(C, Cr) <= tol and rel_fro(S, Sr) <= tol, (dt, modes, k, A.shape)

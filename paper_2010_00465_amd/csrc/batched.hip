@@ -79,7 +79,8 @@ struct BatchArgs {
   const int32_t* order;           // work queue: accepted entries, largest padded order first
   const unsigned int* nqueue;     // its length
   const unsigned int* nlarge;     // queue entries [0, nlarge) go to batched_kernel, the rest to the LDS kernels
-  const unsigned int* nmid;       // [nlarge, nmid): LDS-resident, padded order 48 or 64; [nmid, nqueue): 16 or 32
+  const unsigned int* nmid;       // [nlarge, nmid): LDS-resident, padded order 48 or 64; [nmid, nsmall): 32
+  const unsigned int* nsmall;     // [nsmall, nqueue): LDS-resident, padded order 16
   const void* A;
   void* C;
   void* S;
@@ -103,7 +104,8 @@ struct BatchArgs {
 // whole queue stays its own. The queue's first *nlarge entries are
 // batched_kernel's; of the rest, those of padded orders 48 and 64 (float32
 // only) come first, up to *nmid, for the 64-order LDS-resident kernel, then
-// those of orders 16 and 32 for the 32-order one. The order within a
+// those of order 32, up to *nsmall, for the 32-order one, then those of
+// order 16 for the 16-order one. The order within a
 // bucket does not matter (each matrix is computed by one workgroup the same
 // way wherever it sits in the queue, and both kernels give the same bits).
 constexpr int ORDER_THREADS = 1024;
@@ -171,7 +173,8 @@ __global__ __launch_bounds__(ORDER_THREADS) void batched_order_kernel(int batch,
     counter[0] = 0u;            // next entry of batched_kernel
     counter[1] = run;           // queue length
     counter[2] = next[NBUCKET]; // first entry of the LDS-resident kernels
-    counter[3] = next[NBUCKET + NSB - 2];   // first LDS-resident entry of padded order <= 32
+    counter[3] = next[NBUCKET + NSB - 2];   // first LDS-resident entry of padded order 32
+    counter[4] = next[NBUCKET + NSB - 1];   // first LDS-resident entry of padded order 16
   }
   __syncthreads();
   const unsigned int m = mask;
@@ -579,17 +582,19 @@ __global__ __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(3))) void b
 }
 
 // ----------------------------------------------------------------------------
-// LDS-resident kernels for padded orders up to SN (32: float64, and float32
-// orders 16 and 32; 64: float32 orders 48 and 64). A matrix's whole workspace
+// LDS-resident kernels for padded orders up to SN, each taking the orders
+// above the next smaller instance (16: order 16; 32: order 32; 64: float32
+// orders 48 and 64). A matrix's whole workspace
 // stays on chip: W0 .. W8 in LDS (row stride SN + 1, so the rows an MFMA
-// operand read touches start in different banks; 76 KB for float64 at SN = 32,
-// two workgroups per CU; 150 KB for float32 at SN = 64, one), and the padded
+// operand read touches start in different banks; 23 KB for float64 at
+// SN = 16, six workgroups per CU; 76 KB at SN = 32, two; 150 KB for float32
+// at SN = 64, one), and the padded
 // copy of A, which the schemes use only as a product operand, as the MFMA
 // operand fragments of each wave in registers. Only A is read from memory and
 // only C and S are written. The workgroup has one wave per 16 x 16 output
-// block at order SN (4 or 16 waves); at a smaller padded order the waves whose
-// block lies outside it sit out the products. Each wave applies the epilogue
-// straight from its accumulators. The k order of every product, the operand scaling and the
+// block at order SN (1, 4 or 16 waves); at a smaller padded order the waves
+// whose block lies outside it sit out the products. Each wave applies the
+// epilogue straight from its accumulators. The k order of every product, the operand scaling and the
 // epilogue's fused multiply-adds are those of batched_kernel, so the results
 // are bitwise the same; the two products of a double-angle step run in one
 // pass (they share no output).
@@ -656,7 +661,8 @@ __global__ __launch_bounds__(SmallGeom<SN>::NT) void batched_small_kernel(BatchA
   const int lr = lane & 15, lg = lane >> 4;
   const int bm = wave / NB, bn = wave % NB;   // this wave's output block
   // this kernel's part of the queue (see batched_order_kernel)
-  const int nl = (int)(SN > 32 ? *a.nlarge : *a.nmid), nq = (int)(SN > 32 ? *a.nmid : *a.nqueue);
+  const int nl = (int)(SN > 32 ? *a.nlarge : SN > 16 ? *a.nmid : *a.nsmall);
+  const int nq = (int)(SN > 32 ? *a.nmid : SN > 16 ? *a.nsmall : *a.nqueue);
   const int G = (int)gridDim.x;
   T* const TMP = W + 8 * SSLOT;               // the padded copy of A passes through W8's slot
 
@@ -1041,6 +1047,7 @@ sincosm_status sincosm_eval_batched(int64_t batch, int dtype, const int32_t* n_d
   a.counter = counter;
   a.nlarge = nlarge;
   a.nmid = counter + 3;
+  a.nsmall = counter + 4;
   // product mode per padded order, from the tuning table
   const Arith ar = dtype == SINCOSM_F64 ? Arith::F64 : Arith::F32;
   unsigned int lds_mask = 0u;
@@ -1059,10 +1066,15 @@ sincosm_status sincosm_eval_batched(int64_t batch, int dtype, const int32_t* n_d
     const int g = (int)std::min<int64_t>(batch, cus);
     batched_small_kernel<float, 64><<<g, SmallGeom<64>::NT, 0, stream>>>(a);
   }
-  if (lds_mask & ((1u << 1) | (1u << 2))) {   // padded orders 16, 32: 2 (float64) or 3 (float32) per CU
+  if (lds_mask & (1u << 2)) {   // padded order 32: 2 (float64) or 3 (float32) workgroups per CU
     const int g = (int)std::min<int64_t>(batch, cus * (dtype == SINCOSM_F64 ? 2 : 3));
     if (dtype == SINCOSM_F64) batched_small_kernel<double, 32><<<g, SmallGeom<32>::NT, 0, stream>>>(a);
     else batched_small_kernel<float, 32><<<g, SmallGeom<32>::NT, 0, stream>>>(a);
+  }
+  if (lds_mask & (1u << 1)) {   // padded order 16: one-wave workgroups, 6 (float64) or 10 (float32) per CU
+    const int g = (int)std::min<int64_t>(batch, cus * (dtype == SINCOSM_F64 ? 6 : 10));
+    if (dtype == SINCOSM_F64) batched_small_kernel<double, 16><<<g, SmallGeom<16>::NT, 0, stream>>>(a);
+    else batched_small_kernel<float, 16><<<g, SmallGeom<16>::NT, 0, stream>>>(a);
   }
   if (dtype == SINCOSM_F64) batched_kernel<double><<<L.slots, BNT, 0, stream>>>(a);
   else batched_kernel<float><<<L.slots, BNT, 0, stream>>>(a);

@@ -957,8 +957,8 @@ int device_cus() {
   return cus;
 }
 
-// Workspace: the queue counters (256 bytes: next entry, length, first entries
-// of the LDS-resident kernels), the work queue, then one arena
+// Workspace: the queue counters (256 bytes: next entry, length, and where the
+// parts of the three LDS-resident instances begin), the work queue, then one arena
 // slot of 10 padded matrices of order npm per resident workgroup.
 bool batch_layout(int64_t batch, int npm, int dtype, BatchLayout& L) {
   const int cus = device_cus();

@@ -316,7 +316,8 @@ def bench_tiers(torch, sc, W):
     out = {"workload": "n=4096 2-D Laplacian (64 x 64 grid), ||A||_1 = 64, float64 storage; errors relative "
                        "to the float64 CPU oracle"}
     for name, acc, prod in (("fp64_double", "double", "native"), ("fp64_single_plan", "single", "native"),
-                            ("fp32_products", "single", "f32"), ("bf16x3_products", "single", "bf16x3")):
+                            ("fp32_products", "single", "f32"), ("bf16x3_products", "single", "bf16x3"),
+                            ("int8x5_products", "single", "i8x5")):
         C = torch.empty_like(A)
         S = torch.empty_like(A)
         ws = torch.empty(sc.workspace_size(4096, torch.float64, acc, prod), dtype=torch.uint8, device="cuda")
@@ -327,7 +328,7 @@ def bench_tiers(torch, sc, W):
         out[name] = {"ms": 1e3 * t, "plan": [plan.level, plan.s], "products": plan.products,
                      "rel_err_cos": ec, "rel_err_sin": es}
     fp64 = [k for k in ("fp64_single_plan", "fp64_double")]
-    for tier in ("fp32_products", "bf16x3_products"):
+    for tier in ("fp32_products", "bf16x3_products", "int8x5_products"):
         err = max(out[tier]["rel_err_cos"], out[tier]["rel_err_sin"])
         ok = [k for k in fp64 if max(out[k]["rel_err_cos"], out[k]["rel_err_sin"]) <= err]
         best = min(ok, key=lambda k: out[k]["ms"]) if ok else None

@@ -94,9 +94,20 @@ enum { SINCOSM_PLAN_REFINED = 32 };
  *  F32    - float32 MFMA products and float32 intermediates;
  *  BF16X3 - each float32 operand split as hi + lo (hi = bf16(x), lo = bf16(x - hi)),
  *           products hi*hi + hi*lo + lo*hi on bf16 MFMA with float32 accumulation.
+ *  I8X5   - float64 storage and float64 intermediates and epilogues; each product
+ *           on the int8 matrix cores by error-free splitting (Ozaki's scheme): the
+ *           left operand's rows and the right operand's columns are scaled by
+ *           powers of two and written as five 7-bit digits, the 15 digit products
+ *           of significance above 2^-49 accumulate exactly in int32 and are
+ *           combined in float64; product error below 2^-33 |X||Y| elementwise
+ *           (|.| taken entrywise), far inside the single-accuracy bound
+ *           u = 2^-24 of Table 2, not the double one. dtype F64 only,
+ *           n <= 16384, sincosm_eval, sincosm_eval_planned (and its no-allocation
+ *           form) and sincosm_matmul only (elsewhere SINCOSM_E_UNSUPPORTED).
  * The 1-norm, the plan and the double-angle steps always run in the storage
  * type (float64 for F64). */
-typedef enum { SINCOSM_PROD_NATIVE = 0, SINCOSM_PROD_F32 = 1, SINCOSM_PROD_BF16X3 = 2 } sincosm_prod;
+typedef enum { SINCOSM_PROD_NATIVE = 0, SINCOSM_PROD_F32 = 1, SINCOSM_PROD_BF16X3 = 2,
+               SINCOSM_PROD_I8X5 = 3 } sincosm_prod;
 
 /* The plan chosen for one matrix. level in {3,4,6,7} (= products of the
  * scheme; also 5 with SINCOSM_PLAN_EXTENDED; 2..5 for the wave entries),
@@ -140,8 +151,8 @@ size_t sincosm_workspace_size(int64_t n, int dtype, int acc, int prod);
  *  ws / ws_bytes: device workspace of at least sincosm_workspace_size(...) bytes,
  *  256-byte aligned.
  *  plan_host: optional host pointer receiving the plan used.
- *  Supported: dtype F64 with prod NATIVE, F32 or BF16X3; dtype F32 with prod
- *  NATIVE (= F32) or BF16X3. acc may be DOUBLE or SINGLE in every case, with
+ *  Supported: dtype F64 with prod NATIVE, F32, BF16X3 or I8X5 (n <= 16384);
+ *  dtype F32 with prod NATIVE (= F32) or BF16X3. acc may be DOUBLE or SINGLE in every case, with
  *  SINCOSM_PLAN_EXTENDED and/or SINCOSM_PLAN_REFINED OR-ed in.
  *  Returns SINCOSM_E_NONFINITE (after filling C and S with NaN) when A holds
  *  Inf or NaN. */

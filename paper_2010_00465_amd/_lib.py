@@ -28,7 +28,7 @@ F64, F32 = 0, 1
 ACC = {"double": 0, "single": 1}
 PLAN_EXTENDED = 16   # OR-ed into the accuracy code: the 5-product scheme joins the plan
 PLAN_REFINED = 32    # OR-ed into the accuracy code of sincosm_eval: plan on min(||A||_1, ||A^2||_1^(1/2))
-PROD = {"native": 0, "f32": 1, "bf16x3": 2}
+PROD = {"native": 0, "f32": 1, "bf16x3": 2, "i8x5": 3}
 
 
 class Plan(ctypes.Structure):

@@ -207,11 +207,16 @@ __host__ __device__ inline double resolve_scale(double v, int s) {
 }
 
 // Product arithmetic of one GEMM launch.
-enum class Arith { F64, F32, BF16X3 };
+enum class Arith { F64, F32, BF16X3, I8X5 };
 
 // Launch one GEMM-with-epilogue over all problems. `tile` selects the tile
 // configuration (see gemm.hip); np must be a multiple of tile_size(tile).
-sincosm_status launch_gemm(Arith ar, int tile, const GemmLaunch& g, hipStream_t stream);
+// I8X5 (float64 storage, products on the int8 matrix cores) needs `scratch` of
+// i8x5_scratch_bytes(np) bytes for its operand slices; launches without a
+// product (epilogue only) run on the float64 kernel.
+sincosm_status launch_gemm(Arith ar, int tile, const GemmLaunch& g, hipStream_t stream, void* scratch = nullptr);
+size_t i8x5_scratch_bytes(int64_t np);
+sincosm_status launch_gemm_i8x5(const GemmLaunch& g, void* scratch, hipStream_t stream);
 // Output tile (64 or 32) of the batched kernel's products for padded order np,
 // from the tuning table (64 where it has no entry).
 int batched_tile(Arith ar, int64_t np);

@@ -501,7 +501,7 @@ int tile_size(int tile) {
 }
 
 int choose_tile(Arith ar, int64_t n) {
-  (void)ar;
+  if (ar == Arith::I8X5) return n >= 1536 ? 0 : 1;   // its products need multiples of 64
   if (n >= 1536) return 0;
   if (n >= 256) return 1;
   return 2;
@@ -625,8 +625,14 @@ static bool fold_scales(const GemmLaunch& g, GemmLaunch& out) {
   return changed;
 }
 
-sincosm_status launch_gemm(Arith ar, int tile, const GemmLaunch& g0, hipStream_t stream) {
+sincosm_status launch_gemm(Arith ar, int tile, const GemmLaunch& g0, hipStream_t stream, void* scratch) {
   if (g0.np % tile_size(tile) != 0) return SINCOSM_E_ARG;
+  if (ar == Arith::I8X5) {
+    bool products = false;
+    for (int p = 0; p < g0.nprob; ++p) products |= g0.prob[p].nseg > 0;
+    if (products) return launch_gemm_i8x5(g0, scratch, stream);
+    ar = Arith::F64;   // epilogue only: float64 storage
+  }
   GemmLaunch folded;
   const GemmLaunch& g = fold_scales(g0, folded) ? folded : g0;
   if (ar == Arith::BF16X3) return launch_gemm_bf16x3(tile, g, stream);

@@ -1,0 +1,303 @@
+// Product X Y of float64 matrices on the int8 matrix cores by error-free
+// splitting into slices (the scheme of Ozaki, Ogita, Oishi and Rump, 2012, as
+// used for emulated float64 products on integer matrix units by Ootomo,
+// Ozaki and Yokota, 2024).
+//
+// Every row i of X is scaled by 2^-e_i (e_i from the row's largest magnitude,
+// so the scaled entries lie in (-1, 1)) and written as five signed 7-bit
+// digits, x = 2^e_i sum_{k=1..5} d_k 2^-7k, exactly up to a remainder below
+// 2^(e_i - 35); every column j of Y likewise with 2^f_j. Then
+//   (X Y)_ij = 2^(e_i + f_j) sum_{k, l} 2^-7(k + l) (D_k E_l)_ij,
+// each D_k E_l an int8 product with exact int32 accumulation. The pairs with
+// k + l <= 6 are kept (15 products; the others weigh 2^-49 of the leading
+// term), summed per k + l in int32 (exact up to order 26000), and combined in
+// float64. The product error is about 2^-34 |X| |Y| elementwise. Four digits
+// (28 bits) were measured too few: the schemes' intermediates cancel, and the
+// double-angle steps double what is left, so at s = 6 the single-accuracy bar
+// was exceeded; five leave a margin of about two orders of magnitude.
+//
+// Three preparation kernels write the slices (left operand by rows, right
+// operand by columns, transposed so that both read 64 consecutive k bytes per
+// row of the tile), then the product kernel: 64 x 64 output tiles of four
+// waves (2 x 2 blocks of 16 x 16 each), k steps of 64 on
+// v_mfma_i32_16x16x64_i8, the slices staged through one LDS buffer (the next
+// step's slices wait in registers) with a row stride of 80 bytes (the 16 rows
+// of a fragment read fall on distinct banks), and the fused linear-combination
+// epilogue of the other product kernels.
+#include <math.h>
+
+#include "epilogue.hpp"
+
+namespace sc {
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int NS = 5;            // slices per operand (7 bits each)
+constexpr int QT = 64;           // output tile and k step
+constexpr int QTHR = 256;        // threads of the product kernel (4 waves)
+constexpr int QROW = 80;         // LDS bytes per staged row (64 data + 16 pad)
+constexpr int QPLANE = QT * QROW;             // bytes per staged plane
+constexpr int QSTAGE = 2 * NS * QPLANE;       // A and B planes of one k step
+constexpr int QLDS = QSTAGE;                  // one buffer: 2 workgroups per CU
+constexpr int QPIECES = 2 * NS * QT * 4 / QTHR;   // 16-byte staging loads per thread and k step
+
+// result layout of the int8 16 x 16 MFMA: lane (lr, lg), register r -> row 4 lg + r, column lr
+struct MI8 {
+  __device__ static inline int row_in_block(int lg, int r) { return 4 * lg + r; }
+};
+
+// The exponent e with |x| < 2^e for every x of a row or column whose largest
+// magnitude is m (0 for m = 0).
+__device__ inline int slice_exponent(double m) {
+  if (!(m > 0.0)) return 0;
+  int e = 0;
+  frexp(m, &e);
+  return e;
+}
+
+// NS digits of y = x 2^-e in (-1, 1): d_k = trunc(128 y_k), y_{k+1} = 128 y_k - d_k
+// (exact in float64).
+__device__ inline void slice_digits(double y, int8_t (&d)[NS]) {
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const double t = y * 128.0;
+    const double q = trunc(t);
+    d[k] = (int8_t)(int)q;
+    y = t - q;
+  }
+}
+
+// Left operand: one workgroup per row; planes P[k][i][c] (np x np each).
+__global__ __launch_bounds__(256) void slice_rows_kernel(const double* __restrict__ X, int64_t ld, int np,
+                                                         int8_t* __restrict__ P, int* __restrict__ ex) {
+  __shared__ unsigned long long red[256];
+  const int i = blockIdx.x, tid = threadIdx.x;
+  const double* row = X + (int64_t)i * ld;
+  unsigned long long m = 0ull;
+  for (int c = tid; c < np; c += 256) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(fabs(row[c]));
+    m = b > m ? b : m;
+  }
+  red[tid] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w && red[tid + w] > red[tid]) red[tid] = red[tid + w];
+    __syncthreads();
+  }
+  const int e = slice_exponent(__longlong_as_double((long long)red[0]));
+  if (tid == 0) ex[i] = e;
+  const int64_t plane = (int64_t)np * np;
+  for (int c = tid; c < np; c += 256) {
+    int8_t d[NS];
+    slice_digits(ldexp(row[c], -e), d);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) P[k * plane + (int64_t)i * np + c] = d[k];
+  }
+}
+
+// Right operand, pass 1: column maxima (bit patterns of |x|, compared as
+// integers) over 64 x 64 blocks into cmax (zeroed by the caller).
+__global__ __launch_bounds__(256) void col_max_kernel(const double* __restrict__ X, int64_t ld, int np,
+                                                      unsigned long long* __restrict__ cmax) {
+  __shared__ unsigned long long red[4][64];
+  const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+  const int tid = threadIdx.x, c = tid & 63, g = tid >> 6;
+  unsigned long long m = 0ull;
+  for (int r = g; r < 64; r += 4) {
+    const unsigned long long b =
+        (unsigned long long)__double_as_longlong(fabs(X[(int64_t)(r0 + r) * ld + c0 + c]));
+    m = b > m ? b : m;
+  }
+  red[g][c] = m;
+  __syncthreads();
+  if (g == 0) {
+    for (int q = 1; q < 4; ++q) m = red[q][c] > m ? red[q][c] : m;
+    atomicMax(cmax + c0 + c, m);
+  }
+}
+
+// Right operand, pass 2: planes of the transpose, P[l][j][r] = digit l of
+// X[r][j] 2^-f_j, one 64 x 64 block per workgroup through LDS.
+__global__ __launch_bounds__(256) void slice_cols_kernel(const double* __restrict__ X, int64_t ld, int np,
+                                                         const unsigned long long* __restrict__ cmax,
+                                                         int8_t* __restrict__ P, int* __restrict__ ex) {
+  __shared__ double tile[64][65];
+  const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    tile[r][c] = X[(int64_t)(r0 + r) * ld + c0 + c];
+  }
+  __syncthreads();
+  // thread -> output row j = c0 + (tid >> 2), 16 consecutive r
+  const int jc = tid >> 2, rq = (tid & 3) * 16;
+  const int f = slice_exponent(__longlong_as_double((long long)cmax[c0 + jc]));
+  if (blockIdx.y == 0 && (tid & 3) == 0) ex[c0 + jc] = f;
+  int8_t d[NS][16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    int8_t dd[NS];
+    slice_digits(ldexp(tile[rq + t][jc], -f), dd);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) d[k][t] = dd[k];
+  }
+  const int64_t plane = (int64_t)np * np;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    v4i v;
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+      v[w] = (int)((uint32_t)(uint8_t)d[k][4 * w] | ((uint32_t)(uint8_t)d[k][4 * w + 1] << 8) |
+                   ((uint32_t)(uint8_t)d[k][4 * w + 2] << 16) | ((uint32_t)(uint8_t)d[k][4 * w + 3] << 24));
+    *(v4i*)(P + k * plane + (int64_t)(c0 + jc) * np + r0 + rq) = v;
+  }
+}
+
+__global__ void zero_u64_kernel(unsigned long long* p, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+// The product kernel. A: planes of the left operand by rows, B: planes of
+// the right operand's transpose; both [NS][np][np] int8.
+__global__ __launch_bounds__(QTHR) void gemm_i8x5_kernel(const int8_t* __restrict__ A,
+                                                           const int8_t* __restrict__ B,
+                                                           const int* __restrict__ ea,
+                                                           const int* __restrict__ eb, double scale,
+                                                           GemmLaunch g) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[QLDS];
+  const Problem& P = g.prob[0];
+  const int np = g.np;
+  const int tiles = np / QT;
+  const int tile_m = blockIdx.x / tiles, tile_n = blockIdx.x - (blockIdx.x / tiles) * tiles;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int64_t plane = (int64_t)np * np;
+  const int nk = np / QT;
+
+  // global -> register staging: per k step 2 operands x NS planes x 64 rows x
+  // 64 bytes in pieces of 16 bytes, QPIECES per thread
+  v4i st[QPIECES];
+  auto piece_at = [&](int u, int& op, int& pl, int& row, int& q) {
+    const int piece = u * QTHR + tid;              // 0 .. 2 NS 256 - 1
+    op = piece / (NS * 256);
+    const int rem = piece - op * (NS * 256);
+    pl = rem >> 8;
+    row = (rem >> 2) & 63;
+    q = rem & 3;
+  };
+  auto gload = [&](int kt) {
+    const int k0 = kt * QT;
+#pragma unroll
+    for (int u = 0; u < QPIECES; ++u) {
+      int op, pl, row, q;
+      piece_at(u, op, pl, row, q);
+      const int8_t* src = op == 0 ? A + pl * plane + (int64_t)(tile_m * QT + row) * np + k0 + 16 * q
+                                  : B + pl * plane + (int64_t)(tile_n * QT + row) * np + k0 + 16 * q;
+      st[u] = *(const v4i*)src;
+    }
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int u = 0; u < QPIECES; ++u) {
+      int op, pl, row, q;
+      piece_at(u, op, pl, row, q);
+      *(v4i*)(smem + (op * NS + pl) * QPLANE + row * QROW + 16 * q) = st[u];
+    }
+  };
+
+  constexpr int NG = NS;   // groups k + l = 0 .. NS - 1 (slice indices from 0)
+  v4i acc[NG][2][2];
+#pragma unroll
+  for (int gq = 0; gq < NG; ++gq)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[gq][i][j] = (v4i){0, 0, 0, 0};
+
+  gload(0);
+  lstore();
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) gload(kt + 1);   // in registers while this step computes
+    const unsigned char* sa = smem;
+    const unsigned char* sb = sa + NS * QPLANE;
+    v4i fa[NS][2], fb[NS][2];
+#pragma unroll
+    for (int p = 0; p < NS; ++p)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        fa[p][i] = *(const v4i*)(sa + p * QPLANE + (wm * 32 + i * 16 + lr) * QROW + 16 * lg);
+        fb[p][i] = *(const v4i*)(sb + p * QPLANE + (wn * 32 + i * 16 + lr) * QROW + 16 * lg);
+      }
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+#pragma unroll
+      for (int l = 0; l < NS; ++l) {
+        if (k + l > NS - 1) continue;   // weights 2^-7(k + l + 2): keep those above 2^-49
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[k + l][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[k][i], fb[l][j], acc[k + l][i][j], 0, 0, 0);
+      }
+    if (kt + 1 < nk) {
+      __syncthreads();   // every wave has read this step's slices
+      lstore();
+      __syncthreads();
+    }
+  }
+
+  // float64 values of the block results: sum over k + l, then the row and
+  // column scales 2^(e_i + f_j) and the launch's operand scale
+  v4d dd[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double v = 0.0;
+#pragma unroll
+        for (int gq = NG - 1; gq >= 0; --gq) v += ldexp((double)acc[gq][i][j][r], -7 * (gq + 2));
+        const int row = tile_m * QT + wm * 32 + i * 16 + MI8::row_in_block(lg, r);
+        const int col = tile_n * QT + wn * 32 + j * 16 + lr;
+        dd[i][j][r] = ldexp(v, ea[row] + eb[col]) * scale;
+      }
+  epilogue_bands<double, QT, QT, 2, 2, MI8, v4d, 2, 2>(P, np, tile_m, tile_n, dd, (double*)smem);
+}
+
+}  // namespace
+
+size_t i8x5_scratch_bytes(int64_t np) {
+  const size_t planes = (size_t)NS * (size_t)np * (size_t)np;
+  return 2 * align_up(planes, 256) + 2 * align_up((size_t)np * 4, 256) + align_up((size_t)np * 8, 256);
+}
+
+sincosm_status launch_gemm_i8x5(const GemmLaunch& g, void* scratch, hipStream_t stream) {
+  const int np = g.np;
+  if (!scratch || np <= 0 || np % QT != 0 || np > 16384) return SINCOSM_E_UNSUPPORTED;
+  if (g.nprob != 1 || g.prob[0].nseg != 1 || g.cond.plan) return SINCOSM_E_UNSUPPORTED;
+  const Seg& sg = g.prob[0].seg[0];
+  const size_t planes = (size_t)NS * (size_t)np * (size_t)np;
+  char* base = (char*)scratch;
+  int8_t* Ap = (int8_t*)base;
+  int8_t* Bp = (int8_t*)(base + align_up(planes, 256));
+  int* ea = (int*)(base + 2 * align_up(planes, 256));
+  int* eb = (int*)((char*)ea + align_up((size_t)np * 4, 256));
+  unsigned long long* cmax = (unsigned long long*)((char*)eb + align_up((size_t)np * 4, 256));
+  slice_rows_kernel<<<np, 256, 0, stream>>>((const double*)sg.L, sg.ldl, np, Ap, ea);
+  zero_u64_kernel<<<(np + 255) / 256, 256, 0, stream>>>(cmax, np);
+  dim3 gb(np / 64, np / 64);
+  col_max_kernel<<<gb, 256, 0, stream>>>((const double*)sg.R, sg.ldr, np, cmax);
+  slice_cols_kernel<<<gb, 256, 0, stream>>>((const double*)sg.R, sg.ldr, np, cmax, Bp, eb);
+  const int tiles = np / QT;
+  gemm_i8x5_kernel<<<tiles * tiles, QTHR, 0, stream>>>(Ap, Bp, ea, eb, sg.lscale * sg.rscale, g);
+  SC_HIP(hipGetLastError());
+  return SINCOSM_OK;
+}
+
+}  // namespace sc

@@ -125,6 +125,10 @@ bool modes_for(int64_t n, int dtype, int prod, Modes& m) {
   if (dtype == SINCOSM_F64) {
     m.sq = Arith::F64; m.sq_f64 = true;
     if (prod == SINCOSM_PROD_NATIVE) { m.poly = Arith::F64; m.poly_f64 = true; }
+    else if (prod == SINCOSM_PROD_I8X5) {
+      if (n > 16384) return false;   // int32 accumulation of the slice products
+      m.poly = Arith::I8X5; m.poly_f64 = true;
+    }
     else if (prod == SINCOSM_PROD_F32) { m.poly = Arith::F32; m.poly_f64 = false; }
     else if (prod == SINCOSM_PROD_BF16X3) { m.poly = Arith::BF16X3; m.poly_f64 = false; }
     else return false;
@@ -152,6 +156,8 @@ Layout layout_for(const Modes& m) {
   L.ap_off = off; off += align_up(np2 * pe, 256);
   for (int i = 0; i < 9; ++i) { L.w_off[i] = off; off += align_up(np2 * pe, 256); }
   for (int i = 0; i < 4; ++i) { L.q_off[i] = off; off += align_up(np2 * se, 256); }
+  L.i8_off = off;
+  if (m.poly == Arith::I8X5) off += align_up(i8x5_scratch_bytes(m.np), 256);
   L.total = off;
   return L;
 }
@@ -233,10 +239,10 @@ sincosm_status gemm(Run& r, Arith ar, const GemmLaunch& g0, int kind) {
     gp = &dg;
   }
   const GemmLaunch& g = *gp;
-  if (!r.timed) return launch_gemm(ar, r.m->tile, g, r.stream);
+  if (!r.timed) return launch_gemm(ar, r.m->tile, g, r.stream, r.i8ws);
   if (kind < 0) kind = g.nprob == 2 ? SINCOSM_TIMING_SQUARING : SINCOSM_TIMING_SCHEME;
   const TimingMark t = timing_begin(kind, r.stream);
-  const sincosm_status st = launch_gemm(ar, r.m->tile, g, r.stream);
+  const sincosm_status st = launch_gemm(ar, r.m->tile, g, r.stream, r.i8ws);
   timing_end(t, r.stream);
   return st;
 }

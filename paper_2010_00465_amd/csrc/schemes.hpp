@@ -22,7 +22,7 @@ struct Modes {
 };
 
 struct Layout {
-  size_t norm_off, ap_off, w_off[9], q_off[4], total;
+  size_t norm_off, ap_off, w_off[9], q_off[4], i8_off, total;   // i8_off: operand slices (I8X5 only)
 };
 
 struct Recorder;   // captures launches instead of enqueuing them (batched templates)
@@ -38,6 +38,7 @@ struct Run {
   bool y_ready = false;   // W0 already holds Y = (2^-s A)^2: the schemes skip their first product
   bool timed = true;      // launch timing may record events (off where nothing may be allocated)
   DevCond cond{};         // copied into every launch (plan == nullptr: launches always run)
+  void* i8ws = nullptr;   // operand-slice scratch of I8X5 products
 };
 
 // Launch capture used to build the batched path's stage templates from the

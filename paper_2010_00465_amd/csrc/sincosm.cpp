@@ -185,6 +185,7 @@ sincosm_status eval_planned(int64_t n, int dtype, const void* A, int64_t lda, vo
   r.n = n;
   r.Ap = Ap;
   for (int i = 0; i < 9; ++i) r.W[i] = base + L.w_off[i];
+  r.i8ws = base + L.i8_off;
   r.stream = stream;
   r.timed = timed;
   SC_TRY(launch_norm_copy_plan(n, m.np, A, lda, m.user_f64, Ap, m.poly_f64, acc, ns, stream));
@@ -279,6 +280,7 @@ sincosm_status sincosm_eval(int64_t n, int dtype, const void* A, int64_t lda, vo
   r.n = n;
   r.Ap = Ap;
   for (int i = 0; i < 9; ++i) r.W[i] = base + L.w_off[i];
+  r.i8ws = base + L.i8_off;
   r.stream = stream;
   SC_TRY(launch_norm_copy_plan(n, m.np, A, lda, m.user_f64, Ap, m.poly_f64, acc, ns, stream));
   sincosm_plan plans[2];
@@ -329,6 +331,7 @@ sincosm_status sincosm_eval_async(int64_t n, int dtype, const void* A, int64_t l
   if (!acc_valid(acc, SINCOSM_PLAN_EXTENDED)) return SINCOSM_E_ARG;
   Modes m;
   if (!modes_for(n > 0 ? n : 1, dtype, prod, m)) return SINCOSM_E_ARG;
+  if (m.poly == Arith::I8X5) return SINCOSM_E_UNSUPPORTED;   // its products are not device-planned launches
   if (n == 0) return SINCOSM_OK;
   SC_TRY(check_eval_args(n, dtype, A, lda, C, ldc, S, lds, m, ws, ws_bytes));
   const Layout L = layout_for(m);
@@ -349,7 +352,8 @@ size_t sincosm_matmul_workspace_size(int64_t n, int dtype, int prod) {
   Modes m;
   if (!modes_for(n, dtype, prod, m)) return 0;
   const size_t pe = m.poly_f64 ? 8 : 4;
-  return 2 * align_up((size_t)m.np * m.np * pe, 256);
+  return 2 * align_up((size_t)m.np * m.np * pe, 256) +
+         (m.poly == Arith::I8X5 ? align_up(i8x5_scratch_bytes(m.np), 256) : 0);
 }
 
 sincosm_status sincosm_matmul(int64_t n, int dtype, const void* X, int64_t ldx, const void* Y, int64_t ldy,
@@ -364,14 +368,15 @@ sincosm_status sincosm_matmul(int64_t n, int dtype, const void* X, int64_t ldx, 
   if (!ws || ws_bytes < need || ((uintptr_t)ws & 255u)) return SINCOSM_E_WORKSPACE;
   hipStream_t stream = (hipStream_t)stream_;
   char* base = (char*)ws;
+  const size_t mat = align_up((size_t)m.np * m.np * (m.poly_f64 ? 8 : 4), 256);
   void* Xp = base;
-  void* Yp = base + need / 2;
+  void* Yp = base + mat;
   SC_TRY(launch_convert_pad(n, m.np, X, ldx, m.user_f64, Xp, m.poly_f64, stream));
   SC_TRY(launch_convert_pad(n, m.np, Y, ldy, m.user_f64, Yp, m.poly_f64, stream));
   Problem p = make_problem((int)n);
   add_seg(p, Xp, Yp, m.np);
   add_out(p, Target{Z, ldz, (int)n, m.user_f64}, 1.0, 0.0, {});
-  return launch_gemm(m.poly, m.tile, one(p, (int)m.np), stream);
+  return launch_gemm(m.poly, m.tile, one(p, (int)m.np), stream, base + 2 * mat);
 }
 
 }  // extern "C"

@@ -210,6 +210,7 @@ static sincosm_status wave_check(int64_t n, int dtype, const void* A, int64_t ld
   if (!modes_for(n > 0 ? n : 1, dtype, prod, m)) return SINCOSM_E_ARG;
   if (n > 0 && (!A || lda < n)) return SINCOSM_E_ARG;
   if (m.poly == Arith::BF16X3 && !bf16x3_available()) return SINCOSM_E_UNSUPPORTED;
+  if (m.poly == Arith::I8X5) return SINCOSM_E_UNSUPPORTED;   // sincosm_eval and sincosm_eval_planned only
   return SINCOSM_OK;
 }
 

@@ -276,3 +276,32 @@ def test_async_propagator_argument_errors_without_gpu(lib):
     assert ex(4, 0, p, 4, 1.0, u_odd, 4, 0, 0, 4, p, 64, None, None) == -1
     assert ex(4, 0, p, 4, 1.0, p + 1024, 4, 32, 0, 4, p, 64, None, None) == -1               # refined flag
     assert ex(4, 0, p, 4, 1.0, p + 1024, 4, 0, 0, 4, None, 0, None, None) == -3
+
+
+def test_int8_product_tier_sizes_and_rejections_without_gpu(lib):
+    """SINCOSM_PROD_I8X5: float64 storage only, n <= 16384 (int32 accumulation of the slice
+    products); its workspace adds the slice planes (10 np^2 bytes and the exponents); the
+    device-planned evaluation and the wave and propagator entries reject it before any GPU
+    call."""
+    vp, i64, i32, dbl, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
+    ws = lib.sincosm_workspace_size
+    ws.restype, ws.argtypes = sz, [i64, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    for n in (64, 1000, 4096):
+        np_ = 64 * ((n + 63) // 64) if n < 1536 else 128 * ((n + 127) // 128)
+        assert ws(n, 0, 1, 3) >= ws(n, 0, 1, 0) + 10 * np_ * np_
+    assert ws(64, 1, 1, 3) == 0              # float32 storage
+    assert ws(16384, 0, 1, 3) > 0 and ws(16385, 0, 1, 3) == 0
+    mw = lib.sincosm_matmul_workspace_size
+    mw.restype, mw.argtypes = sz, [i64, ctypes.c_int, ctypes.c_int]
+    assert mw(1000, 0, 3) >= mw(1000, 0, 0) + 10 * 1024 * 1024
+    buf = ctypes.create_string_buffer(8192)
+    p = (ctypes.cast(buf, vp).value + 255) // 256 * 256
+    ea = lib.sincosm_eval_async
+    ea.argtypes = [i64, ctypes.c_int, vp, i64, vp, i64, vp, i64, ctypes.c_int, ctypes.c_int, i32, vp, sz, vp, vp]
+    assert ea(4, 0, p, 4, p + 1024, 4, p + 2048, 4, 1, 3, 8, p, 64, None, None) == -2
+    we = lib.sincosm_wave_eval_async
+    we.argtypes = [i64, ctypes.c_int, vp, i64, dbl, vp, i64, vp, i64, ctypes.c_int, ctypes.c_int, i32, vp, sz, vp, vp]
+    assert we(4, 0, p, 4, 1.0, p + 1024, 4, p + 2048, 4, 1, 3, 4, p, 64, None, None) == -2
+    ex = lib.sincosm_expi_eval_async
+    ex.argtypes = [i64, ctypes.c_int, vp, i64, dbl, vp, i64, ctypes.c_int, ctypes.c_int, i32, vp, sz, vp, vp]
+    assert ex(4, 0, p, 4, 1.0, p + 1024, 4, 1, 3, 4, p, 64, None, None) == -2

@@ -1,0 +1,129 @@
+"""Products on the int8 matrix cores by error-free splitting (SINCOSM_PROD_I8X5) through the C ABI.
+
+The product alone (sincosm_matmul): every operand entry is kept to 35 bits below its row's
+(left operand) or column's (right operand) largest power of two, so the elementwise error of
+Z = X Y is at most 2^-34 (rowmax_i |X| colsum_j |Y| + rowsum_i |X| colmax_j |Y|) plus the
+omitted digit products (2^-49 of the leading term) and the float64 combination; the test
+gates at twice that.
+Whole evaluations (sincosm_eval, float64 storage, intermediates and epilogues in float64, the
+squarings in float64): against the float64 oracle at the single-accuracy bar 5e-6 for the
+single plan (Table 2), and for the double plan at a bound derived from the product's: in the
+Frobenius norm the elementwise bound gives ||E|| <= 2^-33 n^(1/2) ||X|| ||Y|| (a row maximum is
+at most the row's norm, a column sum at most n^(1/2) times the column's norm), so the schemes'
+Pi products and the s squarings, each at most doubling what came before, keep the relative
+error below 8 Pi 2^-33 n^(1/2) 2^s (8 covering the growth of the intermediates, as for the
+tiers' bounds in float32)."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import reference as R
+from tests.conftest import rel_fro
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2010_00465_amd as sc
+    return torch, sc
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("n", [64, 100, 257, 1000])
+@pytest.mark.parametrize("kind", ["gaussian", "graded"])
+def test_i8x5_product_bound(env, n, kind):
+    torch, sc = env
+    say("i8x5 product", n, kind)
+    g = W.rng(180, n, 0 if kind == "gaussian" else 1)
+    X = g.standard_normal((n, n))
+    Y = g.standard_normal((n, n))
+    if kind == "graded":   # rows and columns of very different magnitudes
+        X *= np.exp2(g.integers(-20, 20, size=(n, 1)))
+        Y *= np.exp2(g.integers(-20, 20, size=(1, n)))
+    Xt, Yt = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    Z = torch.empty_like(Xt)
+    sc.sincosm_matmul(Xt, Yt, Z, products="i8x5")
+    torch.cuda.synchronize()
+    Zr = X @ Y
+    aX, aY = np.abs(X), np.abs(Y)
+    bound = 2.0 ** -34 * (np.outer(aX.max(1), aY.sum(0)) + np.outer(aX.sum(1), aY.max(0)))
+    err = np.abs(Z.cpu().numpy() - Zr)
+    ratio = float((err / (2.0 * bound + 1e-300)).max())
+    say("i8x5 product worst error / (2 bound)", ratio)
+    assert ratio <= 1.0
+
+
+@pytest.mark.parametrize("n", [64, 257, 1000])
+@pytest.mark.parametrize("e", [-6.0, -1.0, 1.0, 4.0, 8.0])
+def test_i8x5_eval_single(env, n, e):
+    """Single plan, every level reached over the norms: <= 5e-6 against the float64 oracle."""
+    torch, sc = env
+    say("i8x5 eval single", n, e)
+    A = W.gaussian(n, 2.0 ** e, key=(181, n, int(e) + 10))
+    At = torch.from_numpy(A).cuda()
+    C, S = torch.empty_like(At), torch.empty_like(At)
+    p = sc.sincosm_eval(At, C, S, "single", "i8x5")
+    torch.cuda.synchronize()
+    Cr, Sr = R.sincosm(A)
+    ec, es = rel_fro(C.cpu().numpy(), Cr), rel_fro(S.cpu().numpy(), Sr)
+    say("i8x5 single errors", p.level, p.s, ec, es)
+    assert ec <= 5e-6 and es <= 5e-6
+
+
+@pytest.mark.parametrize("e", [-4.0, 0.0, 4.0, 10.0])
+def test_i8x5_eval_double_plan_bound(env, e):
+    torch, sc = env
+    n = 512
+    say("i8x5 eval double plan", e)
+    A = W.gaussian(n, 2.0 ** e, key=(182, int(e) + 10))
+    At = torch.from_numpy(A).cuda()
+    C, S = torch.empty_like(At), torch.empty_like(At)
+    p = sc.sincosm_eval(At, C, S, "double", "i8x5")
+    torch.cuda.synchronize()
+    Cr, Sr = R.sincosm(A)
+    bound = 8.0 * p.level * 2.0 ** -33 * np.sqrt(n) * 2.0 ** p.s
+    ec, es = rel_fro(C.cpu().numpy(), Cr), rel_fro(S.cpu().numpy(), Sr)
+    say("i8x5 double-plan errors", p.level, p.s, ec, es, bound)
+    assert ec <= bound and es <= bound
+
+
+def test_i8x5_laplacian_tier_workload(env):
+    """The precision tiers' workload at reduced order (2-D Laplacian on a 32 x 32 grid,
+    ||A||_1 = 64, single plan): within the single-accuracy bar with room to spare."""
+    torch, sc = env
+    A = W.laplacian_2d(32, 64.0)
+    At = torch.from_numpy(A).cuda()
+    C, S = torch.empty_like(At), torch.empty_like(At)
+    p = sc.sincosm_eval(At, C, S, "single", "i8x5")
+    torch.cuda.synchronize()
+    Cr, Sr = R.sincosm(A)
+    ec, es = rel_fro(C.cpu().numpy(), Cr), rel_fro(S.cpu().numpy(), Sr)
+    say("i8x5 laplacian", p.level, p.s, ec, es)
+    assert ec <= 5e-7 and es <= 5e-7
+
+
+def test_i8x5_planned_and_refined(env):
+    """sincosm_eval_planned with I8X5 products equals sincosm_eval bitwise; the refined-norm
+    plan (its scaling pass is an epilogue-only launch) runs too."""
+    torch, sc = env
+    n = 300
+    A = torch.from_numpy(W.gaussian(n, 20.0, key=(183,))).cuda()
+    C0, S0, C1, S1 = (torch.empty_like(A) for _ in range(4))
+    p = sc.sincosm_eval(A, C0, S0, "single", "i8x5")
+    sc.sincosm_eval_planned(A, C1, S1, p, "single", "i8x5")
+    torch.cuda.synchronize()
+    assert torch.equal(C0, C1) and torch.equal(S0, S1)
+    sc.sincosm_eval(A, C1, S1, "single", "i8x5", refined=True)
+    torch.cuda.synchronize()
+    Cr, Sr = R.sincosm(A.cpu().numpy())
+    assert rel_fro(C1.cpu().numpy(), Cr) <= 5e-6 and rel_fro(S1.cpu().numpy(), Sr) <= 5e-6

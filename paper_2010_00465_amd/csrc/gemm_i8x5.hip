@@ -20,10 +20,9 @@
 // operand by columns, transposed so that both read 64 consecutive k bytes per
 // row of the tile), then the product kernel: 64 x 64 output tiles of four
 // waves (2 x 2 blocks of 16 x 16 each), k steps of 64 on
-// v_mfma_i32_16x16x64_i8, the slices staged through one LDS buffer (the next
-// step's slices wait in registers) with a row stride of 80 bytes (the 16 rows
-// of a fragment read fall on distinct banks), and the fused linear-combination
-// epilogue of the other product kernels.
+// v_mfma_i32_16x16x64_i8, the slices loaded straight into two LDS buffers
+// (64-byte rows whose 16-byte slots are permuted against bank conflicts), and
+// the fused linear-combination epilogue of the other product kernels.
 #include <math.h>
 
 #include "epilogue.hpp"
@@ -37,11 +36,10 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int NS = 5;            // slices per operand (7 bits each)
 constexpr int QT = 64;           // output tile and k step
 constexpr int QTHR = 256;        // threads of the product kernel (4 waves)
-constexpr int QROW = 80;         // LDS bytes per staged row (64 data + 16 pad)
+constexpr int QROW = 64;         // LDS bytes per staged row (16-byte slots permuted, no padding)
 constexpr int QPLANE = QT * QROW;             // bytes per staged plane
 constexpr int QSTAGE = 2 * NS * QPLANE;       // A and B planes of one k step
-constexpr int QLDS = QSTAGE;                  // one buffer: 2 workgroups per CU
-constexpr int QPIECES = 2 * NS * QT * 4 / QTHR;   // 16-byte staging loads per thread and k step
+constexpr int QLDS = 2 * QSTAGE;              // two buffers: 160 KiB for 2 workgroups per CU
 
 // result layout of the int8 16 x 16 MFMA: lane (lr, lg), register r -> row 4 lg + r, column lr
 struct MI8 {
@@ -160,6 +158,20 @@ __global__ void zero_u64_kernel(unsigned long long* p, int n) {
   if (i < n) p[i] = 0ull;
 }
 
+// Output tile of this workgroup: consecutive workgroups go to different XCDs
+// (round robin), so when the tile count allows, each XCD takes a contiguous
+// range of tiles; within it, groups of 8 tile rows are walked column by
+// column, so that the panels a group shares stay in that XCD's L2.
+__device__ inline void i8_tile_coords(int tpd, int& tm, int& tn) {
+  const int tiles = tpd * tpd, b = blockIdx.x;
+  const int t = (tiles & 7) == 0 ? (b & 7) * (tiles >> 3) + (b >> 3) : b;
+  const int group = t / (8 * tpd), first = group * 8;
+  const int rows = tpd - first < 8 ? tpd - first : 8;
+  const int in_group = t - group * 8 * tpd;
+  tm = first + in_group % rows;
+  tn = in_group / rows;
+}
+
 // The product kernel. A: planes of the left operand by rows, B: planes of
 // the right operand's transpose; both [NS][np][np] int8.
 __global__ __launch_bounds__(QTHR) void gemm_i8x5_kernel(const int8_t* __restrict__ A,
@@ -170,44 +182,40 @@ __global__ __launch_bounds__(QTHR) void gemm_i8x5_kernel(const int8_t* __restric
   __shared__ __attribute__((aligned(16))) unsigned char smem[QLDS];
   const Problem& P = g.prob[0];
   const int np = g.np;
-  const int tiles = np / QT;
-  const int tile_m = blockIdx.x / tiles, tile_n = blockIdx.x - (blockIdx.x / tiles) * tiles;
+  int tile_m, tile_n;
+  i8_tile_coords(np / QT, tile_m, tile_n);
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave >> 1, wn = wave & 1;
   const int lr = lane & 15, lg = lane >> 4;
   const int64_t plane = (int64_t)np * np;
   const int nk = np / QT;
 
-  // global -> register staging: per k step 2 operands x NS planes x 64 rows x
-  // 64 bytes in pieces of 16 bytes, QPIECES per thread
-  v4i st[QPIECES];
-  auto piece_at = [&](int u, int& op, int& pl, int& row, int& q) {
-    const int piece = u * QTHR + tid;              // 0 .. 2 NS 256 - 1
-    op = piece / (NS * 256);
-    const int rem = piece - op * (NS * 256);
-    pl = rem >> 8;
-    row = (rem >> 2) & 63;
-    q = rem & 3;
-  };
-  auto gload = [&](int kt) {
+  // Direct loads (global_load_lds, 16 bytes per lane): one wave instruction
+  // fills 1 KiB of LDS, 16 rows of one plane, lane l writing row l >> 2 at
+  // slot l & 3. Slot s of row r holds k chunk s ^ ((r >> 2) & 3) of that row,
+  // so the lane loads chunk (l & 3) ^ ((l >> 4) & 3). Wave w fills rows
+  // 16 w .. 16 w + 15 of every plane of both operands. With 64-byte rows,
+  // rows r, r + 4, r + 8, r + 12 fall on the same banks; the permutation puts
+  // their k chunks on distinct slots, so the 16 rows of a fragment read (and
+  // the 4 rows x 4 slots of a load) cover the 64 banks once.
+  typedef __attribute__((address_space(3))) void lds_void;
+  typedef __attribute__((address_space(1))) void glb_void;
+  const int lrow = wave * 16 + (lane >> 2);
+  const int lchunk = 16 * ((lane & 3) ^ ((lane >> 4) & 3));
+  const int8_t* const arow = A + (int64_t)(tile_m * QT + lrow) * np + lchunk;
+  const int8_t* const brow = B + (int64_t)(tile_n * QT + lrow) * np + lchunk;
+  auto dload = [&](int buf, int kt) {
     const int k0 = kt * QT;
+    unsigned char* dst = smem + buf * QSTAGE + wave * 1024;
 #pragma unroll
-    for (int u = 0; u < QPIECES; ++u) {
-      int op, pl, row, q;
-      piece_at(u, op, pl, row, q);
-      const int8_t* src = op == 0 ? A + pl * plane + (int64_t)(tile_m * QT + row) * np + k0 + 16 * q
-                                  : B + pl * plane + (int64_t)(tile_n * QT + row) * np + k0 + 16 * q;
-      st[u] = *(const v4i*)src;
+    for (int u = 0; u < 2 * NS; ++u) {
+      const int8_t* src = (u < NS ? arow + u * plane : brow + (u - NS) * plane) + k0;
+      __builtin_amdgcn_global_load_lds((glb_void*)src, (lds_void*)(dst + u * QPLANE), 16, 0, 0);
     }
   };
-  auto lstore = [&]() {
-#pragma unroll
-    for (int u = 0; u < QPIECES; ++u) {
-      int op, pl, row, q;
-      piece_at(u, op, pl, row, q);
-      *(v4i*)(smem + (op * NS + pl) * QPLANE + row * QROW + 16 * q) = st[u];
-    }
-  };
+  // fragment rows: wm 32 + 16 i + lr (A), wn 32 + 16 i + lr (B); k chunk lg
+  const int rslot = 16 * (lg ^ ((lr >> 2) & 3));
+  const int ra0 = (wm * 32 + lr) * QROW + rslot, rb0 = NS * QPLANE + (wn * 32 + lr) * QROW + rslot;
 
   constexpr int NG = NS;   // groups k + l = 0 .. NS - 1 (slice indices from 0)
   v4i acc[NG][2][2];
@@ -218,20 +226,32 @@ __global__ __launch_bounds__(QTHR) void gemm_i8x5_kernel(const int8_t* __restric
 #pragma unroll
       for (int j = 0; j < 2; ++j) acc[gq][i][j] = (v4i){0, 0, 0, 0};
 
-  gload(0);
-  lstore();
+  // Two buffers, one barrier per k step. The buffer a step loads was last
+  // read in the step before: every wave finished those reads before the
+  // barrier that ended that step. Each wave waits for its own direct loads
+  // (vmcnt) before the barrier that publishes them; the last barrier also
+  // frees the LDS for the epilogue.
+  // Step kt first issues the loads of step kt + 1 into the other buffer (the
+  // last step loads its own k block again, so that the loop body has no
+  // branch: the copy is never read, and it has landed before the final
+  // barrier), then reads its fragments from buffer kt & 1 and runs its MFMAs.
+  // The scheduling barriers keep the loads at the start of the step and every
+  // MFMA ahead of the wait for them, so that the loads overlap the products.
+  dload(0, 0);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
-    if (kt + 1 < nk) gload(kt + 1);   // in registers while this step computes
-    const unsigned char* sa = smem;
-    const unsigned char* sb = sa + NS * QPLANE;
+    const int buf = kt & 1;
+    const unsigned char* sb = smem + buf * QSTAGE;
+    dload(buf ^ 1, kt + 1 < nk ? kt + 1 : kt);
+    __builtin_amdgcn_sched_barrier(0);
     v4i fa[NS][2], fb[NS][2];
 #pragma unroll
     for (int p = 0; p < NS; ++p)
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        fa[p][i] = *(const v4i*)(sa + p * QPLANE + (wm * 32 + i * 16 + lr) * QROW + 16 * lg);
-        fb[p][i] = *(const v4i*)(sb + p * QPLANE + (wn * 32 + i * 16 + lr) * QROW + 16 * lg);
+        fa[p][i] = *(const v4i*)(sb + p * QPLANE + ra0 + i * 16 * QROW);
+        fb[p][i] = *(const v4i*)(sb + p * QPLANE + rb0 + i * 16 * QROW);
       }
 #pragma unroll
     for (int k = 0; k < NS; ++k)
@@ -244,11 +264,9 @@ __global__ __launch_bounds__(QTHR) void gemm_i8x5_kernel(const int8_t* __restric
           for (int j = 0; j < 2; ++j)
             acc[k + l][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[k][i], fb[l][j], acc[k + l][i][j], 0, 0, 0);
       }
-    if (kt + 1 < nk) {
-      __syncthreads();   // every wave has read this step's slices
-      lstore();
-      __syncthreads();
-    }
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
   }
 
   // float64 values of the block results: sum over k + l, then the row and

@@ -305,37 +305,47 @@ def bench_backward(torch, sc, W):
 
 
 def bench_tiers(torch, sc, W):
-    """n = 4096: 2-D 5-point Laplacian on a 64 x 64 grid scaled to ||A||_1 = 64; each product
-    arithmetic with its plan table: time and relative error against the float64 CPU oracle; for
-    each lowered tier, the float64 path with the error closest to it from below (matched
-    accuracy: the same or better error)."""
+    """n = 4096: 2-D 5-point Laplacian on a 64 x 64 grid scaled to ||A||_1 = 64, and a Gaussian
+    matrix of the same norm; each product arithmetic with its plan table: time and relative error
+    against the float64 CPU oracle; for each lowered tier, the float64 path with the error closest
+    to it from below (matched accuracy: the same or better error)."""
     from oracle import reference as R
-    Anp = W.laplacian_2d(64, 64.0)
-    A = torch.from_numpy(Anp).cuda()
-    Cr, Sr = R.sincosm(Anp)
+
+    def one(Anp):
+        A = torch.from_numpy(Anp).cuda()
+        Cr, Sr = R.sincosm(Anp)
+        out = {}
+        for name, acc, prod in (("fp64_double", "double", "native"), ("fp64_single_plan", "single", "native"),
+                                ("fp32_products", "single", "f32"), ("bf16x3_products", "single", "bf16x3"),
+                                ("int8x5_products", "single", "i8x5")):
+            C = torch.empty_like(A)
+            S = torch.empty_like(A)
+            ws = torch.empty(sc.workspace_size(4096, torch.float64, acc, prod), dtype=torch.uint8, device="cuda")
+            plan = sc.sincosm_eval(A, C, S, acc, prod, ws=ws)
+            t = _elapsed(torch, lambda: sc.sincosm_eval(A, C, S, acc, prod, ws=ws), 3)
+            ec = float(np.linalg.norm(C.cpu().numpy() - Cr) / np.linalg.norm(Cr))
+            es = float(np.linalg.norm(S.cpu().numpy() - Sr) / np.linalg.norm(Sr))
+            out[name] = {"ms": 1e3 * t, "plan": [plan.level, plan.s], "products": plan.products,
+                         "rel_err_cos": ec, "rel_err_sin": es}
+            del ws
+        fp64 = [k for k in ("fp64_single_plan", "fp64_double")]
+        for tier in ("fp32_products", "bf16x3_products", "int8x5_products"):
+            err = max(out[tier]["rel_err_cos"], out[tier]["rel_err_sin"])
+            ok = [k for k in fp64 if max(out[k]["rel_err_cos"], out[k]["rel_err_sin"]) <= err]
+            best = min(ok, key=lambda k: out[k]["ms"]) if ok else None
+            out[tier]["matched_accuracy_fp64"] = None if best is None else {
+                "path": best, "ms": out[best]["ms"],
+                "rel_err": max(out[best]["rel_err_cos"], out[best]["rel_err_sin"]),
+                "speedup_of_tier": out[best]["ms"] / out[tier]["ms"]}
+            out[tier]["meets_single_accuracy_5e-6"] = err <= 5e-6
+        return out
+
     out = {"workload": "n=4096 2-D Laplacian (64 x 64 grid), ||A||_1 = 64, float64 storage; errors relative "
                        "to the float64 CPU oracle"}
-    for name, acc, prod in (("fp64_double", "double", "native"), ("fp64_single_plan", "single", "native"),
-                            ("fp32_products", "single", "f32"), ("bf16x3_products", "single", "bf16x3"),
-                            ("int8x5_products", "single", "i8x5")):
-        C = torch.empty_like(A)
-        S = torch.empty_like(A)
-        ws = torch.empty(sc.workspace_size(4096, torch.float64, acc, prod), dtype=torch.uint8, device="cuda")
-        plan = sc.sincosm_eval(A, C, S, acc, prod, ws=ws)
-        t = _elapsed(torch, lambda: sc.sincosm_eval(A, C, S, acc, prod, ws=ws), 3)
-        ec = float(np.linalg.norm(C.cpu().numpy() - Cr) / np.linalg.norm(Cr))
-        es = float(np.linalg.norm(S.cpu().numpy() - Sr) / np.linalg.norm(Sr))
-        out[name] = {"ms": 1e3 * t, "plan": [plan.level, plan.s], "products": plan.products,
-                     "rel_err_cos": ec, "rel_err_sin": es}
-    fp64 = [k for k in ("fp64_single_plan", "fp64_double")]
-    for tier in ("fp32_products", "bf16x3_products", "int8x5_products"):
-        err = max(out[tier]["rel_err_cos"], out[tier]["rel_err_sin"])
-        ok = [k for k in fp64 if max(out[k]["rel_err_cos"], out[k]["rel_err_sin"]) <= err]
-        best = min(ok, key=lambda k: out[k]["ms"]) if ok else None
-        out[tier]["matched_accuracy_fp64"] = None if best is None else {
-            "path": best, "ms": out[best]["ms"], "rel_err": max(out[best]["rel_err_cos"], out[best]["rel_err_sin"]),
-            "speedup_of_tier": out[best]["ms"] / out[tier]["ms"]}
-        out[tier]["meets_single_accuracy_5e-6"] = err <= 5e-6
+    out.update(one(W.laplacian_2d(64, 64.0)))
+    out["gaussian"] = dict(workload="n=4096 Gaussian N(0,1) rescaled to ||A||_1 = 64, float64 storage; errors "
+                                    "relative to the float64 CPU oracle",
+                           **one(W.gaussian(4096, 64.0, key=(7, 4096))))
     return out
 
 

@@ -98,10 +98,14 @@ enum { SINCOSM_PLAN_REFINED = 32 };
  *           on the int8 matrix cores by error-free splitting (Ozaki's scheme): the
  *           left operand's rows and the right operand's columns are scaled by
  *           powers of two and written as five 7-bit digits, the 15 digit products
- *           of significance above 2^-49 accumulate exactly in int32 and are
- *           combined in float64; product error below 2^-33 |X||Y| elementwise
- *           (|.| taken entrywise), far inside the single-accuracy bound
- *           u = 2^-24 of Table 2, not the double one. dtype F64 only,
+ *           of weight 2^-14 ... 2^-42 accumulate exactly in int32 and are combined
+ *           in float64. Elementwise product error at most
+ *           2^-34 (rowmax|X| colsum|Y| + rowsum|X| colmax|Y|) for the digits cut
+ *           off, plus 2^-31 n rowmax|X| colmax|Y| for the digit products left out
+ *           (reached only when digits agree in sign throughout; for uncorrelated
+ *           digits those sums grow like n^(1/2) and the first term dominates):
+ *           inside the single-accuracy bound u = 2^-24 of Table 2, not the
+ *           double one. dtype F64 only,
  *           n <= 16384, sincosm_eval, sincosm_eval_planned (and its no-allocation
  *           form) and sincosm_matmul only (elsewhere SINCOSM_E_UNSUPPORTED).
  * The 1-norm, the plan and the double-angle steps always run in the storage

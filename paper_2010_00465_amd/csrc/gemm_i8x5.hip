@@ -8,13 +8,18 @@
 // digits, x = 2^e_i sum_{k=1..5} d_k 2^-7k, exactly up to a remainder below
 // 2^(e_i - 35); every column j of Y likewise with 2^f_j. Then
 //   (X Y)_ij = 2^(e_i + f_j) sum_{k, l} 2^-7(k + l) (D_k E_l)_ij,
-// each D_k E_l an int8 product with exact int32 accumulation. The pairs with
-// k + l <= 6 are kept (15 products; the others weigh 2^-49 of the leading
-// term), summed per k + l in int32 (exact up to order 26000), and combined in
-// float64. The product error is about 2^-34 |X| |Y| elementwise. Four digits
-// (28 bits) were measured too few: the schemes' intermediates cancel, and the
-// double-angle steps double what is left, so at s = 6 the single-accuracy bar
-// was exceeded; five leave a margin of about two orders of magnitude.
+// each D_k E_l an int8 product with exact int32 accumulation. The 15 pairs
+// with k + l <= 6 are kept, summed per k + l in int32 (exact up to order
+// 26000) and combined in float64. Error, elementwise: the digits cut off give
+// at most 2^-34 (rowmax|X| colsum|Y| + rowsum|X| colmax|Y|); the 10 pairs
+// left out (weights 2^-49 and below, digits up to 127) at most
+// 2^-33 n 2^(e_i + f_j) < 2^-31 n rowmax|X| colmax|Y|, a bound reached only
+// when the digits agree in sign along the inner dimension; for uncorrelated
+// digits their sums grow like n^(1/2) and the first term dominates. Four
+// digits (28 bits) were measured too few: the schemes' intermediates cancel,
+// and the double-angle steps double what is left, so at s = 6 the
+// single-accuracy bar was exceeded; five leave a margin of about two orders
+// of magnitude.
 //
 // Three preparation kernels write the slices (left operand by rows, right
 // operand by columns, transposed so that both read 64 consecutive k bytes per
@@ -257,7 +262,7 @@ __global__ __launch_bounds__(QTHR) void gemm_i8x5_kernel(const int8_t* __restric
     for (int k = 0; k < NS; ++k)
 #pragma unroll
       for (int l = 0; l < NS; ++l) {
-        if (k + l > NS - 1) continue;   // weights 2^-7(k + l + 2): keep those above 2^-49
+        if (k + l > NS - 1) continue;   // weights 2^-7(k + l + 2) down to 2^-42 kept
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll

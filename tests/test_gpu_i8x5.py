@@ -1,18 +1,21 @@
 """Products on the int8 matrix cores by error-free splitting (SINCOSM_PROD_I8X5) through the C ABI.
 
 The product alone (sincosm_matmul): every operand entry is kept to 35 bits below its row's
-(left operand) or column's (right operand) largest power of two, so the elementwise error of
-Z = X Y is at most 2^-34 (rowmax_i |X| colsum_j |Y| + rowsum_i |X| colmax_j |Y|) plus the
-omitted digit products (2^-49 of the leading term) and the float64 combination; the test
-gates at twice that.
+(left operand) or column's (right operand) largest power of two, and the digit products of
+weight below 2^-42 are left out, so the elementwise error of Z = X Y is at most
+  T1 + T2,  T1 = 2^-34 (rowmax_i |X| colsum_j |Y| + rowsum_i |X| colmax_j |Y|),
+            T2 = 2^-31 n rowmax_i |X| colmax_j |Y|
+plus the float64 combination. T2 is reached only when digits agree in sign along the inner
+dimension (tested with every digit at 127); for uncorrelated digits (Gaussian and graded
+operands) its sums grow like n^(1/2) and the tests gate at 2 T1 alone.
 Whole evaluations (sincosm_eval, float64 storage, intermediates and epilogues in float64, the
 squarings in float64): against the float64 oracle at the single-accuracy bar 5e-6 for the
 single plan (Table 2), and for the double plan at a bound derived from the product's: in the
-Frobenius norm the elementwise bound gives ||E|| <= 2^-33 n^(1/2) ||X|| ||Y|| (a row maximum is
-at most the row's norm, a column sum at most n^(1/2) times the column's norm), so the schemes'
-Pi products and the s squarings, each at most doubling what came before, keep the relative
-error below 8 Pi 2^-33 n^(1/2) 2^s (8 covering the growth of the intermediates, as for the
-tiers' bounds in float32)."""
+Frobenius norm T1 gives at most 2^-33 n^(1/2) ||X|| ||Y|| (a row maximum is at most the row's
+norm, a column sum at most n^(1/2) times the column's norm) and T2 at most 2^-31 n ||X|| ||Y||,
+so the schemes' Pi products and the s squarings, each at most doubling what came before, keep
+the relative error below 8 Pi (2^-33 n^(1/2) + 2^-31 n) 2^s (8 covering the growth of the
+intermediates, as for the tiers' bounds in float32)."""
 import sys
 
 import numpy as np
@@ -91,7 +94,7 @@ def test_i8x5_eval_double_plan_bound(env, e):
     p = sc.sincosm_eval(At, C, S, "double", "i8x5")
     torch.cuda.synchronize()
     Cr, Sr = R.sincosm(A)
-    bound = 8.0 * p.level * 2.0 ** -33 * np.sqrt(n) * 2.0 ** p.s
+    bound = 8.0 * p.level * (2.0 ** -33 * np.sqrt(n) + 2.0 ** -31 * n) * 2.0 ** p.s
     ec, es = rel_fro(C.cpu().numpy(), Cr), rel_fro(S.cpu().numpy(), Sr)
     say("i8x5 double-plan errors", p.level, p.s, ec, es, bound)
     assert ec <= bound and es <= bound
@@ -127,3 +130,72 @@ def test_i8x5_planned_and_refined(env):
     torch.cuda.synchronize()
     Cr, Sr = R.sincosm(A.cpu().numpy())
     assert rel_fro(C1.cpu().numpy(), Cr) <= 5e-6 and rel_fro(S1.cpu().numpy(), Sr) <= 5e-6
+
+
+def test_i8x5_largest_order_int32_range(env):
+    """n = 16384, the largest order the int8 products take, with every digit at its largest
+    magnitude (all entries 1 - 2^-36: five digits of 127 each), so each of the five int32 sums
+    reaches its bound 5 n 127^2 = 1.32e9 < 2^31 and the digit products left out reach theirs
+    (gate T1 + T2); sampled rows of a Gaussian product of the same order against the float64 host
+    product (gate 2 T1)."""
+    torch, sc = env
+    n = 16384
+    say("i8x5 largest order", n)
+    v = 1.0 - 2.0 ** -36
+    X = torch.full((n, n), v, dtype=torch.float64, device="cuda")
+    Z = torch.empty_like(X)
+    sc.sincosm_matmul(X, X, Z, products="i8x5")
+    torch.cuda.synchronize()
+    exact = n * v * v
+    zr = Z[::4097, ::4097].cpu().numpy()
+    bound = 2.0 ** -34 * 2 * n * v * v + 2.0 ** -31 * n * v * v
+    say("constant product worst error / (T1 + T2)", float(np.abs(zr - exact).max() / bound))
+    assert np.abs(zr - exact).max() <= bound
+    del X
+    g = W.rng(184, n)
+    Xg = torch.from_numpy(g.standard_normal((n, n))).cuda()
+    Yg = torch.from_numpy(g.standard_normal((n, n))).cuda()
+    sc.sincosm_matmul(Xg, Yg, Z, products="i8x5")
+    torch.cuda.synchronize()
+    rows = np.array([0, 1, 5000, 9999, n - 2, n - 1])
+    Xr = Xg[rows].cpu().numpy()
+    Yh = Yg.cpu().numpy()
+    Zr = Xr @ Yh
+    aY = np.abs(Yh)
+    bound = 2.0 ** -34 * (np.outer(np.abs(Xr).max(1), aY.sum(0)) + np.outer(np.abs(Xr).sum(1), aY.max(0)))
+    err = np.abs(Z[rows].cpu().numpy() - Zr)
+    ratio = float((err / (2.0 * bound)).max())
+    say("sampled rows worst error / (2 bound)", ratio)
+    assert ratio <= 1.0
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65])
+def test_i8x5_small_orders(env, n):
+    """Orders at and around one 64 x 64 tile (and n = 1) against the float64 oracle at the
+    single bar."""
+    torch, sc = env
+    say("i8x5 small order", n)
+    A = W.gaussian(n, 3.0, key=(185, n))
+    At = torch.from_numpy(A).cuda()
+    C, S = torch.empty_like(At), torch.empty_like(At)
+    sc.sincosm_eval(At, C, S, "single", "i8x5")
+    torch.cuda.synchronize()
+    Cr, Sr = R.sincosm(A)
+    assert rel_fro(C.cpu().numpy(), Cr) <= 5e-6 and rel_fro(S.cpu().numpy(), Sr) <= 5e-6
+
+
+def test_i8x5_noalloc_matches_planned(env):
+    """The entry point that allocates nothing with int8 products: bitwise equal to
+    sincosm_eval_planned, on two calls in a row (the second of smaller order) sharing the
+    library's scratch."""
+    torch, sc = env
+    for n in (300, 130):
+        say("i8x5 noalloc", n)
+        A = torch.from_numpy(W.gaussian(n, 12.0, key=(186, n))).cuda()
+        plan = sc.plan_host(float(A.abs().sum(0).max()), "single")
+        C0, S0 = torch.empty_like(A), torch.empty_like(A)
+        C1, S1 = torch.full_like(A, 7.0), torch.full_like(A, 7.0)
+        sc.sincosm_eval_planned(A, C0, S0, plan, "single", "i8x5")
+        sc.sincosm_eval_planned_noalloc(A, C1, S1, plan, "single", "i8x5")
+        torch.cuda.synchronize()
+        assert torch.equal(C0, C1) and torch.equal(S0, S1)

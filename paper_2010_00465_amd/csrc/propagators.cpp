@@ -39,7 +39,6 @@ sincosm_status sincosm_expi_eval(int64_t n, int dtype, const void* A, int64_t ld
   }
   if (((uintptr_t)U) & (2 * es - 1)) return SINCOSM_E_ARG;   // complex elements must be aligned pairs
   if (m.poly == Arith::BF16X3 && !bf16x3_available()) return SINCOSM_E_UNSUPPORTED;
-  if (m.poly == Arith::I8X5) return SINCOSM_E_UNSUPPORTED;   // sincosm_eval and sincosm_eval_planned only
   const Layout L = layout_for(m);
   if (!ws || ws_bytes < L.total || ((uintptr_t)ws & 255u)) return SINCOSM_E_WORKSPACE;
   hipStream_t stream = (hipStream_t)stream_;
@@ -61,6 +60,7 @@ sincosm_status sincosm_expi_eval(int64_t n, int dtype, const void* A, int64_t ld
   r.n = n;
   r.Ap = Xp;
   for (int i = 0; i < 9; ++i) r.W[i] = base + L.w_off[i];
+  r.i8ws = base + L.i8_off;
   r.stream = stream;
   void* Q[4];
   for (int i = 0; i < 4; ++i) Q[i] = base + L.q_off[i];
@@ -102,7 +102,7 @@ sincosm_status sincosm_expi_eval_async(int64_t n, int dtype, const void* A, int6
   }
   if (((uintptr_t)U) & (2 * es - 1)) return SINCOSM_E_ARG;
   if (m.poly == Arith::BF16X3 && !bf16x3_available()) return SINCOSM_E_UNSUPPORTED;
-  if (m.poly == Arith::I8X5) return SINCOSM_E_UNSUPPORTED;   // sincosm_eval and sincosm_eval_planned only
+  if (m.poly == Arith::I8X5) return SINCOSM_E_UNSUPPORTED;   // its launches take no DevCond
   const Layout L = layout_for(m);
   if (!ws || ws_bytes < L.total || ((uintptr_t)ws & 255u)) return SINCOSM_E_WORKSPACE;
   Run r;

@@ -199,3 +199,34 @@ def test_i8x5_noalloc_matches_planned(env):
         sc.sincosm_eval_planned_noalloc(A, C1, S1, plan, "single", "i8x5")
         torch.cuda.synchronize()
         assert torch.equal(C0, C1) and torch.equal(S0, S1)
+
+
+@pytest.mark.parametrize("n,e", [(64, 1), (300, 6), (1000, 9)])
+def test_i8x5_wave_pair(env, n, e):
+    """The wave pair c(t^2 A), s(t, A) (Section 2.2) with int8 scheme products: the
+    single-accuracy bar against the oracle (s up to 4 here: ||B||_1 = 2^9)."""
+    from oracle import wave as Wv
+    torch, sc = env
+    say("i8x5 wave", n, e)
+    A = W.gaussian(n, 2.0 ** e, key=(187, n))
+    C, S = sc.wave(torch.from_numpy(A).cuda(), 1.0, "single", "i8x5")
+    Cr, Sr = Wv.reference(A, 1.0)
+    assert rel_fro(C.cpu().numpy(), Cr) <= 5e-6 and rel_fro(S.cpu().numpy(), Sr) <= 5e-6
+
+
+@pytest.mark.parametrize("n,e", [(64, 1), (300, 6)])
+def test_i8x5_propagators(env, n, e):
+    """e^{-itA} and the block propagator e^{tM} with int8 scheme products against the oracle
+    at the single-accuracy bar; the device-planned forms reject the arithmetic."""
+    from oracle import propagators as Pr
+    torch, sc = env
+    say("i8x5 propagators", n, e)
+    A = W.gaussian(n, 2.0 ** e, key=(188, n))
+    At = torch.from_numpy(A).cuda()
+    U = sc.expi(At, 1.0, "single", "i8x5")
+    assert rel_fro(U.cpu().numpy(), Pr.unitary(A, 1.0)) <= 5e-6
+    E = sc.wave_block(At, 1.0, "single", "i8x5")
+    assert rel_fro(E.cpu().numpy(), Pr.symplectic(A, 1.0)) <= 5e-6
+    Ua = torch.empty(n, n, dtype=torch.complex128, device="cuda")
+    with pytest.raises(sc.SincosmError):
+        sc.sincosm_expi_eval_async(At, 1.0, Ua, accuracy="single", products="i8x5")

@@ -72,10 +72,36 @@ __device__ inline void slice_digits(double y, int8_t (&d)[NS]) {
   }
 }
 
+// The operands of a launch's problems and its device-side condition, for the
+// preparation kernels.
+struct I8Operands {
+  DevCond cond;
+  int nprob;
+  const double* L[MAX_PROB];
+  const double* R[MAX_PROB];
+  int64_t ldl[MAX_PROB], ldr[MAX_PROB];
+};
+
+// The problem a launch computes: 0 for a launch without a device plan, else
+// the one the plan record selects; -1 when the record rules the launch out
+// (every workgroup of every kernel of the product then returns at once).
+__device__ inline int i8_problem(const DevCond& c, int nprob, int& s) {
+  s = 0;
+  if (!c.plan) return 0;
+  int level;
+  if (!cond_applies(c, s, level)) return -1;
+  return c.select ? cond_problem(c, nprob, level) : 0;
+}
+
 // Left operand: one workgroup per row; planes P[k][i][c] (np x np each).
-__global__ __launch_bounds__(256) void slice_rows_kernel(const double* __restrict__ X, int64_t ld, int np,
-                                                         int8_t* __restrict__ P, int* __restrict__ ex) {
+__global__ __launch_bounds__(256) void slice_rows_kernel(const I8Operands op, int np, int8_t* __restrict__ P,
+                                                         int* __restrict__ ex) {
   __shared__ unsigned long long red[256];
+  int s;
+  const int q = i8_problem(op.cond, op.nprob, s);
+  if (q < 0) return;
+  const double* __restrict__ X = op.L[q];
+  const int64_t ld = op.ldl[q];
   const int i = blockIdx.x, tid = threadIdx.x;
   const double* row = X + (int64_t)i * ld;
   unsigned long long m = 0ull;
@@ -102,9 +128,13 @@ __global__ __launch_bounds__(256) void slice_rows_kernel(const double* __restric
 
 // Right operand, pass 1: column maxima (bit patterns of |x|, compared as
 // integers) over 64 x 64 blocks into cmax (zeroed by the caller).
-__global__ __launch_bounds__(256) void col_max_kernel(const double* __restrict__ X, int64_t ld, int np,
-                                                      unsigned long long* __restrict__ cmax) {
+__global__ __launch_bounds__(256) void col_max_kernel(const I8Operands op, unsigned long long* __restrict__ cmax) {
   __shared__ unsigned long long red[4][64];
+  int s;
+  const int q = i8_problem(op.cond, op.nprob, s);
+  if (q < 0) return;
+  const double* __restrict__ X = op.R[q];
+  const int64_t ld = op.ldr[q];
   const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
   const int tid = threadIdx.x, c = tid & 63, g = tid >> 6;
   unsigned long long m = 0ull;
@@ -123,10 +153,15 @@ __global__ __launch_bounds__(256) void col_max_kernel(const double* __restrict__
 
 // Right operand, pass 2: planes of the transpose, P[l][j][r] = digit l of
 // X[r][j] 2^-f_j, one 64 x 64 block per workgroup through LDS.
-__global__ __launch_bounds__(256) void slice_cols_kernel(const double* __restrict__ X, int64_t ld, int np,
+__global__ __launch_bounds__(256) void slice_cols_kernel(const I8Operands op, int np,
                                                          const unsigned long long* __restrict__ cmax,
                                                          int8_t* __restrict__ P, int* __restrict__ ex) {
   __shared__ double tile[64][65];
+  int s;
+  const int q = i8_problem(op.cond, op.nprob, s);
+  if (q < 0) return;
+  const double* __restrict__ X = op.R[q];
+  const int64_t ld = op.ldr[q];
   const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
   const int tid = threadIdx.x;
   for (int e = tid; e < 64 * 64; e += 256) {
@@ -182,10 +217,13 @@ __device__ inline void i8_tile_coords(int tpd, int& tm, int& tn) {
 __global__ __launch_bounds__(QTHR) void gemm_i8x5_kernel(const int8_t* __restrict__ A,
                                                            const int8_t* __restrict__ B,
                                                            const int* __restrict__ ea,
-                                                           const int* __restrict__ eb, double scale,
-                                                           GemmLaunch g) {
+                                                           const int* __restrict__ eb, GemmLaunch g) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[QLDS];
-  const Problem& P = g.prob[0];
+  int dyn_s;
+  const int pq = i8_problem(g.cond, g.nprob, dyn_s);
+  if (pq < 0) return;   // uniform: the whole workgroup leaves
+  const Problem& P = g.prob[pq];
+  const double scale = resolve_scale(P.seg[0].lscale, dyn_s) * resolve_scale(P.seg[0].rscale, dyn_s);
   const int np = g.np;
   int tile_m, tile_n;
   i8_tile_coords(np / QT, tile_m, tile_n);
@@ -303,8 +341,21 @@ size_t i8x5_scratch_bytes(int64_t np) {
 sincosm_status launch_gemm_i8x5(const GemmLaunch& g, void* scratch, hipStream_t stream) {
   const int np = g.np;
   if (!scratch || np <= 0 || np % QT != 0 || np > 16384) return SINCOSM_E_UNSUPPORTED;
-  if (g.nprob != 1 || g.prob[0].nseg != 1 || g.cond.plan) return SINCOSM_E_UNSUPPORTED;
-  const Seg& sg = g.prob[0].seg[0];
+  // one problem, or (device-planned, select) alternatives of which the plan
+  // record picks one; each a single k segment
+  if (g.nprob < 1 || g.nprob > MAX_PROB || (g.nprob > 1 && !(g.cond.plan && g.cond.select)))
+    return SINCOSM_E_UNSUPPORTED;
+  I8Operands op;
+  op.cond = g.cond;
+  op.nprob = g.nprob;
+  for (int q = 0; q < g.nprob; ++q) {
+    if (g.prob[q].nseg != 1) return SINCOSM_E_UNSUPPORTED;
+    const Seg& sg = g.prob[q].seg[0];
+    op.L[q] = (const double*)sg.L;
+    op.R[q] = (const double*)sg.R;
+    op.ldl[q] = sg.ldl;
+    op.ldr[q] = sg.ldr;
+  }
   const size_t planes = (size_t)NS * (size_t)np * (size_t)np;
   char* base = (char*)scratch;
   int8_t* Ap = (int8_t*)base;
@@ -312,13 +363,13 @@ sincosm_status launch_gemm_i8x5(const GemmLaunch& g, void* scratch, hipStream_t 
   int* ea = (int*)(base + 2 * align_up(planes, 256));
   int* eb = (int*)((char*)ea + align_up((size_t)np * 4, 256));
   unsigned long long* cmax = (unsigned long long*)((char*)eb + align_up((size_t)np * 4, 256));
-  slice_rows_kernel<<<np, 256, 0, stream>>>((const double*)sg.L, sg.ldl, np, Ap, ea);
+  slice_rows_kernel<<<np, 256, 0, stream>>>(op, np, Ap, ea);
   zero_u64_kernel<<<(np + 255) / 256, 256, 0, stream>>>(cmax, np);
   dim3 gb(np / 64, np / 64);
-  col_max_kernel<<<gb, 256, 0, stream>>>((const double*)sg.R, sg.ldr, np, cmax);
-  slice_cols_kernel<<<gb, 256, 0, stream>>>((const double*)sg.R, sg.ldr, np, cmax, Bp, eb);
+  col_max_kernel<<<gb, 256, 0, stream>>>(op, cmax);
+  slice_cols_kernel<<<gb, 256, 0, stream>>>(op, np, cmax, Bp, eb);
   const int tiles = np / QT;
-  gemm_i8x5_kernel<<<tiles * tiles, QTHR, 0, stream>>>(Ap, Bp, ea, eb, sg.lscale * sg.rscale, g);
+  gemm_i8x5_kernel<<<tiles * tiles, QTHR, 0, stream>>>(Ap, Bp, ea, eb, g);
   SC_HIP(hipGetLastError());
   return SINCOSM_OK;
 }

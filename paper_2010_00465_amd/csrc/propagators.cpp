@@ -102,7 +102,6 @@ sincosm_status sincosm_expi_eval_async(int64_t n, int dtype, const void* A, int6
   }
   if (((uintptr_t)U) & (2 * es - 1)) return SINCOSM_E_ARG;
   if (m.poly == Arith::BF16X3 && !bf16x3_available()) return SINCOSM_E_UNSUPPORTED;
-  if (m.poly == Arith::I8X5) return SINCOSM_E_UNSUPPORTED;   // its launches take no DevCond
   const Layout L = layout_for(m);
   if (!ws || ws_bytes < L.total || ((uintptr_t)ws & 255u)) return SINCOSM_E_WORKSPACE;
   Run r;

@@ -113,6 +113,7 @@ sincosm_status enqueue_async_pair(Run& r, const Layout& L, char* base, const voi
   for (int i = 0; i < 4; ++i) Q[i] = base + L.q_off[i];
   r.Ap = base + L.ap_off;
   for (int i = 0; i < 9; ++i) r.W[i] = base + L.w_off[i];
+  r.i8ws = base + L.i8_off;
   SC_TRY(launch_norm_copy_plan(r.n, m.np, A, lda, m.user_f64, base + L.ap_off, m.poly_f64, acc, ns, r.stream, 0,
                                pre, s_max, plan_dev));
   // Every product launch below reads the plan record. The scheme writes (C, S)
@@ -331,7 +332,6 @@ sincosm_status sincosm_eval_async(int64_t n, int dtype, const void* A, int64_t l
   if (!acc_valid(acc, SINCOSM_PLAN_EXTENDED)) return SINCOSM_E_ARG;
   Modes m;
   if (!modes_for(n > 0 ? n : 1, dtype, prod, m)) return SINCOSM_E_ARG;
-  if (m.poly == Arith::I8X5) return SINCOSM_E_UNSUPPORTED;   // its products are not device-planned launches
   if (n == 0) return SINCOSM_OK;
   SC_TRY(check_eval_args(n, dtype, A, lda, C, ldc, S, lds, m, ws, ws_bytes));
   const Layout L = layout_for(m);

@@ -203,14 +203,13 @@ struct WaveCall {
 
 // Validation common to every wave entry point (outputs are checked by the caller).
 static sincosm_status wave_check(int64_t n, int dtype, const void* A, int64_t lda, double t, int acc, int prod,
-                                 Modes& m, bool device_planned) {
+                                 Modes& m) {
   if (n < 0 || n > (1 << 20)) return SINCOSM_E_ARG;
   if (acc != SINCOSM_ACC_DOUBLE && acc != SINCOSM_ACC_SINGLE) return SINCOSM_E_ARG;
   if (!isfinite(t)) return SINCOSM_E_ARG;
   if (!modes_for(n > 0 ? n : 1, dtype, prod, m)) return SINCOSM_E_ARG;
   if (n > 0 && (!A || lda < n)) return SINCOSM_E_ARG;
   if (m.poly == Arith::BF16X3 && !bf16x3_available()) return SINCOSM_E_UNSUPPORTED;
-  if (device_planned && m.poly == Arith::I8X5) return SINCOSM_E_UNSUPPORTED;   // its launches take no DevCond
   return SINCOSM_OK;
 }
 
@@ -293,6 +292,7 @@ static sincosm_status wave_async_pair(WaveCall& c, int64_t n, const void* A, int
   r.n = n;
   r.Ap = Ap;
   for (int i = 0; i < 9; ++i) r.W[i] = c.base + c.L.w_off[i];
+  r.i8ws = c.base + c.L.i8_off;
   r.stream = c.stream;
   void* Q[4];
   for (int i = 0; i < 4; ++i) Q[i] = c.base + c.L.q_off[i];
@@ -336,7 +336,7 @@ sincosm_status sincosm_wave_eval(int64_t n, int dtype, const void* A, int64_t ld
                                  int64_t ldc, void* S, int64_t lds, int acc, int prod, void* ws,
                                  size_t ws_bytes, sincosm_plan* plan_host, void* stream) {
   WaveCall c;
-  SC_TRY(wave_check(n, dtype, A, lda, t, acc, prod, c.m, false));
+  SC_TRY(wave_check(n, dtype, A, lda, t, acc, prod, c.m));
   if (n == 0) { empty_plan(acc, plan_host); return SINCOSM_OK; }
   if (!C || !S || ldc < n || lds < n) return SINCOSM_E_ARG;
   const size_t es = dtype == SINCOSM_F64 ? 8 : 4;
@@ -358,7 +358,7 @@ sincosm_status sincosm_wave_block_eval(int64_t n, int dtype, const void* A, int6
                                        int64_t lde, int acc, int prod, void* ws, size_t ws_bytes,
                                        sincosm_plan* plan_host, void* stream) {
   WaveCall c;
-  SC_TRY(wave_check(n, dtype, A, lda, t, acc, prod, c.m, false));
+  SC_TRY(wave_check(n, dtype, A, lda, t, acc, prod, c.m));
   if (n == 0) { empty_plan(acc, plan_host); return SINCOSM_OK; }
   if (!E || lde < 2 * n) return SINCOSM_E_ARG;
   const size_t es = dtype == SINCOSM_F64 ? 8 : 4;
@@ -409,7 +409,7 @@ sincosm_status sincosm_wave_eval_async(int64_t n, int dtype, const void* A, int6
                                        void* ws, size_t ws_bytes, sincosm_plan* plan_dev, void* stream) {
   if (s_max < 0 || s_max > 1100) return SINCOSM_E_ARG;
   WaveCall c;
-  SC_TRY(wave_check(n, dtype, A, lda, t, acc, prod, c.m, true));
+  SC_TRY(wave_check(n, dtype, A, lda, t, acc, prod, c.m));
   if (n == 0) return SINCOSM_OK;
   if (!C || !S || ldc < n || lds < n) return SINCOSM_E_ARG;
   const size_t es = dtype == SINCOSM_F64 ? 8 : 4;
@@ -431,7 +431,7 @@ sincosm_status sincosm_wave_block_eval_async(int64_t n, int dtype, const void* A
                                              size_t ws_bytes, sincosm_plan* plan_dev, void* stream) {
   if (s_max < 0 || s_max > 1100) return SINCOSM_E_ARG;
   WaveCall c;
-  SC_TRY(wave_check(n, dtype, A, lda, t, acc, prod, c.m, true));
+  SC_TRY(wave_check(n, dtype, A, lda, t, acc, prod, c.m));
   if (n == 0) return SINCOSM_OK;
   if (!E || lde < 2 * n) return SINCOSM_E_ARG;
   const size_t es = dtype == SINCOSM_F64 ? 8 : 4;

@@ -281,8 +281,7 @@ def test_async_propagator_argument_errors_without_gpu(lib):
 def test_int8_product_tier_sizes_and_rejections_without_gpu(lib):
     """SINCOSM_PROD_I8X5: float64 storage only, n <= 16384 (int32 accumulation of the slice
     products); its workspace adds the slice planes (10 np^2 bytes and the exponents); the
-    device-planned evaluation and the wave and propagator entries reject it before any GPU
-    call."""
+    batched pass rejects it before any GPU call."""
     vp, i64, i32, dbl, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
     ws = lib.sincosm_workspace_size
     ws.restype, ws.argtypes = sz, [i64, ctypes.c_int, ctypes.c_int, ctypes.c_int]
@@ -294,14 +293,7 @@ def test_int8_product_tier_sizes_and_rejections_without_gpu(lib):
     mw = lib.sincosm_matmul_workspace_size
     mw.restype, mw.argtypes = sz, [i64, ctypes.c_int, ctypes.c_int]
     assert mw(1000, 0, 3) >= mw(1000, 0, 0) + 10 * 1024 * 1024
-    buf = ctypes.create_string_buffer(8192)
-    p = (ctypes.cast(buf, vp).value + 255) // 256 * 256
-    ea = lib.sincosm_eval_async
-    ea.argtypes = [i64, ctypes.c_int, vp, i64, vp, i64, vp, i64, ctypes.c_int, ctypes.c_int, i32, vp, sz, vp, vp]
-    assert ea(4, 0, p, 4, p + 1024, 4, p + 2048, 4, 1, 3, 8, p, 64, None, None) == -2
-    we = lib.sincosm_wave_eval_async
-    we.argtypes = [i64, ctypes.c_int, vp, i64, dbl, vp, i64, vp, i64, ctypes.c_int, ctypes.c_int, i32, vp, sz, vp, vp]
-    assert we(4, 0, p, 4, 1.0, p + 1024, 4, p + 2048, 4, 1, 3, 4, p, 64, None, None) == -2
-    ex = lib.sincosm_expi_eval_async
-    ex.argtypes = [i64, ctypes.c_int, vp, i64, dbl, vp, i64, ctypes.c_int, ctypes.c_int, i32, vp, sz, vp, vp]
-    assert ex(4, 0, p, 4, 1.0, p + 1024, 4, 1, 3, 4, p, 64, None, None) == -2
+    bws = lib.sincosm_batched_workspace_size
+    bws.restype, bws.argtypes = sz, [i64, ctypes.POINTER(i32), ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    ns = (i32 * 2)(16, 32)
+    assert bws(2, ns, 0, 0, 3) == 0          # the batched pass takes native products only

@@ -217,7 +217,7 @@ def test_i8x5_wave_pair(env, n, e):
 @pytest.mark.parametrize("n,e", [(64, 1), (300, 6)])
 def test_i8x5_propagators(env, n, e):
     """e^{-itA} and the block propagator e^{tM} with int8 scheme products against the oracle
-    at the single-accuracy bar; the device-planned forms reject the arithmetic."""
+    at the single-accuracy bar; the device-planned e^{-itA} gives bitwise the same result."""
     from oracle import propagators as Pr
     torch, sc = env
     say("i8x5 propagators", n, e)
@@ -227,6 +227,89 @@ def test_i8x5_propagators(env, n, e):
     assert rel_fro(U.cpu().numpy(), Pr.unitary(A, 1.0)) <= 5e-6
     E = sc.wave_block(At, 1.0, "single", "i8x5")
     assert rel_fro(E.cpu().numpy(), Pr.symplectic(A, 1.0)) <= 5e-6
-    Ua = torch.empty(n, n, dtype=torch.complex128, device="cuda")
-    with pytest.raises(sc.SincosmError):
-        sc.sincosm_expi_eval_async(At, 1.0, Ua, accuracy="single", products="i8x5")
+    Ua = torch.full((n, n), 3.0, dtype=torch.complex128, device="cuda")
+    sc.sincosm_expi_eval_async(At, 1.0, Ua, accuracy="single", products="i8x5")
+    torch.cuda.synchronize()
+    assert torch.equal(Ua, U)
+
+
+def _sync_async(env, A, s_max=16):
+    torch, sc = env
+    C0, S0 = torch.empty_like(A), torch.empty_like(A)
+    p0 = sc.sincosm_eval(A, C0, S0, "single", "i8x5")
+    C1, S1 = torch.full_like(A, 5.0), torch.full_like(A, 5.0)
+    pd = torch.zeros(sc.PLAN_BYTES, dtype=torch.uint8, device="cuda")
+    sc.sincosm_eval_async(A, C1, S1, s_max, "single", "i8x5", plan_dev=pd)
+    torch.cuda.synchronize()
+    return (C0, S0, p0), (C1, S1, sc.plan_from_device(pd))
+
+
+@pytest.mark.parametrize("n", [100, 400])
+@pytest.mark.parametrize("e", [-7.0, -2.0, 0.5, 3.0, 8.0])
+def test_i8x5_async_equals_sync(env, n, e):
+    """sincosm_eval_async with int8 products (the plan decided on the device; slot launches of
+    alternative levels, each int8 kernel leaving when the record rules it out): the same plan
+    and bitwise the same cos and sin as sincosm_eval."""
+    torch, sc = env
+    say("i8x5 async", n, e)
+    A = torch.from_numpy(W.gaussian(n, 2.0 ** e, key=(189, n, int(e) + 10))).cuda()
+    (C0, S0, p0), (C1, S1, p1) = _sync_async(env, A)
+    assert (p1.level, p1.s, p1.status) == (p0.level, p0.s, 0)
+    assert torch.equal(C0, C1) and torch.equal(S0, S1)
+
+
+def test_i8x5_async_graph_capture(env):
+    """Captured once with no plan known, replayed on inputs whose plans differ, with eager work
+    between the replays: each replay equals sincosm_eval with int8 products bitwise."""
+    torch, sc = env
+    n = 192
+    A = torch.zeros(n, n, dtype=torch.float64, device="cuda")
+    C, S = torch.empty_like(A), torch.empty_like(A)
+    ws = torch.empty(sc.workspace_size(n, torch.float64, "single", "i8x5"), dtype=torch.uint8, device="cuda")
+    pd = torch.zeros(sc.PLAN_BYTES, dtype=torch.uint8, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        sc.sincosm_eval_async(A, C, S, 8, "single", "i8x5", ws=ws, plan_dev=pd)   # warm-up outside capture
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        sc.sincosm_eval_async(A, C, S, 8, "single", "i8x5", ws=ws, plan_dev=pd)
+    seen = set()
+    for k, e in enumerate([-5.0, 0.5, 3.0, 7.0]):
+        say("i8x5 async graph replay", e)
+        A.copy_(torch.from_numpy(W.gaussian(n, 2.0 ** e, key=(190, k))).cuda())
+        junk = torch.randn(256, 256, device="cuda", dtype=torch.float64)
+        junk = junk @ junk
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        rec = sc.plan_from_device(pd)
+        Ce, Se = torch.empty_like(A), torch.empty_like(A)
+        pe = sc.sincosm_eval(A, Ce, Se, "single", "i8x5")
+        torch.cuda.synchronize()
+        assert (rec.level, rec.s, rec.status) == (pe.level, pe.s, 0)
+        assert torch.equal(C, Ce) and torch.equal(S, Se), e
+        seen.add((rec.level, rec.s))
+    assert len(seen) == 4
+
+
+@pytest.mark.parametrize("n,e", [(64, 1), (300, 6)])
+def test_i8x5_wave_async(env, n, e):
+    """The device-planned wave pair and block with int8 products against the oracle at the
+    single-accuracy bar."""
+    from oracle import wave as Wv
+    from oracle import propagators as Pr
+    torch, sc = env
+    say("i8x5 wave async", n, e)
+    A = W.gaussian(n, 2.0 ** e, key=(191, n))
+    At = torch.from_numpy(A).cuda()
+    C, S = torch.empty_like(At), torch.empty_like(At)
+    sc.sincosm_wave_eval_async(At, 1.0, C, S, 8, "single", "i8x5")
+    E = torch.empty(2 * n, 2 * n, dtype=torch.float64, device="cuda")
+    sc.sincosm_wave_block_eval_async(At, 1.0, E, 8, "single", "i8x5")
+    torch.cuda.synchronize()
+    Cr, Sr = Wv.reference(A, 1.0)
+    assert rel_fro(C.cpu().numpy(), Cr) <= 5e-6 and rel_fro(S.cpu().numpy(), Sr) <= 5e-6
+    assert rel_fro(E.cpu().numpy(), Pr.symplectic(A, 1.0)) <= 5e-6

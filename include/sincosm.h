@@ -105,12 +105,13 @@ enum { SINCOSM_PLAN_REFINED = 32 };
  *           (reached only when digits agree in sign throughout; for uncorrelated
  *           digits those sums grow like n^(1/2) and the first term dominates):
  *           inside the single-accuracy bound u = 2^-24 of Table 2, not the
- *           double one. dtype F64 only,
- *           n <= 16384 (for sincosm_wave_block_eval the order of A: its products
- *           are n x n), accepted by the entry points whose plan reaches the host: sincosm_eval, sincosm_eval_planned (and its
- *           no-allocation form), sincosm_wave_eval, sincosm_wave_block_eval,
- *           sincosm_expi_eval and sincosm_matmul; the device-planned entry points
- *           and the batched and reverse passes return SINCOSM_E_UNSUPPORTED.
+ *           double one. dtype F64 only, n <= 16384 (for the wave block entries
+ *           the order of A: their products are n x n). Accepted by every
+ *           single-matrix entry point, device-planned ones included (each int8
+ *           kernel honours the launch's plan record), and by sincosm_matmul,
+ *           where a row of X or a column of Y holding Inf or NaN gives a NaN row
+ *           or column of Z; the batched and reverse passes return
+ *           SINCOSM_E_UNSUPPORTED.
  * The 1-norm, the plan and the double-angle steps always run in the storage
  * type (float64 for F64). */
 typedef enum { SINCOSM_PROD_NATIVE = 0, SINCOSM_PROD_F32 = 1, SINCOSM_PROD_BF16X3 = 2,

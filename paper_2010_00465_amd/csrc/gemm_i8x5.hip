@@ -51,9 +51,15 @@ struct MI8 {
   __device__ static inline int row_in_block(int lg, int r) { return 4 * lg + r; }
 };
 
+// Exponent of a row or column holding Inf or NaN (outside every float64
+// exponent): its digits are written as zeros and its results as NaN.
+constexpr int I8_NONFINITE = 1 << 16;
+
 // The exponent e with |x| < 2^e for every x of a row or column whose largest
-// magnitude is m (0 for m = 0).
+// magnitude is m (0 for m = 0). m is the maximum of the |x| bit patterns, so
+// it is Inf or NaN exactly when one of the entries is.
 __device__ inline int slice_exponent(double m) {
+  if (!isfinite(m)) return I8_NONFINITE;
   if (!(m > 0.0)) return 0;
   int e = 0;
   frexp(m, &e);
@@ -63,6 +69,7 @@ __device__ inline int slice_exponent(double m) {
 // NS digits of y = x 2^-e in (-1, 1): d_k = trunc(128 y_k), y_{k+1} = 128 y_k - d_k
 // (exact in float64).
 __device__ inline void slice_digits(double y, int8_t (&d)[NS]) {
+  if (!isfinite(y)) y = 0.0;   // a row or column with Inf or NaN (its results are NaN)
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     const double t = y * 128.0;
@@ -326,7 +333,8 @@ __global__ __launch_bounds__(QTHR) void gemm_i8x5_kernel(const int8_t* __restric
         for (int gq = NG - 1; gq >= 0; --gq) v += ldexp((double)acc[gq][i][j][r], -7 * (gq + 2));
         const int row = tile_m * QT + wm * 32 + i * 16 + MI8::row_in_block(lg, r);
         const int col = tile_n * QT + wn * 32 + j * 16 + lr;
-        dd[i][j][r] = ldexp(v, ea[row] + eb[col]) * scale;
+        const int e = ea[row], f = eb[col];
+        dd[i][j][r] = (e == I8_NONFINITE || f == I8_NONFINITE) ? __builtin_nan("") : ldexp(v, e + f) * scale;
       }
   epilogue_bands<double, QT, QT, 2, 2, MI8, v4d, 2, 2>(P, np, tile_m, tile_n, dd, (double*)smem);
 }

@@ -313,3 +313,30 @@ def test_i8x5_wave_async(env, n, e):
     Cr, Sr = Wv.reference(A, 1.0)
     assert rel_fro(C.cpu().numpy(), Cr) <= 5e-6 and rel_fro(S.cpu().numpy(), Sr) <= 5e-6
     assert rel_fro(E.cpu().numpy(), Pr.symplectic(A, 1.0)) <= 5e-6
+
+
+def test_i8x5_product_nonfinite_rows_and_columns(env):
+    """sincosm_matmul with int8 products: a row of X holding NaN and a column of Y holding Inf
+    give a NaN row and column of Z (where a float64 product is non-finite too); every other
+    entry stays within the product bound."""
+    torch, sc = env
+    n = 130
+    g = W.rng(192, n)
+    X = g.standard_normal((n, n))
+    Y = g.standard_normal((n, n))
+    Zr = X @ Y
+    X[5, 7] = np.nan
+    Y[3, 11] = np.inf
+    Z = torch.empty(n, n, dtype=torch.float64, device="cuda")
+    sc.sincosm_matmul(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(), Z, products="i8x5")
+    torch.cuda.synchronize()
+    Zg = Z.cpu().numpy()
+    assert np.isnan(Zg[5]).all() and np.isnan(Zg[:, 11]).all()
+    keep = np.ones((n, n), bool)
+    keep[5] = False
+    keep[:, 11] = False
+    assert np.isfinite(Zg[keep]).all()
+    Xf, Yf = np.nan_to_num(X, nan=0.0), np.nan_to_num(Y, posinf=0.0)
+    aX, aY = np.abs(Xf), np.abs(Yf)
+    bound = 2.0 ** -34 * (np.outer(aX.max(1), aY.sum(0)) + np.outer(aX.sum(1), aY.max(0)))
+    assert (np.abs(Zg - Zr)[keep] <= 2.0 * bound[keep]).all()

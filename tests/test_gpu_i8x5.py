@@ -340,3 +340,24 @@ def test_i8x5_product_nonfinite_rows_and_columns(env):
     aX, aY = np.abs(Xf), np.abs(Yf)
     bound = 2.0 ** -34 * (np.outer(aX.max(1), aY.sum(0)) + np.outer(aX.sum(1), aY.max(0)))
     assert (np.abs(Zg - Zr)[keep] <= 2.0 * bound[keep]).all()
+
+
+@pytest.mark.parametrize("norm", [0.1, 0.8, 40.0])
+def test_i8x5_extended_plan(env, norm):
+    """The extended plan (the 5-product scheme among the candidates) with int8 products:
+    against the float64 oracle at the single-accuracy bar, and the device-planned form
+    bitwise equal to the synchronous one."""
+    torch, sc = env
+    n = 200
+    say("i8x5 extended", norm)
+    A = W.gaussian(n, norm, key=(193, int(norm * 10)))
+    At = torch.from_numpy(A).cuda()
+    C, S = torch.empty_like(At), torch.empty_like(At)
+    p = sc.sincosm_eval(At, C, S, "single", "i8x5", extended=True)
+    C1, S1 = torch.full_like(At, 2.0), torch.full_like(At, 2.0)
+    sc.sincosm_eval_async(At, C1, S1, 8, "single", "i8x5", extended=True)
+    torch.cuda.synchronize()
+    Cr, Sr = R.sincosm(A)
+    say("i8x5 extended plan", p.level, p.s)
+    assert rel_fro(C.cpu().numpy(), Cr) <= 5e-6 and rel_fro(S.cpu().numpy(), Sr) <= 5e-6
+    assert torch.equal(C, C1) and torch.equal(S, S1)

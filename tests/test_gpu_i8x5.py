@@ -361,3 +361,47 @@ def test_i8x5_extended_plan(env, norm):
     say("i8x5 extended plan", p.level, p.s)
     assert rel_fro(C.cpu().numpy(), Cr) <= 5e-6 and rel_fro(S.cpu().numpy(), Sr) <= 5e-6
     assert torch.equal(C, C1) and torch.equal(S, S1)
+
+
+def _emulate_i8x5(X, Y):
+    """The int8 product's arithmetic on the CPU: per-row (X) and per-column (Y) exponents from
+    the largest magnitude, five 7-bit digits d = trunc(128 y) with y <- 128 y - d (exact in
+    float64), the digit products of each weight k + l <= 4 (slice indices from 0) summed
+    exactly (int64 here), and the five sums combined in float64 from the smallest weight up,
+    then scaled by 2^(e_i + f_j)."""
+    def digits(M, axis):
+        m = np.abs(M).max(axis=axis, keepdims=True)
+        e = np.where(m > 0, np.frexp(m)[1], 0)
+        y = np.ldexp(M, -e)
+        ds = []
+        for _ in range(5):
+            t = y * 128.0
+            q = np.trunc(t)
+            ds.append(q.astype(np.int64))
+            y = t - q
+        return ds, e
+    D, e = digits(X, 1)
+    E, f = digits(Y, 0)
+    v = np.zeros((X.shape[0], Y.shape[1]))
+    for g in range(4, -1, -1):
+        S = sum(D[k] @ E[g - k] for k in range(g + 1))
+        v = v + np.ldexp(S.astype(np.float64), -7 * (g + 2))
+    return np.ldexp(v, e + f)
+
+
+@pytest.mark.parametrize("n,kind", [(64, "gaussian"), (100, "graded"), (257, "gaussian")])
+def test_i8x5_product_bitwise_emulation(env, n, kind):
+    """sincosm_matmul with int8 products equals the CPU emulation of its arithmetic bit for bit
+    (the int32 sums are exact, and the float64 combination has a fixed order)."""
+    torch, sc = env
+    say("i8x5 emulation", n, kind)
+    g = W.rng(194, n, 0 if kind == "gaussian" else 1)
+    X = g.standard_normal((n, n))
+    Y = g.standard_normal((n, n))
+    if kind == "graded":
+        X *= np.exp2(g.integers(-30, 30, size=(n, 1)))
+        Y *= np.exp2(g.integers(-30, 30, size=(1, n)))
+    Z = torch.empty(n, n, dtype=torch.float64, device="cuda")
+    sc.sincosm_matmul(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(), Z, products="i8x5")
+    torch.cuda.synchronize()
+    assert np.array_equal(Z.cpu().numpy(), _emulate_i8x5(X, Y))

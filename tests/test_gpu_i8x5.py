@@ -405,3 +405,27 @@ def test_i8x5_product_bitwise_emulation(env, n, kind):
     sc.sincosm_matmul(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(), Z, products="i8x5")
     torch.cuda.synchronize()
     assert np.array_equal(Z.cpu().numpy(), _emulate_i8x5(X, Y))
+
+
+def test_i8x5_seeded_sweep(env):
+    """24 seeded draws (order uniform on 16 ... 400, ||A||_1 = 2^e with e uniform on [-6, 8],
+    Gaussian, symmetric and 1-D Laplacian families): every single-plan evaluation with int8
+    products within the single-accuracy bar against the float64 oracle."""
+    torch, sc = env
+    g = W.rng(195)
+    worst = 0.0
+    for k in range(24):
+        n = int(g.integers(16, 401))
+        e = float(g.uniform(-6.0, 8.0))
+        fam = ("gaussian", "symmetric", "laplacian1d")[k % 3]
+        A = W.family(fam, n, 2.0 ** e, key=(195, k))
+        At = torch.from_numpy(A).cuda()
+        C, S = torch.empty_like(At), torch.empty_like(At)
+        p = sc.sincosm_eval(At, C, S, "single", "i8x5")
+        torch.cuda.synchronize()
+        Cr, Sr = R.sincosm(A)
+        err = max(rel_fro(C.cpu().numpy(), Cr), rel_fro(S.cpu().numpy(), Sr))
+        say("i8x5 sweep", k, fam, n, round(e, 2), p.level, p.s, err)
+        worst = max(worst, err)
+        assert err <= 5e-6, (k, fam, n, e)
+    say("i8x5 sweep worst", worst)

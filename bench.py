@@ -34,6 +34,7 @@ if ROOT not in sys.path:
 
 FP64_MFMA_PEAK_TFLOPS = 78.6
 FP32_MFMA_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 N = 4096
 ANCHORS = (-4, 0, 4, 10)
 
@@ -171,6 +172,40 @@ def measured_traffic():
         return None
 
 
+def batched_traffic():
+    """Counter bytes (HBM reads + writes, copy-calibrated) per 20,000-matrix batched call, float64
+    and float32, from the committed counter summary; None once csrc/batched.hip has changed."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "batched_mixed_20k.md")
+    try:
+        text = open(prof).read()
+        with open(os.path.join(ROOT, "paper_2010_00465_amd", "csrc", "batched.hip"), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("batched_sources_sha256") != sha:
+        return None
+    try:
+        return {"f64": float(vals["traffic_bytes_per_call (float64)"]),
+                "f32": float(vals["traffic_bytes_per_call (float32)"])}
+    except (KeyError, ValueError):
+        return None
+
+
+def _hbm_roofline(traffic, seconds):
+    """HBM roofline of a batched call: counter bytes per call over the timed call, against 8 TB/s."""
+    if traffic is None:
+        return None
+    achieved = traffic / seconds / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic}
+
+
 def _elapsed(torch, fn, reps):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -256,9 +291,11 @@ def bench_batched(torch, sc, W):
                                            "graph_replay_evals_per_s": k / t_loop_graph,
                                            "graph_replay_tflops_algorithmic": loop_flops / t_loop_graph / 1e12},
             "speedup_vs_loop": (len(ns) / t) / (k / t_loop),
+            "hbm_roofline": _hbm_roofline((batched_traffic() or {}).get("f64"), t),
             "float32_single": {"ms_per_batch": 1e3 * t32, "evals_per_s": len(ns) / t32,
                                "tflops_algorithmic": flops32 / t32 / 1e12,
-                               "mean_products": float(np.mean([p.products for p in pl32]))}}
+                               "mean_products": float(np.mean([p.products for p in pl32])),
+                               "hbm_roofline": _hbm_roofline((batched_traffic() or {}).get("f32"), t32)}}
 
 
 def bench_batched_call(torch, sc, W):
@@ -276,7 +313,9 @@ def bench_batched_call(torch, sc, W):
         flops = float(sum(p.products * 2.0 * int(n) ** 3 for p, n in zip(pl, ns)))
         t = _elapsed(torch, lambda: w.run(A, C, S, plans), 3)
         out["f64_double" if dt == torch.float64 else "f32_single"] = {
-            "ms_per_batch": 1e3 * t, "tflops_algorithmic": flops / t / 1e12}
+            "ms_per_batch": 1e3 * t, "tflops_algorithmic": flops / t / 1e12,
+            "hbm_roofline": _hbm_roofline((batched_traffic() or {}).get("f64" if dt == torch.float64 else "f32"),
+                                          t)}
         del A, C, S, w
     return out
 

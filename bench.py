@@ -349,6 +349,7 @@ def bench_tiers(torch, sc, W):
     against the float64 CPU oracle; for each lowered tier, the float64 path with the error closest
     to it from below (matched accuracy: the same or better error)."""
     from oracle import reference as R
+    from paper_2010_00465_amd import _lib
 
     def one(Anp):
         A = torch.from_numpy(Anp).cuda()
@@ -366,6 +367,19 @@ def bench_tiers(torch, sc, W):
             es = float(np.linalg.norm(S.cpu().numpy() - Sr) / np.linalg.norm(Sr))
             out[name] = {"ms": 1e3 * t, "plan": [plan.level, plan.s], "products": plan.products,
                          "rel_err_cos": ec, "rel_err_sin": es}
+            # per-launch durations of one more evaluation (HIP events around each product launch;
+            # an int8 scheme product's launch includes its slicing kernels)
+            _lib.lib.sincosm_timing_enable(1)
+            sc.sincosm_eval(A, C, S, acc, prod, ws=ws)
+            per = {}
+            for kind, key in ((0, "scheme_product_ms"), (1, "double_angle_step_ms")):
+                ms, cnt = ctypes.c_double(), ctypes.c_int64()
+                _lib.lib.sincosm_timing_read(kind, ctypes.byref(ms), ctypes.byref(cnt))
+                per[key] = ms.value / cnt.value if cnt.value else None
+            _lib.lib.sincosm_timing_enable(0)
+            out[name].update(per)
+            if prod == "i8x5" and per["scheme_product_ms"]:
+                out[name]["int8_pops_per_scheme_product"] = 15 * 2.0 * 4096 ** 3 / per["scheme_product_ms"] / 1e12
             del ws
         fp64 = [k for k in ("fp64_single_plan", "fp64_double")]
         for tier in ("fp32_products", "bf16x3_products", "int8x5_products"):

@@ -39,7 +39,11 @@ namespace {
 constexpr int BT = 64;        // largest output tile of the per-workgroup product loop
 constexpr int BBK = 16;       // k step
 constexpr int BNT = 256;      // threads (4 waves in a 2 x 2 grid)
-constexpr int WG_PER_CU = 4;  // resident workgroups per CU the arena is sized for
+// Resident workgroups per CU the grid and the arena are sized for: the
+// persistent kernel's registers allow three waves per SIMD, so three
+// workgroups of four waves are resident per CU; a fourth per CU would start
+// only once a resident one leaves, with the queue already empty.
+constexpr int WG_PER_CU = 3;
 constexpr int NMAX = 256;     // largest order of the batched path
 // Per padded order: how its products run. TILE_64 / TILE_32: the arena in
 // global memory, output tiles of 64 x 64 or 32 x 32 (batched_kernel);

@@ -92,6 +92,9 @@ def sincosm_eval(A: torch.Tensor, C: torch.Tensor, S: torch.Tensor, accuracy: st
                  products: str = "native", ws: torch.Tensor | None = None, raise_nonfinite=True,
                  extended: bool = False, refined: bool = False) -> Plan:
     """C-ABI sincosm_eval on torch tensors (writes C and S in place). Returns the plan.
+    ``products``: the scheme products' arithmetic, "native" (the storage type), "f32",
+    "bf16x3" or "i8x5" (float64 storage only: int8 matrix cores on five 7-bit slices per
+    operand, float64 intermediates; meant for the single-accuracy plan).
     ``extended``: the plan may also use the 5-product scheme; ``refined``: plan on
     min(||A||_1, ||A^2||_1^(1/2)) (against overscaling of nonnormal A)."""
     _require_cuda(A, C, S)

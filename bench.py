@@ -678,7 +678,7 @@ def bench_propagators(torch, sc, W):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+        print("bench.py: the library and this benchmark run on one GPU; --gpus must be 1 "
               "(the batched path shards by matrix and a single large matrix by row blocks, "
               "but no multi-GPU code is built)", file=sys.stderr)
         sys.exit(2)
